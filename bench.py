@@ -1,0 +1,244 @@
+#!/usr/bin/env python3
+"""Benchmark of the fused D3Q19 Shan-Chen lattice Boltzmann step on one MI355X.
+
+Workload (default): one droplet in a 256^3 periodic box, FP32-shifted populations, psi =
+exp(-1/n), G = 1.3 G_c, radius 60, tanh width 2, seeded uniform noise 1e-6 (seed 3), tau = 1.
+A step is one fused time step of the whole box; every 2048 steps (the paper's convergence
+interval 2^11) the run-control loop takes the FP64 observables, as it would to test convergence.
+The state is created on the device before timing and stays resident in HBM.
+
+Prints ONE JSON line with MLUPS (million lattice-node updates per second), the roofline of the
+step kernel (algorithmic bytes 2 * 19 * 4 B per node update against 8 TB/s), and the oracle
+timed on the host cores on a bounded sample of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = ("MLUPS + % of HBM roofline (1 GPU); batched droplets/hour and p50/p99 "
+          "time-to-equilibrium")
+HBM_PEAK_GBPS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step_droplet256_fp32.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2105_08772_amd", "csrc", "kernels.hip")
+
+
+def kernel_hash():
+    with open(KERNEL_SRC, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def measured_traffic(nodes):
+    """HBM bytes per step launch from committed rocprofv3 counter summaries, if they were taken
+    on the current kernel source (else None)."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_sha256_16") != kernel_hash() or t.get("nodes") != nodes:
+        return None
+    return t.get("bytes_per_launch")
+
+
+def stream_copy_gbps(torch, nbytes=2 << 30, reps=20):
+    """Achievable HBM bandwidth: device-to-device copy of a 2 GiB buffer (read + write)."""
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    s = e0.elapsed_time(e1) / 1e3 / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * nbytes / s / 1e9
+
+
+def cpu_baseline(args, nodes_gpu):
+    """The FP64 oracle on the host cores: its own initial state of the same droplet, then
+    `cpu_steps` plain steps of the whole box."""
+    import numpy as np  # noqa: F401
+    import oracle
+    from oracle import core, eos
+    oracle.build(force=False)
+    kind = 0 if args.psi == "exp" else 1
+    G = eos.G_of(1.3, kind)
+    ng, nl, _ = eos.coexistence_rule(G, kind)
+    L = args.size
+    n0 = core.init_density(L, L, L, core.DROPLET, args.radius, 2.0, nl, ng, 1e-6, 3)
+    f = core.init_populations(n0, G, kind)
+    del n0
+    t0 = time.perf_counter()
+    f = core.run(f, G, 1.0, kind, args.cpu_steps)
+    dt = time.perf_counter() - t0
+    nodes = L ** 3
+    return {"value": round(nodes * args.cpu_steps / dt / 1e6, 3), "unit": "MLUPS",
+            "cores": core.threads(), "kind": "oracle",
+            "sample": f"{args.cpu_steps} steps of the whole {L}^3 droplet (FP64 oracle, "
+                      f"{dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=4096)
+    ap.add_argument("--warmup", type=int, default=128)
+    ap.add_argument("--size", type=int, default=256)
+    ap.add_argument("--radius", type=float, default=60.0)
+    ap.add_argument("--psi", choices=["exp", "oneminus"], default="exp")
+    ap.add_argument("--prec", choices=["fp32", "fp64"], default="fp32")
+    ap.add_argument("--observe-every", type=int, default=2048)
+    ap.add_argument("--rows", type=int, default=0)
+    ap.add_argument("--zchunk", type=int, default=0)
+    ap.add_argument("--remap", type=int, default=-1)
+    ap.add_argument("--tune", action="store_true", help="sweep launch shapes, keep the fastest")
+    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-copy", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2105_08772_amd as lbm
+
+    torch.cuda.set_device(0)
+    # a dedicated stream (default priority): the library enqueues on it and the timing events
+    # are recorded on it
+    stream = torch.cuda.Stream()
+    L = args.size
+    psi = lbm.LBM_SC_PSI_EXP if args.psi == "exp" else lbm.LBM_SC_PSI_ONEMINUS
+    prec = lbm.LBM_SC_FP32_SHIFTED if args.prec == "fp32" else lbm.LBM_SC_FP64
+    cfg = lbm.config(L, L, L, psi=psi, geom=lbm.LBM_SC_DROPLET, prec=prec, tau=1.0,
+                     g_over_gc=1.3, radius=args.radius, width=2.0, noise_amp=1e-6, seed=3,
+                     stream=stream.cuda_stream)
+    box = lbm.Box(cfg)
+    info = box.info()
+    nodes = info["nodes"]
+    print(f"# created {L}^3 box, {info['device_bytes'] / 2**30:.2f} GiB on the device",
+          file=sys.stderr, flush=True)
+    bytes_per_step = info["bytes_per_step"]
+
+    def time_steps(k):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        box.step(k)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / 1e3 / k
+
+    tuned = None
+    if args.tune:
+        best = None
+        for rows in (1, 2, 4):
+            for zc in (8, 16, 32, 64, 128):
+                for remap in (0, 1):
+                    box.set_launch(rows, zc, remap)
+                    box.step(8)
+                    t = time_steps(64)
+                    print(f"# tune rows={rows} zchunk={zc} remap={remap} "
+                          f"{nodes / t / 1e6:.0f} MLUPS", file=sys.stderr, flush=True)
+                    if best is None or t < best[0]:
+                        best = (t, rows, zc, remap)
+        tuned = dict(rows=best[1], z_chunk=best[2], xcd_remap=best[3])
+        box.set_launch(best[1], best[2], best[3])
+    if args.rows or args.zchunk or args.remap >= 0:
+        i = box.info()
+        box.set_launch(args.rows or i["block_y"] // 4, args.zchunk or i["z_chunk"],
+                       args.remap if args.remap >= 0 else 1)
+    info = box.info()
+
+    # warmup
+    box.step(args.warmup)
+    box.observables(profile=False)
+    torch.cuda.synchronize()
+
+    # timed region: K steps with an FP64 observation every observe_every steps
+    K = args.steps
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = 0
+    last = None
+    while done < K:
+        n = min(args.observe_every - done % args.observe_every, K - done)
+        box.step(n)
+        done += n
+        if done % args.observe_every == 0:
+            last, _ = box.observables(profile=False)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    wall = t1 - t0
+    mlups = nodes * K / wall / 1e6
+    print(f"# timed {K} steps: {mlups:.0f} MLUPS", file=sys.stderr, flush=True)
+
+    # the dominant kernel alone: average launch duration over back-to-back steps
+    k_steps = min(K, 2048)
+    step_s = time_steps(k_steps)
+    achieved = bytes_per_step / step_s / 1e9
+    obs, _ = box.observables(profile=False)
+    box.close()
+
+    copy_bw = None if args.no_copy else stream_copy_gbps(torch)
+    traffic = measured_traffic(nodes)
+
+    out = {
+        "metric": METRIC,
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / K * 1e3, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if prec == lbm.LBM_SC_FP32_SHIFTED else "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"droplet {L}^3 periodic, {'FP32-shifted' if args.prec == 'fp32' else 'FP64'}"
+                        f" populations, psi={args.psi}, G/G_c=1.3, R={args.radius:g}, tanh width 2,"
+                        f" noise 1e-6 seed 3, tau=1, FP64 observables every {args.observe_every}"
+                        f" steps",
+            "nodes": nodes,
+            "launch": {"block": [64, info["block_y"]], "z_chunk": info["z_chunk"],
+                       "tuned": tuned},
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBPS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBPS, 4),
+            "traffic": traffic,
+            "kernel_ms": round(step_s * 1e3, 5),
+            "bytes_per_launch": bytes_per_step,
+            "stream_copy_GBps": None if copy_bw is None else round(copy_bw, 1),
+        },
+        "checks": {"finite": obs["finite"],
+                   "mass_drift_rel": abs(obs["mass"] - obs["mass0"]) / obs["mass0"],
+                   "dP": obs["dP"], "R_s": obs["R_s"]},
+    }
+    if not args.no_cpu:
+        print("# timing the oracle on the host cores", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(args, nodes)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,183 @@
+/*
+ * lbm_sc.h - C ABI of the MI355X (gfx950) Shan-Chen D3Q19 lattice Boltzmann library.
+ *
+ * The library relaxes hydrostatic droplets, bubbles and flat slabs of a Shan-Chen non-ideal fluid
+ * (Lulli, Biferale, Falcucci, Sbragaglia, Shan, "A Mesoscale Perspective on the Tolman Length",
+ * arXiv:2105.08772) on one GPU. One time step is the lattice transport of Sec. 2, Eq. (lbm),
+ * with the BGK collision Eq. (sm:omega_i), the Guo forcing term, the second-order equilibrium and
+ * the Guo equilibrium velocity that follow it, and the Shan-Chen force Eq. (SCForce). The
+ * observables are those of Sec. 3 and Sec. 4: mass, momentum, centre of mass, the lattice
+ * pressure tensor Eq. (sm:pt) along a line or averaged over planes, P_in, P_out, the generalized
+ * surface tension Eq. (gen_sigma) and its minimum R_s, the equimolar radius R_e, the flat-interface
+ * sigma_0 and the velocity-change convergence measure.
+ *
+ * Conventions shared by every entry point:
+ *   - Every function returns an lbm_sc_status (0 on success, a negative code otherwise) unless
+ *     stated otherwise; lbm_sc_last_error() then describes the failure. No C++ exception crosses
+ *     this boundary.
+ *   - The handle owns all device memory it allocates and frees it in lbm_sc_destroy. The caller
+ *     owns every pointer it passes; the library keeps none of them after the call returns, except
+ *     the stream in lbm_sc_config.
+ *   - A handle is used from one host thread at a time.
+ *   - Host arrays of populations use the canonical layout f[i][z][y][x] (x fastest, no padding,
+ *     FP64) and hold the pre-collision populations f_i(x, t) of the current time t. The D3Q19
+ *     order is: i = 0 rest; 1..6 = +x, -x, +y, -y, +z, -z; 7..18 = (1,1,0), (-1,-1,0), (1,-1,0),
+ *     (-1,1,0), (1,0,1), (-1,0,-1), (1,0,-1), (-1,0,1), (0,1,1), (0,-1,-1), (0,1,-1), (0,-1,1).
+ *     Every moving velocity is followed by its opposite.
+ *   - Boxes are periodic along all three axes.
+ */
+#ifndef LBM_SC_H
+#define LBM_SC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_sc lbm_sc; /* opaque handle */
+
+typedef enum {
+    LBM_SC_OK = 0,
+    LBM_SC_EINVAL = -1,    /* invalid argument or configuration */
+    LBM_SC_ENOMEM = -2,    /* device or host allocation failed */
+    LBM_SC_EDEVICE = -3,   /* a HIP runtime call or a kernel launch failed */
+    LBM_SC_EUNSTABLE = -4  /* a non-finite value or n <= 0 was seen by lbm_sc_observables */
+} lbm_sc_status;
+
+/* Pseudopotentials of Sec. 4. */
+enum { LBM_SC_PSI_EXP = 0 /* psi = exp(-1/n) */, LBM_SC_PSI_ONEMINUS = 1 /* psi = 1 - exp(-n) */ };
+
+/* Initial geometry (Sec. 4 tanh profile). FROM_HOST leaves the state undefined until
+ * lbm_sc_set_populations is called. */
+enum { LBM_SC_DROPLET = 0, LBM_SC_BUBBLE = 1, LBM_SC_SLAB = 2, LBM_SC_FROM_HOST = 3 };
+
+/* Population storage. FP64 stores f_i in double precision and computes in double precision.
+ * FP32_SHIFTED stores g_i = f_i - w_i rho_ref in single precision and computes the step in
+ * single precision; its observables are computed in double precision. */
+enum { LBM_SC_FP64 = 0, LBM_SC_FP32_SHIFTED = 1 };
+
+typedef struct {
+    int32_t nx, ny, nz;      /* periodic box, each >= 1; x is the fastest axis */
+    int32_t psi;             /* LBM_SC_PSI_* */
+    int32_t geom;            /* LBM_SC_DROPLET / BUBBLE / SLAB / FROM_HOST */
+    int32_t prec;            /* LBM_SC_FP64 / LBM_SC_FP32_SHIFTED */
+    int32_t slab_axis;       /* slab normal: 0 = x, 1 = y, 2 = z */
+    int32_t reserved0;       /* must be 0 */
+    double tau;              /* BGK relaxation time, > 0.5 */
+    double g_over_gc;        /* coupling G = g_over_gc * G_c(psi); G_c < 0, so > 1 separates phases */
+    double radius;           /* droplet/bubble radius R of the tanh profile (Sec. 4), > 0 */
+    double width;            /* tanh width w: n = (n_in+n_out)/2 - (n_in-n_out)/2 tanh((r-R)/w), > 0 */
+    double slab_thickness;   /* slab: thickness of the liquid layer centred at floor(L/2) */
+    double n_in, n_out;      /* densities inside/outside; both 0 => flat coexistence densities from
+                                lbm_sc_coexistence (liquid inside for DROPLET and SLAB, gas inside for
+                                BUBBLE) */
+    double noise_amp;        /* additive uniform noise in [-noise_amp, noise_amp) on the initial n */
+    uint64_t seed;           /* noise of node k = SplitMix64(seed ^ k), k = (z*ny + y)*nx + x */
+    double rho_ref;          /* FP32_SHIFTED reference density; 0 => (n_in + n_out)/2 */
+    void* stream;            /* hipStream_t to enqueue on, or NULL for a stream the handle owns */
+} lbm_sc_config;
+
+typedef struct {
+    int64_t step;            /* time steps taken since creation or the last set_populations */
+    double mass, mass0;      /* sum_x n now and at creation / last set_populations */
+    double mom[3];           /* sum_x n u, u = (sum_i xi_i f_i + F/2)/n (Sec. 2) */
+    double com[3];           /* centre of mass: c + sum n d / M, d the minimum-image offset from
+                                c = floor(L/2); for even L the node at offset L/2 counts 0 */
+    double n_center, n_far;  /* n at c and at the far probe ((c + floor(L/2)) mod L per axis) */
+    double P_in, P_out, dP;  /* P^xx of Eq. (sm:pt) at the two probes (Sec. 4), dP = P_in - P_out */
+    double C;                /* int_0^{R_out} r^2 (P_out - P^yy(c + r e_x)) dr, trapezoid on nodes */
+    double R_s, sigma_s;     /* minimum of sigma[R] = dP R/3 + C/R^2 (Eq. gen_sigma): (6C/dP)^(1/3),
+                                dP R_s/2; NaN unless dP > 0 and C > 0 (droplet/bubble only) */
+    double R_e;              /* equimolar radius (Sec. 4) from mass, n_center, n_far */
+    double sigma0_flat;      /* slab: sum over the half box [L/2, L) along the normal of P_N - P_T */
+    double pn_spread;        /* slab: max - min over planes of the plane-averaged P_N */
+    double du_l1;            /* L^-3 sum_x sum_a |u_a - u_a(previous observables call)| (Sec. 4) */
+    double du_max;           /* max_x max_a of the same difference */
+    double n_min, n_max;     /* extrema of n over the box */
+    int32_t finite;          /* 1 if every n is finite and > 0 and every u finite, else 0 */
+    int32_t has_du;          /* 1 if du_l1/du_max compare against an earlier call */
+} lbm_sc_obs;
+
+typedef struct {
+    double G;                /* coupling used */
+    double Gc;               /* critical coupling of the pseudopotential */
+    double n_in, n_out;      /* densities used for the initial profile */
+    double rho_ref;          /* FP32_SHIFTED reference density (0 for FP64) */
+    int64_t nodes;           /* nx*ny*nz */
+    int64_t device_bytes;    /* device memory held by the handle */
+    int64_t bytes_per_step;  /* algorithmic HBM bytes of one step: 2 * 19 * sizeof(storage) * nodes */
+    int32_t block_x, block_y, z_chunk; /* launch shape of the fused step kernel */
+    int32_t reserved;
+} lbm_sc_info;
+
+/* Create a box. Validates cfg (LBM_SC_EINVAL on any out-of-range field: sizes < 1, tau <= 0.5,
+ * unknown enums, radius/width <= 0 for DROPLET/BUBBLE/SLAB, g_over_gc <= 1 when the densities must
+ * come from lbm_sc_coexistence), allocates two population buffers and the observation scratch on
+ * the current HIP device (LBM_SC_ENOMEM), and builds the initial state on the device: the tanh
+ * profile plus noise, psi, the force of Eq. (SCForce), and f = f_eq(n, u = -F/(2n)) so that the
+ * physical velocity (sum xi f + F/2)/n is zero. Returns after the work is enqueued and *out set.
+ * On failure *out is NULL and nothing is leaked. */
+int lbm_sc_create(const lbm_sc_config* cfg, lbm_sc** out);
+
+/* Enqueue nsteps (>= 0) time steps of Eq. (lbm) on the handle's stream: fused pull streaming,
+ * density and psi, Shan-Chen force, Guo equilibrium velocity, BGK collision with the Guo term.
+ * Returns after enqueueing (asynchronous); LBM_SC_EDEVICE if a launch fails. */
+int lbm_sc_step(lbm_sc* h, int64_t nsteps);
+
+/* Wait until all work enqueued on the handle's stream has finished. */
+int lbm_sc_sync(lbm_sc* h);
+
+/* Compute the observables of the current state in FP64 (listed in lbm_sc_obs) and synchronise.
+ * prof may be NULL; otherwise prof_len must be 4*L where L is nx (droplet/bubble/from-host: the line
+ * y = floor(ny/2), z = floor(nz/2), x = 0..nx-1) or the box length along slab_axis (slab: averages
+ * over planes normal to the axis); it receives [n, P^xx, P^yy, P^zz] each of length L. The
+ * velocity field of this call becomes the reference of the next call's du_l1/du_max. Returns
+ * LBM_SC_EUNSTABLE (with *out filled) if out->finite is 0. */
+int lbm_sc_observables(lbm_sc* h, lbm_sc_obs* out, double* prof, size_t prof_len);
+
+/* Copy the current pre-collision populations f_i(x, t) to the host array f (canonical layout,
+ * len must be 19*nx*ny*nz). FP32_SHIFTED states are widened to FP64 and the shift w_i rho_ref
+ * added back. Synchronises. */
+int lbm_sc_get_populations(lbm_sc* h, double* f, size_t len);
+
+/* Replace the state by the host array f (canonical layout, pre-collision populations at the
+ * current time, len 19*nx*ny*nz). FP32_SHIFTED stores them rounded after subtracting w_i rho_ref.
+ * Resets the step counter, mass0 and the du reference. Synchronises. */
+int lbm_sc_set_populations(lbm_sc* h, const double* f, size_t len);
+
+/* Set the launch shape of the fused step kernel: rows of the x-y tile per wave (1, 2 or 4; the
+ * tile is 64 x 4*rows nodes), planes per workgroup along z (z_chunk >= 1) and whether workgroups
+ * are remapped so that neighbouring tiles share an XCD (xcd_remap 0 or 1). The shape changes
+ * only the schedule: every node's arithmetic and result are the same for every shape. Used by the
+ * autotuner; LBM_SC_EINVAL for values out of range. */
+int lbm_sc_set_launch(lbm_sc* h, int32_t rows, int32_t z_chunk, int32_t xcd_remap);
+
+/* Describe the handle (coupling, densities, sizes, launch shape). */
+int lbm_sc_get_info(lbm_sc* h, lbm_sc_info* out);
+
+/* Release everything the handle owns (after waiting for its stream). NULL is ignored. */
+void lbm_sc_destroy(lbm_sc* h);
+
+/* Message of the last failure on the calling thread; valid until the next call on that thread.
+ * Never NULL. */
+const char* lbm_sc_last_error(void);
+
+/* Critical coupling G_c of the bulk pressure P(n) = n c_s^2 + (G c_s^2/2) psi(n)^2 (Eq. bulkp):
+ * dP/dn = d^2P/dn^2 = 0, i.e. -e^2 for LBM_SC_PSI_EXP and -4 for LBM_SC_PSI_ONEMINUS. Returns NaN
+ * for an unknown psi. Host only. */
+double lbm_sc_gc(int32_t psi);
+
+/* Flat-interface coexistence densities and pressure for G = g_over_gc * G_c (the "equilibrium
+ * values of n_g, n_l for a flat interface" of Sec. 4), from the leading-order lattice rule
+ * P(n_g) = P(n_l) = p0 and int_{n_g}^{n_l} (p0 - P(n)) psi'(n)/psi(n) dn = 0, which follows from
+ * the flat-interface constancy of P_N stated after Eq. (sm:pt). Host only; any output pointer may
+ * be NULL. LBM_SC_EINVAL if g_over_gc <= 1 or no coexistence exists. */
+int lbm_sc_coexistence(int32_t psi, double g_over_gc, double* n_gas, double* n_liquid, double* p0);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_SC_H */

@@ -60,6 +60,8 @@ def lib():
         L.ora_init_populations.argtypes = [_D, i, i, i, d, i, _D]
         L.ora_velocity.argtypes = [_D, i, i, i, d, i, _D, _D]
         L.ora_run.argtypes = [_D, i, i, i, d, d, i, ll]
+        L.ora_threads.argtypes = []
+        L.ora_threads.restype = i
         _lib = L
     return _lib
 
@@ -83,6 +85,11 @@ def tables():
     W = np.zeros(19)
     lib().ora_tables(xi.ctypes.data_as(_I), _p(w), _p(W))
     return xi.reshape(19, 3), w, W
+
+
+def threads():
+    """OpenMP threads the oracle's loops use."""
+    return lib().ora_threads()
 
 
 def psi(n, kind):

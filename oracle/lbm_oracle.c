@@ -30,6 +30,7 @@
  * P[k][z][y][x] with k = 0..5 for xx, yy, zz, xy, xz, yz.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -80,6 +81,9 @@ double ora_psi(double n, int kind)
 {
     return kind == 0 ? exp(-1.0 / n) : 1.0 - exp(-n);
 }
+
+/* Threads an OpenMP loop of the oracle uses. */
+int ora_threads(void) { return omp_get_max_threads(); }
 
 /* Exposed constants so that tests can check the tables themselves. */
 void ora_tables(int* xi_out, double* w_out, double* W_out)

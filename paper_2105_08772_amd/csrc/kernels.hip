@@ -1,0 +1,884 @@
+// Device kernels of the Shan-Chen D3Q19 lattice Boltzmann library (gfx950).
+//
+// Population storage: SoA, population i of node (x, y, z) at i * stride + (z * ny + y) * nx + x.
+// The stored arrays hold the post-collision populations of the previous step, f*_i(x, t - 1), so
+// the pre-collision state of time t is the pull f_i(x, t) = f*_i(x - xi_i, t - 1) (Eq. lbm of
+// arXiv:2105.08772 read as pull streaming). FP32 storage keeps g_i = f_i - w_i rho_ref.
+//
+// Fused step (one launch per time step, Sec. 2 of the paper):
+//   pull the 19 populations -> density n and momentum j -> psi(n) -> Shan-Chen force F from the
+//   psi of the 18 neighbours (Eq. SCForce) -> u_eq = (j + F/2)/n -> BGK relaxation to the
+//   second-order equilibrium plus the Guo term -> store. psi at the neighbours is needed at the
+//   same time level, so each workgroup owns a 64 x (4 rows) x-y tile, marches up a chunk of
+//   z-planes, pulls the densities of its tile plus a one-node x-y halo into an LDS ring of four
+//   psi planes, and collides plane q once the psi of plane q + 1 is in LDS. Only the xy halo
+//   and the two end planes of each chunk are pulled twice; the repeated reads are meant to hit
+//   L2 because neighbouring tiles run together on the same XCD.
+#include <type_traits>
+
+#include "kernels.hpp"
+#include "d3q19.hpp"
+
+namespace lbm {
+namespace {
+
+constexpr int BX = 64;       // tile width = one wave64 row
+constexpr int NT = 256;      // threads per workgroup
+constexpr int NWAVE = NT / 64;
+
+__device__ __forceinline__ int wrapi(int v, int L)
+{
+    int r = v % L;
+    return r < 0 ? r + L : r;
+}
+
+template <typename T, int PSI>
+__device__ __forceinline__ T psi_of(T n)
+{
+    if constexpr (sizeof(T) == 4) {
+        if constexpr (PSI == 0) return expf(-1.0f / n);
+        else return 1.0f - expf(-n);
+    } else {
+        if constexpr (PSI == 0) return exp(-1.0 / n);
+        else return 1.0 - exp(-n);
+    }
+}
+
+__device__ __forceinline__ double psi_rt(double n, int kind)
+{
+    return kind == 0 ? exp(-1.0 / n) : 1.0 - exp(-n);
+}
+
+// Logical tile for a workgroup id so that each XCD (the hardware deals workgroups round-robin
+// over 8 XCDs) receives one contiguous run of logical tiles: neighbours share its L2.
+__device__ __forceinline__ unsigned xcd_remap(unsigned b, unsigned nb)
+{
+    constexpr unsigned NX = 8;
+    const unsigned xcd = b % NX, k = b / NX, per = nb / NX, rem = nb % NX;
+    return xcd * per + (xcd < rem ? xcd : rem) + k;
+}
+
+// Population arrays are addressed through two buffer resources: populations 0..9 and 10..18, each
+// group under 4 GiB (checked by the host). A load or store of population i is one buffer
+// instruction with the node's byte offset in a vector register and the population's byte offset
+// (a multiple of the array stride) as the scalar offset; out-of-range offsets read 0 and write
+// nothing instead of faulting.
+constexpr int SPLIT = 10;
+constexpr unsigned RSRC_FLAGS = 0x00020000u;  // raw buffer, 32-bit dword format (gfx9 family)
+
+struct PopBuf {
+    __amdgpu_buffer_rsrc_t lo, hi;
+    unsigned pop_bytes;  // stride * sizeof(T)
+};
+
+template <typename T>
+__device__ __forceinline__ PopBuf make_popbuf(const T* p, unsigned long long stride)
+{
+    PopBuf b;
+    const unsigned long long pb = stride * sizeof(T);
+    char* base = reinterpret_cast<char*>(const_cast<T*>(p));
+    const unsigned long long lo_bytes = pb * SPLIT, hi_bytes = pb * (Q - SPLIT);
+    b.lo = __builtin_amdgcn_make_buffer_rsrc(base, (short)0, (int)(unsigned)lo_bytes, (int)RSRC_FLAGS);
+    b.hi = __builtin_amdgcn_make_buffer_rsrc(base + lo_bytes, (short)0, (int)(unsigned)hi_bytes,
+                                             (int)RSRC_FLAGS);
+    b.pop_bytes = (unsigned)pb;
+    return b;
+}
+
+template <typename T, int I>
+__device__ __forceinline__ T bload(const PopBuf& b, unsigned voff)
+{
+    constexpr int J = I < SPLIT ? I : I - SPLIT;
+    const __amdgpu_buffer_rsrc_t r = I < SPLIT ? b.lo : b.hi;
+    if constexpr (sizeof(T) == 4) {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff,
+                                                                              (int)(J * b.pop_bytes), 0));
+    } else {
+        typedef int v2i __attribute__((ext_vector_type(2)));
+        const v2i v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)(J * b.pop_bytes), 0);
+        return __builtin_bit_cast(double, v);
+    }
+}
+
+template <typename T, int I>
+__device__ __forceinline__ void bstore(const PopBuf& b, unsigned voff, T v)
+{
+    constexpr int J = I < SPLIT ? I : I - SPLIT;
+    const __amdgpu_buffer_rsrc_t r = I < SPLIT ? b.lo : b.hi;
+    if constexpr (sizeof(T) == 4) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(int, v), r, (int)voff,
+                                              (int)(J * b.pop_bytes), 0);
+    } else {
+        typedef int v2i __attribute__((ext_vector_type(2)));
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2i, v), r, (int)voff,
+                                              (int)(J * b.pop_bytes), 0);
+    }
+}
+
+// Compile-time loop over population indices.
+template <int I, int N, typename F>
+__device__ __forceinline__ void static_for(F&& f)
+{
+    if constexpr (I < N) {
+        f(std::integral_constant<int, I>{});
+        static_for<I + 1, N>(f);
+    }
+}
+
+struct StepArgs {
+    BoxDesc b;
+    int tiles_x, tiles_y, nchunks, zc, remap;
+    double inv_tau, guo_pref;
+};
+
+// Pull the 19 pre-collision populations of one node and reduce them to (sum g, j). Byte offsets
+// zo/yo/xo[d] address the plane/row/column at coordinate + d - 1; the source of velocity xi is the
+// node - xi.
+// The density deviation is accumulated in double precision: for FP32 storage the sum of the 19
+// stored values is then exact, so the density a node sees is exactly the mass it holds.
+template <typename T>
+__device__ __forceinline__ void pull_moments(const PopBuf& src, const unsigned (&zo)[3],
+                                             const unsigned (&yo)[3], const unsigned (&xo)[3],
+                                             double& dn, T& jx, T& jy, T& jz)
+{
+    T f[Q];
+    static_for<0, Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        f[i] = bload<T, i>(src, zo[1 - CZ[i]] + yo[1 - CY[i]] + xo[1 - CX[i]]);
+    });
+    double s = (double)f[0];
+    T ax = T(0), ay = T(0), az = T(0);
+#pragma unroll
+    for (int i = 1; i < Q; i += 2) {
+        s += (double)f[i] + (double)f[i + 1];
+        const T d = f[i] - f[i + 1];
+        if (CX[i] > 0) ax += d;
+        if (CX[i] < 0) ax -= d;
+        if (CY[i] > 0) ay += d;
+        if (CY[i] < 0) ay -= d;
+        if (CZ[i] > 0) az += d;
+        if (CZ[i] < 0) az -= d;
+    }
+    dn = s;
+    jx = ax;
+    jy = ay;
+    jz = az;
+}
+
+// Collide one node and store its 19 post-collision (shifted) populations at byte offset off.
+// dn64 = sum g (n - rho_ref, exact), j = sum xi g = sum xi f. Rest population: mass-exact
+// closure g*_0 = dn - sum_{i>0} g*_i (the stored values summed in double precision), equal to
+// the BGK value in exact arithmetic; the node's stored mass then changes only by the final
+// rounding of g*_0.
+template <typename T, bool TAU1>
+__device__ __forceinline__ void collide_store(const PopBuf& dst, unsigned off, T rho_ref,
+                                              double dn64, T jx, T jy, T jz, T Fx, T Fy, T Fz,
+                                              T inv_tau, T guo_pref, const T* fin)
+{
+    const T dn = (T)dn64;
+    const T n = rho_ref + dn;
+    const T inv_n = T(1) / n;
+    const T ux = (jx + T(0.5) * Fx) * inv_n;
+    const T uy = (jy + T(0.5) * Fy) * inv_n;
+    const T uz = (jz + T(0.5) * Fz) * inv_n;
+    const T uu = ux * ux + uy * uy + uz * uz;
+    const T uF = ux * Fx + uy * Fy + uz * Fz;
+    double sum = 0.0;
+    static_for<0, (Q - 1) / 2>([&](auto K) {
+        constexpr int i = 1 + 2 * decltype(K)::value;
+        const T w = (T)weight(i);
+        const T c = T(CX[i]) * ux + T(CY[i]) * uy + T(CZ[i]) * uz;
+        const T cf = T(CX[i]) * Fx + T(CY[i]) * Fy + T(CZ[i]) * Fz;
+        T gp, gm;
+        if constexpr (TAU1) {
+            // tau = 1: f* = f_eq + (1/2) Guo bracket
+            const T even = w * (dn + n * (T(4.5) * c * c - T(1.5) * uu) + T(4.5) * c * cf - T(1.5) * uF);
+            const T odd = w * (T(3) * n * c + T(1.5) * cf);
+            gp = even + odd;
+            gm = even - odd;
+        } else {
+            const T eq_e = w * (dn + n * (T(4.5) * c * c - T(1.5) * uu));
+            const T eq_o = w * (T(3) * n * c);
+            const T gu_e = guo_pref * w * (T(9) * c * cf - T(3) * uF);
+            const T gu_o = guo_pref * w * (T(3) * cf);
+            gp = fin[i] + (eq_e + eq_o - fin[i]) * inv_tau + gu_e + gu_o;
+            gm = fin[i + 1] + (eq_e - eq_o - fin[i + 1]) * inv_tau + gu_e - gu_o;
+        }
+        bstore<T, i>(dst, off, gp);
+        bstore<T, i + 1>(dst, off, gm);
+        sum += (double)gp + (double)gm;
+    });
+    bstore<T, 0>(dst, off, (T)(dn64 - sum));
+}
+
+template <typename T, int PSI, bool TAU1, int R>
+__global__ __launch_bounds__(NT) void k_step(StepArgs a, const T* __restrict__ src,
+                                             T* __restrict__ dst)
+{
+    constexpr int BY = NWAVE * R;
+    constexpr int LX = BX + 2, LY = BY + 2;
+    constexpr int NH = 2 * LX + 2 * BY;
+    static_assert(NH <= NT, "halo ring larger than the workgroup");
+    __shared__ T ring[4][LY][LX];
+
+    const int nx = a.b.nx, ny = a.b.ny, nz = a.b.nz;
+    const unsigned nxy = a.b.nxy;
+    const PopBuf sbuf = make_popbuf(src, a.b.stride);
+    const PopBuf dbuf = make_popbuf(dst, a.b.stride);
+    const T rho_ref = (T)a.b.rho_ref;
+    const T G = (T)a.b.G;
+    const T inv_tau = (T)a.inv_tau;
+    const T guo_pref = (T)a.guo_pref;
+
+    const unsigned logical = a.remap ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
+    const int tix = (int)(logical % (unsigned)a.tiles_x);
+    const unsigned t2 = logical / (unsigned)a.tiles_x;
+    const int tiy = (int)(t2 % (unsigned)a.tiles_y);
+    const int ch = (int)(t2 / (unsigned)a.tiles_y);
+    const int x0 = tix * BX, y0 = tiy * BY;
+    const int z0 = ch * a.zc;
+    const int z1 = min(z0 + a.zc, nz);
+
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+
+    // The thread's own column; lanes past the box edge wrap and only feed psi to the LDS ring.
+    constexpr unsigned E = sizeof(T);
+    const bool xin = x0 + lane < nx;
+    const int x = wrapi(x0 + lane, nx);
+    const unsigned xo[3] = {(unsigned)wrapi(x - 1, nx) * E, (unsigned)x * E,
+                            (unsigned)wrapi(x + 1, nx) * E};
+    unsigned yo[R][3];
+    bool yin[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int yg = y0 + wv * R + r;
+        yin[r] = yg < ny;
+        const int y = wrapi(yg, ny);
+        yo[r][0] = (unsigned)wrapi(y - 1, ny) * (unsigned)nx * E;
+        yo[r][1] = (unsigned)y * (unsigned)nx * E;
+        yo[r][2] = (unsigned)wrapi(y + 1, ny) * (unsigned)nx * E;
+    }
+
+    // Halo node of this thread (ring position hx, hy in LDS coordinates), if any.
+    const int t = threadIdx.x;
+    const bool has_halo = t < NH;
+    int hx = 0, hy = 0;
+    if (t < LX) {
+        hx = t;
+        hy = 0;
+    } else if (t < 2 * LX) {
+        hx = t - LX;
+        hy = BY + 1;
+    } else if (t < 2 * LX + BY) {
+        hx = 0;
+        hy = 1 + (t - 2 * LX);
+    } else {
+        hx = BX + 1;
+        hy = 1 + (t - 2 * LX - BY);
+    }
+    const int hxg = wrapi(x0 - 1 + hx, nx), hyg = wrapi(y0 - 1 + hy, ny);
+    const unsigned hxo[3] = {(unsigned)wrapi(hxg - 1, nx) * E, (unsigned)hxg * E,
+                             (unsigned)wrapi(hxg + 1, nx) * E};
+    const unsigned hyo[3] = {(unsigned)wrapi(hyg - 1, ny) * (unsigned)nx * E,
+                             (unsigned)hyg * (unsigned)nx * E,
+                             (unsigned)wrapi(hyg + 1, ny) * (unsigned)nx * E};
+
+    double pdn[R];
+    T pjx[R], pjy[R], pjz[R];
+    unsigned pzo[3] = {0u, 0u, 0u};
+    const int nplanes = (z1 - z0) + 2;
+    for (int k = 0; k < nplanes; ++k) {
+        const int p = z0 - 1 + k;
+        const unsigned zo[3] = {(unsigned)wrapi(p - 1, nz) * nxy * E,
+                                (unsigned)wrapi(p, nz) * nxy * E,
+                                (unsigned)wrapi(p + 1, nz) * nxy * E};
+        T(*slot)[LX] = ring[k & 3];
+        double cdn[R];
+        T cjx[R], cjy[R], cjz[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            pull_moments(sbuf, zo, yo[r], xo, cdn[r], cjx[r], cjy[r], cjz[r]);
+            slot[wv * R + r + 1][lane + 1] = psi_of<T, PSI>(rho_ref + (T)cdn[r]);
+        }
+        if (has_halo) {
+            double hdn;
+            T hjx, hjy, hjz;
+            pull_moments(sbuf, zo, hyo, hxo, hdn, hjx, hjy, hjz);
+            slot[hy][hx] = psi_of<T, PSI>(rho_ref + (T)hdn);
+        }
+        __syncthreads();
+        if (k >= 2) {
+            // collide plane q = p - 1 with psi of planes q - 1, q, q + 1
+            const T(*pm)[LX] = ring[(k - 2) & 3];
+            const T(*pc)[LX] = ring[(k - 1) & 3];
+            const T(*pp)[LX] = ring[k & 3];
+            const unsigned qoff = (unsigned)(p - 1) * nxy * E;
+            const int lx = lane + 1;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                if (!(xin && yin[r])) continue;
+                const int ly = wv * R + r + 1;
+                const T c_e = pc[ly][lx + 1], c_w = pc[ly][lx - 1];
+                const T c_n = pc[ly + 1][lx], c_s = pc[ly - 1][lx];
+                const T c_ne = pc[ly + 1][lx + 1], c_nw = pc[ly + 1][lx - 1];
+                const T c_se = pc[ly - 1][lx + 1], c_sw = pc[ly - 1][lx - 1];
+                const T p_c = pp[ly][lx], p_e = pp[ly][lx + 1], p_w = pp[ly][lx - 1];
+                const T p_n = pp[ly + 1][lx], p_s = pp[ly - 1][lx];
+                const T m_c = pm[ly][lx], m_e = pm[ly][lx + 1], m_w = pm[ly][lx - 1];
+                const T m_n = pm[ly + 1][lx], m_s = pm[ly - 1][lx];
+                const T psi0 = pc[ly][lx];
+                const T w1 = (T)W1, w2 = (T)W2;
+                // S = sum_a w_a psi(x + xi_a) xi_a; F = -G c_s^2 psi(x) sum_a W_a psi xi_a
+                //   = -G psi(x) S   (Eq. SCForce with c_s^2 W_a = w_a)
+                const T Sx = w1 * (c_e - c_w) +
+                             w2 * ((c_ne - c_nw) + (c_se - c_sw) + (p_e - p_w) + (m_e - m_w));
+                const T Sy = w1 * (c_n - c_s) +
+                             w2 * ((c_ne - c_se) + (c_nw - c_sw) + (p_n - p_s) + (m_n - m_s));
+                const T Sz = w1 * (p_c - m_c) +
+                             w2 * ((p_e - m_e) + (p_w - m_w) + (p_n - m_n) + (p_s - m_s));
+                const T gp = -G * psi0;
+                const unsigned off = qoff + yo[r][1] + xo[1];
+                if constexpr (TAU1) {
+                    collide_store<T, true>(dbuf, off, rho_ref, pdn[r], pjx[r], pjy[r], pjz[r],
+                                           gp * Sx, gp * Sy, gp * Sz, inv_tau, guo_pref, nullptr);
+                } else {
+                    T fin[Q];
+                    static_for<0, Q>([&](auto I) {
+                        constexpr int i = decltype(I)::value;
+                        fin[i] = bload<T, i>(sbuf, pzo[1 - CZ[i]] + yo[r][1 - CY[i]] + xo[1 - CX[i]]);
+                    });
+                    collide_store<T, false>(dbuf, off, rho_ref, pdn[r], pjx[r], pjy[r], pjz[r],
+                                            gp * Sx, gp * Sy, gp * Sz, inv_tau, guo_pref, fin);
+                }
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            pdn[r] = cdn[r];
+            pjx[r] = cjx[r];
+            pjy[r] = cjy[r];
+            pjz[r] = cjz[r];
+        }
+        pzo[0] = zo[0];
+        pzo[1] = zo[1];
+        pzo[2] = zo[2];
+    }
+}
+
+template <typename T, int PSI, bool TAU1, int R>
+hipError_t launch_step_t(const StepArgs& a, const void* src, void* dst, hipStream_t st)
+{
+    const unsigned grid = (unsigned)(a.tiles_x * a.tiles_y * a.nchunks);
+    hipLaunchKernelGGL((k_step<T, PSI, TAU1, R>), dim3(grid), dim3(NT), 0, st, a,
+                       (const T*)src, (T*)dst);
+    return hipGetLastError();
+}
+
+template <typename T, int PSI, bool TAU1>
+hipError_t dispatch_rows(int rows, const StepArgs& a, const void* src, void* dst, hipStream_t st)
+{
+    switch (rows) {
+        case 1: return launch_step_t<T, PSI, TAU1, 1>(a, src, dst, st);
+        case 2: return launch_step_t<T, PSI, TAU1, 2>(a, src, dst, st);
+        case 4: return launch_step_t<T, PSI, TAU1, 4>(a, src, dst, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
+hipError_t dispatch_step(const StepShape& s, const StepArgs& a, const void* src, void* dst,
+                         hipStream_t st)
+{
+    const bool tau1 = a.b.tau == 1.0;
+    if (a.b.psi == 0)
+        return tau1 ? dispatch_rows<T, 0, true>(s.rows, a, src, dst, st)
+                    : dispatch_rows<T, 0, false>(s.rows, a, src, dst, st);
+    return tau1 ? dispatch_rows<T, 1, true>(s.rows, a, src, dst, st)
+                : dispatch_rows<T, 1, false>(s.rows, a, src, dst, st);
+}
+
+// ------------------------------------------------------------------------------------------
+// Initial state
+// ------------------------------------------------------------------------------------------
+
+__device__ __forceinline__ unsigned long long splitmix64(unsigned long long s)
+{
+    unsigned long long z = s + 0x9E3779B97F4A7C15ULL;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ int min_image(int v, int c, int L)
+{
+    int d = v - c;
+    if (2 * d > L) d -= L;
+    if (2 * d < -L) d += L;
+    return d;
+}
+
+__global__ void k_init_density(BoxDesc b, InitDesc d, double* __restrict__ dn,
+                               double* __restrict__ dpsi)
+{
+    const unsigned k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= b.n) return;
+    const int x = (int)(k % (unsigned)b.nx);
+    const int y = (int)((k / (unsigned)b.nx) % (unsigned)b.ny);
+    const int z = (int)(k / b.nxy);
+    const double dx = min_image(x, b.nx / 2, b.nx);
+    const double dy = min_image(y, b.ny / 2, b.ny);
+    const double dz = min_image(z, b.nz / 2, b.nz);
+    double r;
+    if (d.geom == 2) {
+        const double dd = d.slab_axis == 0 ? dx : (d.slab_axis == 1 ? dy : dz);
+        r = fabs(dd);
+    } else {
+        r = sqrt(dx * dx + dy * dy + dz * dz);
+    }
+    double n = 0.5 * (d.n_in + d.n_out) - 0.5 * (d.n_in - d.n_out) * tanh((r - d.radius) / d.width);
+    if (d.noise_amp != 0.0) {
+        const double u = (double)(splitmix64(d.seed ^ (unsigned long long)k) >> 11) *
+                         (1.0 / 9007199254740992.0);
+        n += d.noise_amp * (2.0 * u - 1.0);
+    }
+    dn[k] = n;
+    dpsi[k] = psi_rt(n, b.psi);
+}
+
+// S = sum_a w_a psi(x + xi_a) xi_a from a psi field with periodic wrap.
+__device__ __forceinline__ void sc_sum(const BoxDesc& b, const double* __restrict__ psi, int x,
+                                       int y, int z, double& Sx, double& Sy, double& Sz)
+{
+    double sx = 0.0, sy = 0.0, sz = 0.0;
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        const unsigned k = ((unsigned)wrapi(z + CZ[i], b.nz) * (unsigned)b.ny +
+                            (unsigned)wrapi(y + CY[i], b.ny)) * (unsigned)b.nx +
+                           (unsigned)wrapi(x + CX[i], b.nx);
+        const double v = weight(i) * psi[k];
+        sx += CX[i] * v;
+        sy += CY[i] * v;
+        sz += CZ[i] * v;
+    }
+    Sx = sx;
+    Sy = sy;
+    Sz = sz;
+}
+
+template <typename T>
+__global__ void k_init_pops(BoxDesc b, const double* __restrict__ dn,
+                            const double* __restrict__ dpsi, T* __restrict__ dst)
+{
+    const unsigned k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= b.n) return;
+    const int x = (int)(k % (unsigned)b.nx);
+    const int y = (int)((k / (unsigned)b.nx) % (unsigned)b.ny);
+    const int z = (int)(k / b.nxy);
+    double Sx, Sy, Sz;
+    sc_sum(b, dpsi, x, y, z, Sx, Sy, Sz);
+    const double n = dn[k];
+    const double g = -b.G * dpsi[k];
+    // zero physical velocity: u = -F/(2n)
+    const double ux = -0.5 * g * Sx / n, uy = -0.5 * g * Sy / n, uz = -0.5 * g * Sz / n;
+    const double uu = ux * ux + uy * uy + uz * uz;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const double c = CX[i] * ux + CY[i] * uy + CZ[i] * uz;
+        const double f = weight(i) * n * (1.0 + 3.0 * c + 4.5 * c * c - 1.5 * uu);
+        // f_i(x, 0) is the pull of the stored slot at x - xi_i
+        const unsigned s = ((unsigned)wrapi(z - CZ[i], b.nz) * (unsigned)b.ny +
+                            (unsigned)wrapi(y - CY[i], b.ny)) * (unsigned)b.nx +
+                           (unsigned)wrapi(x - CX[i], b.nx);
+        dst[(unsigned long long)i * b.stride + s] = (T)(f - weight(i) * b.rho_ref);
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Canonical FP64 <-> stored conversion (one population per launch)
+// ------------------------------------------------------------------------------------------
+
+template <typename T>
+__global__ void k_get(BoxDesc b, int cx, int cy, int cz, double w, const T* __restrict__ src,
+                      double* __restrict__ out)
+{
+    const unsigned k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= b.n) return;
+    const int x = (int)(k % (unsigned)b.nx);
+    const int y = (int)((k / (unsigned)b.nx) % (unsigned)b.ny);
+    const int z = (int)(k / b.nxy);
+    const unsigned s = ((unsigned)wrapi(z - cz, b.nz) * (unsigned)b.ny +
+                        (unsigned)wrapi(y - cy, b.ny)) * (unsigned)b.nx +
+                       (unsigned)wrapi(x - cx, b.nx);
+    out[k] = (double)src[s] + w * b.rho_ref;
+}
+
+template <typename T>
+__global__ void k_set(BoxDesc b, int cx, int cy, int cz, double w, const double* __restrict__ in,
+                      T* __restrict__ dst)
+{
+    const unsigned k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= b.n) return;
+    const int x = (int)(k % (unsigned)b.nx);
+    const int y = (int)((k / (unsigned)b.nx) % (unsigned)b.ny);
+    const int z = (int)(k / b.nxy);
+    // the slot at x holds the population that arrives at x + xi_i
+    const unsigned s = ((unsigned)wrapi(z + cz, b.nz) * (unsigned)b.ny +
+                        (unsigned)wrapi(y + cy, b.ny)) * (unsigned)b.nx +
+                       (unsigned)wrapi(x + cx, b.nx);
+    dst[k] = (T)(in[s] - w * b.rho_ref);
+}
+
+// ------------------------------------------------------------------------------------------
+// Observation (FP64)
+// ------------------------------------------------------------------------------------------
+
+template <typename T>
+__global__ void k_obs_pull(BoxDesc b, const T* __restrict__ src, double* __restrict__ dn,
+                           double* __restrict__ dpsi, double* __restrict__ dj)
+{
+    for (unsigned k = blockIdx.x * blockDim.x + threadIdx.x; k < b.n;
+         k += gridDim.x * blockDim.x) {
+        const int x = (int)(k % (unsigned)b.nx);
+        const int y = (int)((k / (unsigned)b.nx) % (unsigned)b.ny);
+        const int z = (int)(k / b.nxy);
+        double s = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const unsigned o = ((unsigned)wrapi(z - CZ[i], b.nz) * (unsigned)b.ny +
+                                (unsigned)wrapi(y - CY[i], b.ny)) * (unsigned)b.nx +
+                               (unsigned)wrapi(x - CX[i], b.nx);
+            const double f = (double)src[(unsigned long long)i * b.stride + o] + weight(i) * b.rho_ref;
+            s += f;
+            jx += CX[i] * f;
+            jy += CY[i] * f;
+            jz += CZ[i] * f;
+        }
+        dn[k] = s;
+        dpsi[k] = psi_rt(s, b.psi);
+        dj[k] = jx;
+        dj[b.n + k] = jy;
+        dj[2 * (unsigned long long)b.n + k] = jz;
+    }
+}
+
+enum { P_MASS = 0, P_MX, P_MY, P_MZ, P_CX, P_CY, P_CZ, P_DU, P_DMAX, P_BAD, P_NMIN, P_NMAX };
+static_assert(P_NMAX < OBS_PARTS, "partials");
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_down(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ double wave_min(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_down(v, o, 64));
+    return v;
+}
+
+// Offset from the centre used by the centre of mass: minimum image, and 0 for the node exactly
+// half a box away (it lies on both sides).
+__device__ __forceinline__ double com_offset(int v, int L)
+{
+    const int d = min_image(v, L / 2, L);
+    return (2 * d == L || 2 * d == -L) ? 0.0 : (double)d;
+}
+
+__global__ __launch_bounds__(256) void k_obs_reduce(BoxDesc b, const double* __restrict__ dn,
+                                                    const double* __restrict__ dpsi,
+                                                    double* __restrict__ du,
+                                                    const double* __restrict__ duprev,
+                                                    int has_prev, double* __restrict__ parts)
+{
+    double acc[OBS_PARTS];
+#pragma unroll
+    for (int q = 0; q < OBS_PARTS; ++q) acc[q] = 0.0;
+    acc[P_NMIN] = 1.0e300;
+    acc[P_NMAX] = -1.0e300;
+    const unsigned long long N = b.n;
+    for (unsigned k = blockIdx.x * blockDim.x + threadIdx.x; k < b.n;
+         k += gridDim.x * blockDim.x) {
+        const int x = (int)(k % (unsigned)b.nx);
+        const int y = (int)((k / (unsigned)b.nx) % (unsigned)b.ny);
+        const int z = (int)(k / b.nxy);
+        double Sx, Sy, Sz;
+        sc_sum(b, dpsi, x, y, z, Sx, Sy, Sz);
+        const double g = -b.G * dpsi[k];
+        const double Fx = g * Sx, Fy = g * Sy, Fz = g * Sz;
+        const double n = dn[k];
+        const double px = du[k] + 0.5 * Fx, py = du[N + k] + 0.5 * Fy, pz = du[2 * N + k] + 0.5 * Fz;
+        const double ux = px / n, uy = py / n, uz = pz / n;
+        du[k] = ux;
+        du[N + k] = uy;
+        du[2 * N + k] = uz;
+        acc[P_MASS] += n;
+        acc[P_MX] += px;
+        acc[P_MY] += py;
+        acc[P_MZ] += pz;
+        acc[P_CX] += n * com_offset(x, b.nx);
+        acc[P_CY] += n * com_offset(y, b.ny);
+        acc[P_CZ] += n * com_offset(z, b.nz);
+        if (has_prev) {
+            const double ex = fabs(ux - duprev[k]), ey = fabs(uy - duprev[N + k]),
+                         ez = fabs(uz - duprev[2 * N + k]);
+            acc[P_DU] += ex + ey + ez;
+            acc[P_DMAX] = fmax(acc[P_DMAX], fmax(ex, fmax(ey, ez)));
+        }
+        const bool ok = (n > 0.0) && isfinite(n) && isfinite(ux) && isfinite(uy) && isfinite(uz);
+        if (!ok) acc[P_BAD] += 1.0;
+        acc[P_NMIN] = fmin(acc[P_NMIN], n);
+        acc[P_NMAX] = fmax(acc[P_NMAX], n);
+    }
+    __shared__ double red[4][OBS_PARTS];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < OBS_PARTS; ++q) {
+        double v;
+        if (q == P_DMAX || q == P_NMAX) v = wave_max(acc[q]);
+        else if (q == P_NMIN) v = wave_min(acc[q]);
+        else v = wave_sum(acc[q]);
+        if (lane == 0) red[wv][q] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < OBS_PARTS) {
+        const int q = threadIdx.x;
+        double v = red[0][q];
+        for (int w = 1; w < 4; ++w) {
+            if (q == P_DMAX || q == P_NMAX) v = fmax(v, red[w][q]);
+            else if (q == P_NMIN) v = fmin(v, red[w][q]);
+            else v += red[w][q];
+        }
+        parts[blockIdx.x * OBS_PARTS + q] = v;
+    }
+}
+
+__global__ void k_obs_final(const double* __restrict__ parts, int nblocks, double* __restrict__ scal)
+{
+    const int q = threadIdx.x;
+    if (q >= OBS_PARTS) return;
+    double v = parts[q];
+    for (int blk = 1; blk < nblocks; ++blk) {
+        const double p = parts[blk * OBS_PARTS + q];
+        if (q == P_DMAX || q == P_NMAX) v = fmax(v, p);
+        else if (q == P_NMIN) v = fmin(v, p);
+        else v += p;
+    }
+    scal[q] = v;
+}
+
+// Diagonal of the lattice pressure tensor, Eq. (sm:pt):
+//   P^aa = n c_s^2 + (G c_s^2/2) psi(x) sum_a W_a psi(x + xi_a) (xi_a^a)^2
+//        = n/3 + (G/2) psi(x) sum_a w_a psi(x + xi_a) (xi_a^a)^2.
+__device__ __forceinline__ void pt_diag(const BoxDesc& b, const double* __restrict__ dn,
+                                        const double* __restrict__ psi, int x, int y, int z,
+                                        double& n, double& Pxx, double& Pyy, double& Pzz)
+{
+    double sxx = 0.0, syy = 0.0, szz = 0.0;
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        const unsigned k = ((unsigned)wrapi(z + CZ[i], b.nz) * (unsigned)b.ny +
+                            (unsigned)wrapi(y + CY[i], b.ny)) * (unsigned)b.nx +
+                           (unsigned)wrapi(x + CX[i], b.nx);
+        const double v = weight(i) * psi[k];
+        sxx += CX[i] * CX[i] * v;
+        syy += CY[i] * CY[i] * v;
+        szz += CZ[i] * CZ[i] * v;
+    }
+    const unsigned k0 = ((unsigned)z * (unsigned)b.ny + (unsigned)y) * (unsigned)b.nx + (unsigned)x;
+    n = dn[k0];
+    const double h = 0.5 * b.G * psi[k0];
+    Pxx = n / 3.0 + h * sxx;
+    Pyy = n / 3.0 + h * syy;
+    Pzz = n / 3.0 + h * szz;
+}
+
+// probes[0..3] = n and P^xx at the centre, n and P^xx at the far probe.
+__global__ void k_probes(BoxDesc b, const double* __restrict__ dn, const double* __restrict__ dpsi,
+                         double* __restrict__ probes)
+{
+    const int t = threadIdx.x;
+    if (t >= 2) return;
+    const int cx = b.nx / 2, cy = b.ny / 2, cz = b.nz / 2;
+    const int x = t == 0 ? cx : (cx + b.nx / 2) % b.nx;
+    const int y = t == 0 ? cy : (cy + b.ny / 2) % b.ny;
+    const int z = t == 0 ? cz : (cz + b.nz / 2) % b.nz;
+    double n, pxx, pyy, pzz;
+    pt_diag(b, dn, dpsi, x, y, z, n, pxx, pyy, pzz);
+    probes[2 * t] = n;
+    probes[2 * t + 1] = pxx;
+}
+
+__global__ void k_profile_line(BoxDesc b, const double* __restrict__ dn,
+                               const double* __restrict__ dpsi, double* __restrict__ prof)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= b.nx) return;
+    double n, pxx, pyy, pzz;
+    pt_diag(b, dn, dpsi, x, b.ny / 2, b.nz / 2, n, pxx, pyy, pzz);
+    prof[x] = n;
+    prof[b.nx + x] = pxx;
+    prof[2 * b.nx + x] = pyy;
+    prof[3 * b.nx + x] = pzz;
+}
+
+// One workgroup per plane normal to `axis`; plane averages of n, P^xx, P^yy, P^zz.
+__global__ __launch_bounds__(256) void k_profile_planes(BoxDesc b, int axis,
+                                                       const double* __restrict__ dn,
+                                                       const double* __restrict__ dpsi,
+                                                       double* __restrict__ prof)
+{
+    const int s = blockIdx.x;
+    const int L = axis == 0 ? b.nx : (axis == 1 ? b.ny : b.nz);
+    const int A = axis == 0 ? b.ny : b.nx;  // first in-plane axis length
+    const int B = axis == 2 ? b.ny : b.nz;  // second in-plane axis length
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int t = threadIdx.x; t < A * B; t += blockDim.x) {
+        const int a = t % A, c = t / A;
+        int x, y, z;
+        if (axis == 0) { x = s; y = a; z = c; }
+        else if (axis == 1) { x = a; y = s; z = c; }
+        else { x = a; y = c; z = s; }
+        double n, pxx, pyy, pzz;
+        pt_diag(b, dn, dpsi, x, y, z, n, pxx, pyy, pzz);
+        acc[0] += n;
+        acc[1] += pxx;
+        acc[2] += pyy;
+        acc[3] += pzz;
+    }
+    __shared__ double red[4][4];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const double v = wave_sum(acc[q]);
+        if (lane == 0) red[wv][q] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        const int q = threadIdx.x;
+        const double v = ((red[0][q] + red[1][q]) + red[2][q]) + red[3][q];
+        prof[q * L + s] = v / (double)(A * B);
+    }
+}
+
+unsigned blocks_for(unsigned n, unsigned bs) { return (n + bs - 1) / bs; }
+
+}  // namespace
+
+// ------------------------------------------------------------------------------------------
+// Host launchers
+// ------------------------------------------------------------------------------------------
+
+hipError_t launch_step(bool fp32, const BoxDesc& b, const StepShape& s, const void* src, void* dst,
+                       hipStream_t st)
+{
+    if (s.rows != 1 && s.rows != 2 && s.rows != 4) return hipErrorInvalidValue;
+    if (s.z_chunk < 1) return hipErrorInvalidValue;
+    StepArgs a;
+    a.b = b;
+    a.tiles_x = (b.nx + BX - 1) / BX;
+    const int by = NWAVE * s.rows;
+    a.tiles_y = (b.ny + by - 1) / by;
+    a.zc = s.z_chunk < b.nz ? s.z_chunk : b.nz;
+    a.nchunks = (b.nz + a.zc - 1) / a.zc;
+    a.remap = s.xcd_remap;
+    a.inv_tau = 1.0 / b.tau;
+    a.guo_pref = 1.0 - 0.5 / b.tau;
+    return fp32 ? dispatch_step<float>(s, a, src, dst, st)
+                : dispatch_step<double>(s, a, src, dst, st);
+}
+
+hipError_t launch_init(bool fp32, const BoxDesc& b, const InitDesc& d, double* dn, double* dpsi,
+                       void* dst, hipStream_t st)
+{
+    const unsigned g = blocks_for(b.n, 256);
+    hipLaunchKernelGGL(k_init_density, dim3(g), dim3(256), 0, st, b, d, dn, dpsi);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (fp32)
+        hipLaunchKernelGGL(k_init_pops<float>, dim3(g), dim3(256), 0, st, b, (const double*)dn,
+                           (const double*)dpsi, (float*)dst);
+    else
+        hipLaunchKernelGGL(k_init_pops<double>, dim3(g), dim3(256), 0, st, b, (const double*)dn,
+                           (const double*)dpsi, (double*)dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_get(bool fp32, const BoxDesc& b, int i, const void* src, double* out,
+                      hipStream_t st)
+{
+    const unsigned g = blocks_for(b.n, 256);
+    if (fp32)
+        hipLaunchKernelGGL(k_get<float>, dim3(g), dim3(256), 0, st, b, CX[i], CY[i], CZ[i],
+                           weight(i), (const float*)src + (unsigned long long)i * b.stride, out);
+    else
+        hipLaunchKernelGGL(k_get<double>, dim3(g), dim3(256), 0, st, b, CX[i], CY[i], CZ[i],
+                           weight(i), (const double*)src + (unsigned long long)i * b.stride, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_set(bool fp32, const BoxDesc& b, int i, const double* in, void* dst,
+                      hipStream_t st)
+{
+    const unsigned g = blocks_for(b.n, 256);
+    if (fp32)
+        hipLaunchKernelGGL(k_set<float>, dim3(g), dim3(256), 0, st, b, CX[i], CY[i], CZ[i],
+                           weight(i), in, (float*)dst + (unsigned long long)i * b.stride);
+    else
+        hipLaunchKernelGGL(k_set<double>, dim3(g), dim3(256), 0, st, b, CX[i], CY[i], CZ[i],
+                           weight(i), in, (double*)dst + (unsigned long long)i * b.stride);
+    return hipGetLastError();
+}
+
+hipError_t launch_observe(bool fp32, const BoxDesc& b, const void* src, double* dn, double* dpsi,
+                          double* du, const double* duprev, int has_prev, double* parts,
+                          double* scal, hipStream_t st)
+{
+    const unsigned g = blocks_for(b.n, 256) < 4096u ? blocks_for(b.n, 256) : 4096u;
+    if (fp32)
+        hipLaunchKernelGGL(k_obs_pull<float>, dim3(g), dim3(256), 0, st, b, (const float*)src, dn,
+                           dpsi, du);
+    else
+        hipLaunchKernelGGL(k_obs_pull<double>, dim3(g), dim3(256), 0, st, b, (const double*)src,
+                           dn, dpsi, du);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_obs_reduce, dim3(OBS_BLOCKS), dim3(256), 0, st, b, (const double*)dn,
+                       (const double*)dpsi, du, duprev, has_prev, parts);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_obs_final, dim3(1), dim3(64), 0, st, (const double*)parts, OBS_BLOCKS,
+                       scal);
+    return hipGetLastError();
+}
+
+hipError_t launch_profile_line(const BoxDesc& b, const double* dn, const double* dpsi,
+                               double* prof, double* probes, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_profile_line, dim3(blocks_for(b.nx, 256)), dim3(256), 0, st, b, dn, dpsi,
+                       prof);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_probes, dim3(1), dim3(64), 0, st, b, dn, dpsi, probes);
+    return hipGetLastError();
+}
+
+hipError_t launch_profile_planes(const BoxDesc& b, int axis, const double* dn, const double* dpsi,
+                                 double* prof, double* probes, hipStream_t st)
+{
+    const int L = axis == 0 ? b.nx : (axis == 1 ? b.ny : b.nz);
+    hipLaunchKernelGGL(k_profile_planes, dim3(L), dim3(256), 0, st, b, axis, dn, dpsi, prof);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_probes, dim3(1), dim3(64), 0, st, b, dn, dpsi, probes);
+    return hipGetLastError();
+}
+
+}  // namespace lbm

@@ -1,0 +1,61 @@
+// Host-side declarations of the device launchers (implemented in kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbm {
+
+// Geometry and physics of one box, passed by value to every kernel.
+struct BoxDesc {
+    int nx, ny, nz;
+    unsigned nxy;            // nx * ny
+    unsigned n;              // nx * ny * nz
+    unsigned long long stride;  // elements between consecutive population arrays (>= n)
+    int psi;                 // 0: exp(-1/n), 1: 1 - exp(-n)
+    double G;
+    double tau;
+    double rho_ref;          // 0 for FP64 storage
+};
+
+// Launch shape of the fused step kernel. The workgroup is 256 threads = 4 wave64s; the tile is
+// 64 x (4 * rows) nodes in x-y and z_chunk planes in z.
+struct StepShape {
+    int rows;        // rows of the tile per wave (1, 2 or 4)
+    int z_chunk;     // planes marched per workgroup
+    int xcd_remap;   // 1: map consecutive logical tiles to one XCD
+};
+
+struct InitDesc {
+    int geom;            // 0 droplet, 1 bubble, 2 slab
+    int slab_axis;
+    double radius;       // R (droplet/bubble) or half thickness (slab)
+    double width;
+    double n_in, n_out;
+    double noise_amp;
+    unsigned long long seed;
+};
+
+// Number of per-block partial sums written by the observation reduction.
+constexpr int OBS_PARTS = 14;
+// Fixed grid of the observation reduction (deterministic order of the partial sums).
+constexpr int OBS_BLOCKS = 512;
+
+hipError_t launch_step(bool fp32, const BoxDesc& b, const StepShape& s, const void* src, void* dst,
+                       hipStream_t st);
+hipError_t launch_init(bool fp32, const BoxDesc& b, const InitDesc& d, double* dn, double* dpsi,
+                       void* dst, hipStream_t st);
+hipError_t launch_get(bool fp32, const BoxDesc& b, int i, const void* src, double* out,
+                      hipStream_t st);
+hipError_t launch_set(bool fp32, const BoxDesc& b, int i, const double* in, void* dst,
+                      hipStream_t st);
+// Observation: pull moments, then force/velocity/reductions, then line or plane profiles.
+hipError_t launch_observe(bool fp32, const BoxDesc& b, const void* src, double* dn, double* dpsi,
+                          double* du, const double* duprev, int has_prev, double* parts,
+                          double* scal, hipStream_t st);
+hipError_t launch_profile_line(const BoxDesc& b, const double* dn, const double* dpsi,
+                               double* prof, double* probes, hipStream_t st);
+hipError_t launch_profile_planes(const BoxDesc& b, int axis, const double* dn, const double* dpsi,
+                                 double* prof, double* probes, hipStream_t st);
+
+}  // namespace lbm

@@ -1,0 +1,595 @@
+// Host side of the C ABI declared in include/lbm_sc.h: configuration checks, the flat-interface
+// coexistence rule, device memory, the step loop and the observables assembly.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/lbm_sc.h"
+#include "kernels.hpp"
+
+namespace {
+
+thread_local std::string g_err = "no error";
+
+int fail(int code, const std::string& msg)
+{
+    g_err = msg;
+    return code;
+}
+
+int fail_hip(const char* what, hipError_t e)
+{
+    return fail(LBM_SC_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr)                                   \
+    do {                                                \
+        hipError_t e_ = (expr);                         \
+        if (e_ != hipSuccess) return fail_hip(#expr, e_); \
+    } while (0)
+
+// ------------------------------------------------------------------------------------------
+// Equation of state (Eq. bulkp with e_2 = 1, c_s^2 = 1/3)
+// ------------------------------------------------------------------------------------------
+
+constexpr double CS2 = 1.0 / 3.0;
+
+double psi_h(double n, int kind) { return kind == 0 ? std::exp(-1.0 / n) : -std::expm1(-n); }
+double dpsi_h(double n, int kind)
+{
+    return kind == 0 ? std::exp(-1.0 / n) / (n * n) : std::exp(-n);
+}
+double dlogpsi_h(double n, int kind) { return kind == 0 ? 1.0 / (n * n) : 1.0 / std::expm1(n); }
+double P_h(double n, double G, int kind)
+{
+    const double p = psi_h(n, kind);
+    return n * CS2 + 0.5 * G * CS2 * p * p;
+}
+double dP_h(double n, double G, int kind) { return CS2 + G * CS2 * psi_h(n, kind) * dpsi_h(n, kind); }
+
+double gc_h(int kind) { return kind == 0 ? -std::exp(2.0) : -4.0; }
+double nc_h(int kind) { return kind == 0 ? 1.0 : std::log(2.0); }
+
+template <typename F>
+bool bisect(F f, double lo, double hi, double& root)
+{
+    double flo = f(lo), fhi = f(hi);
+    if (!(flo * fhi <= 0.0)) return false;
+    for (int it = 0; it < 200; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (mid == lo || mid == hi) break;
+        const double fm = f(mid);
+        if ((fm <= 0.0) == (flo <= 0.0)) {
+            lo = mid;
+            flo = fm;
+        } else {
+            hi = mid;
+        }
+    }
+    root = 0.5 * (lo + hi);
+    return true;
+}
+
+// Adaptive Simpson quadrature.
+template <typename F>
+double simpson_rec(F& f, double a, double b, double fa, double fm, double fb, double whole,
+                   double tol, int depth)
+{
+    const double m = 0.5 * (a + b), lm = 0.5 * (a + m), rm = 0.5 * (m + b);
+    const double flm = f(lm), frm = f(rm);
+    const double left = (m - a) / 6.0 * (fa + 4.0 * flm + fm);
+    const double right = (b - m) / 6.0 * (fm + 4.0 * frm + fb);
+    const double d = left + right - whole;
+    if (depth <= 0 || std::fabs(d) <= 15.0 * tol) return left + right + d / 15.0;
+    return simpson_rec(f, a, m, fa, flm, fm, left, 0.5 * tol, depth - 1) +
+           simpson_rec(f, m, b, fm, frm, fb, right, 0.5 * tol, depth - 1);
+}
+
+template <typename F>
+double integrate(F f, double a, double b, double tol)
+{
+    // split into panels so that the recursion starts resolved
+    const int panels = 64;
+    double total = 0.0;
+    for (int k = 0; k < panels; ++k) {
+        const double x0 = a + (b - a) * k / panels, x1 = a + (b - a) * (k + 1) / panels;
+        const double f0 = f(x0), f1 = f(x1), fm = f(0.5 * (x0 + x1));
+        const double whole = (x1 - x0) / 6.0 * (f0 + 4.0 * fm + f1);
+        total += simpson_rec(f, x0, x1, f0, fm, f1, whole, tol / panels, 40);
+    }
+    return total;
+}
+
+struct Coex {
+    double ng, nl, p0;
+};
+
+// Leading-order flat coexistence: P(n_g) = P(n_l) = p0, int (p0 - P) psi'/psi dn = 0.
+bool coexistence(int kind, double ratio, Coex& out)
+{
+    if (!(ratio > 1.0)) return false;
+    const double G = ratio * gc_h(kind), nc = nc_h(kind);
+    double sg, sl;
+    auto dP = [&](double n) { return dP_h(n, G, kind); };
+    if (!bisect(dP, 1e-3, nc, sg) || !bisect(dP, nc, 50.0, sl)) return false;
+    auto roots = [&](double p0, double& ng, double& nl) {
+        auto h = [&](double n) { return P_h(n, G, kind) - p0; };
+        return bisect(h, std::fmin(1e-9, 0.5 * p0), sg, ng) && bisect(h, sl, 200.0, nl);
+    };
+    auto residual = [&](double p0, bool& ok) {
+        double ng, nl;
+        ok = roots(p0, ng, nl);
+        if (!ok) return 0.0;
+        auto integrand = [&](double n) { return (p0 - P_h(n, G, kind)) * dlogpsi_h(n, kind); };
+        return integrate(integrand, ng, nl, 1e-15);
+    };
+    const double p_hi = P_h(sg, G, kind);
+    const double p_lo = std::fmax(P_h(sl, G, kind), 0.0);
+    const double eps = 1e-9 * (p_hi - p_lo);
+    bool ok;
+    double hi = p_hi - eps, r_hi = residual(hi, ok);
+    if (!ok) return false;
+    double lo = -1.0;
+    for (int k = 1; k < 60; ++k) {
+        // geometric steps away from the top of the coexistence range
+        const double frac = std::pow(10.0, -9.0 + 9.0 * k / 59.0);
+        double p = p_hi - (p_hi - p_lo) * frac;
+        if (k == 59) p = p_lo + eps;
+        const double r = residual(p, ok);
+        if (!ok) return false;
+        if ((r > 0.0) != (r_hi > 0.0)) {
+            lo = p;
+            break;
+        }
+        hi = p;
+        r_hi = r;
+    }
+    if (lo < 0.0) return false;
+    double p0;
+    auto res = [&](double p) {
+        bool okk;
+        return residual(p, okk);
+    };
+    if (!bisect(res, lo, hi, p0)) return false;
+    double ng, nl;
+    if (!roots(p0, ng, nl)) return false;
+    out = {ng, nl, p0};
+    return true;
+}
+
+}  // namespace
+
+struct lbm_sc {
+    lbm_sc_config cfg;
+    lbm::BoxDesc box;
+    lbm::StepShape shape;
+    lbm::InitDesc init;
+    bool fp32 = false;
+    size_t elem = 8;
+    void* pop[2] = {nullptr, nullptr};
+    int cur = 0;
+    int64_t step = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    double* d_n = nullptr;     // N doubles: density, also the staging buffer of get/set
+    double* d_psi = nullptr;   // N doubles
+    double* d_u = nullptr;     // 3N doubles: momentum, then velocity
+    double* d_uprev = nullptr; // 3N doubles
+    double* d_parts = nullptr; // OBS_BLOCKS * OBS_PARTS
+    double* d_small = nullptr; // scalars (OBS_PARTS) + probes (4)
+    double* d_prof = nullptr;  // 4 * Lmax
+    int has_prev = 0;
+    double mass0 = 0.0;
+    double G = 0.0, Gc = 0.0;
+    int64_t device_bytes = 0;
+};
+
+namespace {
+
+int validate(const lbm_sc_config* c)
+{
+    if (!c) return fail(LBM_SC_EINVAL, "cfg is NULL");
+    if (c->nx < 1 || c->ny < 1 || c->nz < 1) return fail(LBM_SC_EINVAL, "box sizes must be >= 1");
+    const double nodes = (double)c->nx * c->ny * c->nz;
+    if (nodes > 4.0e9) return fail(LBM_SC_EINVAL, "box has more than 4e9 nodes");
+    if (c->psi != LBM_SC_PSI_EXP && c->psi != LBM_SC_PSI_ONEMINUS)
+        return fail(LBM_SC_EINVAL, "psi must be LBM_SC_PSI_EXP or LBM_SC_PSI_ONEMINUS");
+    if (c->geom < LBM_SC_DROPLET || c->geom > LBM_SC_FROM_HOST)
+        return fail(LBM_SC_EINVAL, "unknown geom");
+    if (c->prec != LBM_SC_FP64 && c->prec != LBM_SC_FP32_SHIFTED)
+        return fail(LBM_SC_EINVAL, "prec must be LBM_SC_FP64 or LBM_SC_FP32_SHIFTED");
+    if (c->reserved0 != 0) return fail(LBM_SC_EINVAL, "reserved0 must be 0");
+    if (!(c->tau > 0.5) || !std::isfinite(c->tau)) return fail(LBM_SC_EINVAL, "tau must be > 0.5");
+    if (!std::isfinite(c->g_over_gc)) return fail(LBM_SC_EINVAL, "g_over_gc must be finite");
+    if (c->geom != LBM_SC_FROM_HOST) {
+        if (!(c->width > 0.0)) return fail(LBM_SC_EINVAL, "width must be > 0");
+        if (c->geom == LBM_SC_SLAB) {
+            if (c->slab_axis < 0 || c->slab_axis > 2) return fail(LBM_SC_EINVAL, "slab_axis must be 0..2");
+            if (!(c->slab_thickness > 0.0)) return fail(LBM_SC_EINVAL, "slab_thickness must be > 0");
+        } else if (!(c->radius > 0.0)) {
+            return fail(LBM_SC_EINVAL, "radius must be > 0");
+        }
+        const bool auto_dens = c->n_in == 0.0 && c->n_out == 0.0;
+        if (auto_dens && !(c->g_over_gc > 1.0))
+            return fail(LBM_SC_EINVAL, "g_over_gc must be > 1 when the coexistence densities are computed");
+        if (!auto_dens && !(c->n_in > 0.0 && c->n_out > 0.0))
+            return fail(LBM_SC_EINVAL, "n_in and n_out must both be > 0 (or both 0)");
+        if (!(c->noise_amp >= 0.0)) return fail(LBM_SC_EINVAL, "noise_amp must be >= 0");
+    }
+    if (!(c->rho_ref >= 0.0) || !std::isfinite(c->rho_ref)) return fail(LBM_SC_EINVAL, "rho_ref must be >= 0");
+    return LBM_SC_OK;
+}
+
+void release(lbm_sc* h)
+{
+    if (!h) return;
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    void* bufs[] = {h->pop[0], h->pop[1], h->d_n, h->d_psi, h->d_u, h->d_uprev,
+                    h->d_parts, h->d_small, h->d_prof};
+    for (void* p : bufs)
+        if (p) (void)hipFree(p);
+    if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+    delete h;
+}
+
+int alloc(lbm_sc* h, void** p, size_t bytes)
+{
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return fail(LBM_SC_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed: " +
+                                       hipGetErrorString(e));
+    }
+    h->device_bytes += (int64_t)bytes;
+    return LBM_SC_OK;
+}
+
+int profile_len(const lbm_sc* h)
+{
+    if (h->cfg.geom == LBM_SC_SLAB)
+        return h->cfg.slab_axis == 0 ? h->box.nx : (h->cfg.slab_axis == 1 ? h->box.ny : h->box.nz);
+    return h->box.nx;
+}
+
+// Run the observation kernels and assemble lbm_sc_obs on the host (synchronises).
+int observe(lbm_sc* h, lbm_sc_obs* o, double* prof_out)
+{
+    const lbm::BoxDesc& b = h->box;
+    HIP_TRY(lbm::launch_observe(h->fp32, b, h->pop[h->cur], h->d_n, h->d_psi, h->d_u, h->d_uprev,
+                                h->has_prev, h->d_parts, h->d_small, h->stream));
+    const int L = profile_len(h);
+    if (h->cfg.geom == LBM_SC_SLAB)
+        HIP_TRY(lbm::launch_profile_planes(b, h->cfg.slab_axis, h->d_n, h->d_psi, h->d_prof,
+                                           h->d_small + lbm::OBS_PARTS, h->stream));
+    else
+        HIP_TRY(lbm::launch_profile_line(b, h->d_n, h->d_psi, h->d_prof,
+                                         h->d_small + lbm::OBS_PARTS, h->stream));
+    double small[lbm::OBS_PARTS + 4];
+    std::vector<double> prof(4 * (size_t)L);
+    HIP_TRY(hipMemcpyAsync(small, h->d_small, sizeof(small), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipMemcpyAsync(prof.data(), h->d_prof, prof.size() * sizeof(double),
+                           hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipMemcpyAsync(h->d_uprev, h->d_u, 3 * (size_t)b.n * sizeof(double),
+                           hipMemcpyDeviceToDevice, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+
+    std::memset(o, 0, sizeof(*o));
+    const double nan = std::nan("");
+    o->step = h->step;
+    o->mass = small[0];
+    o->mass0 = h->mass0;
+    for (int c = 0; c < 3; ++c) o->mom[c] = small[1 + c];
+    const int dims[3] = {b.nx, b.ny, b.nz};
+    for (int c = 0; c < 3; ++c) o->com[c] = dims[c] / 2 + small[4 + c] / small[0];
+    o->du_l1 = h->has_prev ? small[7] / (double)b.n : nan;
+    o->du_max = h->has_prev ? small[8] : nan;
+    o->has_du = h->has_prev;
+    o->finite = small[9] == 0.0 ? 1 : 0;
+    o->n_min = small[10];
+    o->n_max = small[11];
+    const double* probes = small + lbm::OBS_PARTS;
+    o->n_center = probes[0];
+    o->P_in = probes[1];
+    o->n_far = probes[2];
+    o->P_out = probes[3];
+    o->dP = o->P_in - o->P_out;
+    o->C = nan;
+    o->R_s = nan;
+    o->sigma_s = nan;
+    o->R_e = nan;
+    o->sigma0_flat = nan;
+    o->pn_spread = nan;
+    if (h->cfg.geom == LBM_SC_SLAB) {
+        const int a = h->cfg.slab_axis, t = (a + 1) % 3;
+        const double* PN = prof.data() + (size_t)(1 + a) * L;
+        const double* PT = prof.data() + (size_t)(1 + t) * L;
+        double s = 0.0, mx = PN[0], mn = PN[0];
+        for (int k = L / 2; k < L; ++k) s += PN[k] - PT[k];
+        for (int k = 0; k < L; ++k) {
+            mx = std::fmax(mx, PN[k]);
+            mn = std::fmin(mn, PN[k]);
+        }
+        o->sigma0_flat = s;
+        o->pn_spread = mx - mn;
+    } else {
+        // C = int_0^{R_out} r^2 (P_out - P_T(r)) dr along +x from the centre, P_T = P^yy
+        const int cx = b.nx / 2, R_out = b.nx - 1 - cx;
+        const double* Pyy = prof.data() + 2 * (size_t)L;
+        double C = 0.0;
+        for (int r = 0; r < R_out; ++r) {
+            const double y0 = (double)r * r * (o->P_out - Pyy[cx + r]);
+            const double y1 = (double)(r + 1) * (r + 1) * (o->P_out - Pyy[cx + r + 1]);
+            C += 0.5 * (y0 + y1);
+        }
+        o->C = C;
+        if (o->dP > 0.0 && C > 0.0) {
+            o->R_s = std::cbrt(6.0 * C / o->dP);
+            o->sigma_s = 0.5 * o->dP * o->R_s;
+        }
+        const double V = (double)b.n;
+        const double v = 3.0 * (o->mass - V * o->n_far) / (4.0 * M_PI * (o->n_center - o->n_far));
+        o->R_e = std::cbrt(v);
+    }
+    if (prof_out) std::memcpy(prof_out, prof.data(), prof.size() * sizeof(double));
+    h->has_prev = 1;
+    return LBM_SC_OK;
+}
+
+void default_shape(lbm_sc* h)
+{
+    h->shape.rows = h->fp32 ? 4 : 2;
+    h->shape.xcd_remap = 1;
+    const int by = 4 * h->shape.rows;
+    const long tiles = (long)((h->box.nx + 63) / 64) * ((h->box.ny + by - 1) / by);
+    // aim at about 1024 workgroups (4 per CU) with chunks of at least 8 planes
+    long chunks = (1024 + tiles - 1) / tiles;
+    const long max_chunks = (h->box.nz + 7) / 8;
+    if (chunks > max_chunks) chunks = max_chunks;
+    if (chunks < 1) chunks = 1;
+    h->shape.z_chunk = (int)((h->box.nz + chunks - 1) / chunks);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lbm_sc_last_error(void) { return g_err.c_str(); }
+
+double lbm_sc_gc(int32_t psi)
+{
+    if (psi != LBM_SC_PSI_EXP && psi != LBM_SC_PSI_ONEMINUS) return std::nan("");
+    return gc_h(psi);
+}
+
+int lbm_sc_coexistence(int32_t psi, double g_over_gc, double* n_gas, double* n_liquid, double* p0)
+{
+    if (psi != LBM_SC_PSI_EXP && psi != LBM_SC_PSI_ONEMINUS) return fail(LBM_SC_EINVAL, "unknown psi");
+    if (!(g_over_gc > 1.0)) return fail(LBM_SC_EINVAL, "g_over_gc must be > 1");
+    Coex c;
+    if (!coexistence(psi, g_over_gc, c)) return fail(LBM_SC_EINVAL, "no flat coexistence found");
+    if (n_gas) *n_gas = c.ng;
+    if (n_liquid) *n_liquid = c.nl;
+    if (p0) *p0 = c.p0;
+    return LBM_SC_OK;
+}
+
+int lbm_sc_create(const lbm_sc_config* cfg, lbm_sc** out)
+{
+    if (!out) return fail(LBM_SC_EINVAL, "out is NULL");
+    *out = nullptr;
+    int rc = validate(cfg);
+    if (rc) return rc;
+    lbm_sc* h = new (std::nothrow) lbm_sc();
+    if (!h) return fail(LBM_SC_ENOMEM, "host allocation failed");
+    h->cfg = *cfg;
+    h->fp32 = cfg->prec == LBM_SC_FP32_SHIFTED;
+    h->elem = h->fp32 ? 4 : 8;
+    h->Gc = gc_h(cfg->psi);
+    h->G = cfg->g_over_gc * h->Gc;
+
+    double n_in = cfg->n_in, n_out = cfg->n_out;
+    if (cfg->geom != LBM_SC_FROM_HOST && n_in == 0.0 && n_out == 0.0) {
+        Coex c;
+        if (!coexistence(cfg->psi, cfg->g_over_gc, c)) {
+            release(h);
+            return fail(LBM_SC_EINVAL, "no flat coexistence for this psi and g_over_gc");
+        }
+        n_in = cfg->geom == LBM_SC_BUBBLE ? c.ng : c.nl;
+        n_out = cfg->geom == LBM_SC_BUBBLE ? c.nl : c.ng;
+    }
+    h->cfg.n_in = n_in;
+    h->cfg.n_out = n_out;
+    double rho_ref = 0.0;
+    if (h->fp32) rho_ref = cfg->rho_ref > 0.0 ? cfg->rho_ref : 0.5 * (n_in + n_out);
+    if (h->fp32 && !(rho_ref > 0.0)) {
+        release(h);
+        return fail(LBM_SC_EINVAL, "FP32_SHIFTED with geom FROM_HOST needs rho_ref > 0");
+    }
+    h->cfg.rho_ref = rho_ref;
+
+    lbm::BoxDesc& b = h->box;
+    b.nx = cfg->nx;
+    b.ny = cfg->ny;
+    b.nz = cfg->nz;
+    b.nxy = (unsigned)cfg->nx * (unsigned)cfg->ny;
+    b.n = b.nxy * (unsigned)cfg->nz;
+    b.stride = ((unsigned long long)b.n + 63ull) / 64ull * 64ull;
+    b.psi = cfg->psi;
+    b.G = h->G;
+    b.tau = cfg->tau;
+    b.rho_ref = rho_ref;
+    default_shape(h);
+    // the step kernel addresses populations 0..9 and 10..18 through two buffer resources of at
+    // most 4 GiB each
+    if ((unsigned long long)10 * b.stride * h->elem >= (1ull << 32)) {
+        release(h);
+        return fail(LBM_SC_EINVAL, "box too large: 10 population arrays must fit in 4 GiB");
+    }
+
+    if (cfg->stream) {
+        h->stream = (hipStream_t)cfg->stream;
+    } else {
+        hipError_t e = hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            h->stream = nullptr;
+            release(h);
+            return fail_hip("hipStreamCreateWithFlags", e);
+        }
+        h->own_stream = true;
+    }
+
+    const size_t N = b.n;
+    const size_t popbytes = (size_t)19 * b.stride * h->elem;
+    int Lmax = b.nx > b.ny ? b.nx : b.ny;
+    Lmax = Lmax > b.nz ? Lmax : b.nz;
+    if ((rc = alloc(h, &h->pop[0], popbytes)) || (rc = alloc(h, &h->pop[1], popbytes)) ||
+        (rc = alloc(h, (void**)&h->d_n, N * 8)) || (rc = alloc(h, (void**)&h->d_psi, N * 8)) ||
+        (rc = alloc(h, (void**)&h->d_u, 3 * N * 8)) || (rc = alloc(h, (void**)&h->d_uprev, 3 * N * 8)) ||
+        (rc = alloc(h, (void**)&h->d_parts, (size_t)lbm::OBS_BLOCKS * lbm::OBS_PARTS * 8)) ||
+        (rc = alloc(h, (void**)&h->d_small, (lbm::OBS_PARTS + 4) * 8)) ||
+        (rc = alloc(h, (void**)&h->d_prof, 4 * (size_t)Lmax * 8))) {
+        std::string msg = g_err;
+        release(h);
+        return fail(rc, msg);
+    }
+
+    if (cfg->geom != LBM_SC_FROM_HOST) {
+        lbm::InitDesc& d = h->init;
+        d.geom = cfg->geom == LBM_SC_SLAB ? 2 : 0;
+        d.slab_axis = cfg->slab_axis;
+        d.radius = cfg->geom == LBM_SC_SLAB ? 0.5 * cfg->slab_thickness : cfg->radius;
+        d.width = cfg->width;
+        d.n_in = n_in;
+        d.n_out = n_out;
+        d.noise_amp = cfg->noise_amp;
+        d.seed = cfg->seed;
+        hipError_t e = lbm::launch_init(h->fp32, b, d, h->d_n, h->d_psi, h->pop[0], h->stream);
+        if (e != hipSuccess) {
+            release(h);
+            return fail_hip("launch_init", e);
+        }
+        lbm_sc_obs o;
+        rc = observe(h, &o, nullptr);
+        if (rc) {
+            std::string msg = g_err;
+            release(h);
+            return fail(rc, msg);
+        }
+        h->mass0 = o.mass;
+    } else {
+        hipError_t e = hipMemsetAsync(h->pop[0], 0, popbytes, h->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+        if (e != hipSuccess) {
+            release(h);
+            return fail_hip("hipMemsetAsync", e);
+        }
+    }
+    h->cur = 0;
+    h->step = 0;
+    *out = h;
+    return LBM_SC_OK;
+}
+
+int lbm_sc_step(lbm_sc* h, int64_t nsteps)
+{
+    if (!h) return fail(LBM_SC_EINVAL, "handle is NULL");
+    if (nsteps < 0) return fail(LBM_SC_EINVAL, "nsteps must be >= 0");
+    for (int64_t s = 0; s < nsteps; ++s) {
+        hipError_t e = lbm::launch_step(h->fp32, h->box, h->shape, h->pop[h->cur],
+                                        h->pop[1 - h->cur], h->stream);
+        if (e != hipSuccess) return fail_hip("launch_step", e);
+        h->cur = 1 - h->cur;
+        ++h->step;
+    }
+    return LBM_SC_OK;
+}
+
+int lbm_sc_sync(lbm_sc* h)
+{
+    if (!h) return fail(LBM_SC_EINVAL, "handle is NULL");
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return LBM_SC_OK;
+}
+
+int lbm_sc_observables(lbm_sc* h, lbm_sc_obs* out, double* prof, size_t prof_len)
+{
+    if (!h || !out) return fail(LBM_SC_EINVAL, "handle or out is NULL");
+    if (prof && prof_len != 4 * (size_t)profile_len(h))
+        return fail(LBM_SC_EINVAL, "prof_len must be 4 * " + std::to_string(profile_len(h)));
+    int rc = observe(h, out, prof);
+    if (rc) return rc;
+    if (!out->finite) return fail(LBM_SC_EUNSTABLE, "non-finite value or n <= 0 in the state");
+    return LBM_SC_OK;
+}
+
+int lbm_sc_get_populations(lbm_sc* h, double* f, size_t len)
+{
+    if (!h || !f) return fail(LBM_SC_EINVAL, "handle or f is NULL");
+    const size_t N = h->box.n;
+    if (len != 19 * N) return fail(LBM_SC_EINVAL, "len must be 19*nx*ny*nz");
+    for (int i = 0; i < 19; ++i) {
+        HIP_TRY(lbm::launch_get(h->fp32, h->box, i, h->pop[h->cur], h->d_n, h->stream));
+        HIP_TRY(hipMemcpyAsync(f + (size_t)i * N, h->d_n, N * 8, hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+    }
+    return LBM_SC_OK;
+}
+
+int lbm_sc_set_populations(lbm_sc* h, const double* f, size_t len)
+{
+    if (!h || !f) return fail(LBM_SC_EINVAL, "handle or f is NULL");
+    const size_t N = h->box.n;
+    if (len != 19 * N) return fail(LBM_SC_EINVAL, "len must be 19*nx*ny*nz");
+    for (int i = 0; i < 19; ++i) {
+        HIP_TRY(hipMemcpyAsync(h->d_n, f + (size_t)i * N, N * 8, hipMemcpyHostToDevice, h->stream));
+        HIP_TRY(lbm::launch_set(h->fp32, h->box, i, h->d_n, h->pop[h->cur], h->stream));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+    }
+    h->step = 0;
+    h->has_prev = 0;
+    lbm_sc_obs o;
+    int rc = observe(h, &o, nullptr);
+    if (rc) return rc;
+    h->mass0 = o.mass;
+    return LBM_SC_OK;
+}
+
+int lbm_sc_get_info(lbm_sc* h, lbm_sc_info* out)
+{
+    if (!h || !out) return fail(LBM_SC_EINVAL, "handle or out is NULL");
+    std::memset(out, 0, sizeof(*out));
+    out->G = h->G;
+    out->Gc = h->Gc;
+    out->n_in = h->cfg.n_in;
+    out->n_out = h->cfg.n_out;
+    out->rho_ref = h->cfg.rho_ref;
+    out->nodes = (int64_t)h->box.n;
+    out->device_bytes = h->device_bytes;
+    out->bytes_per_step = (int64_t)2 * 19 * (int64_t)h->elem * (int64_t)h->box.n;
+    out->block_x = 64;
+    out->block_y = 4 * h->shape.rows;
+    out->z_chunk = h->shape.z_chunk;
+    return LBM_SC_OK;
+}
+
+int lbm_sc_set_launch(lbm_sc* h, int32_t rows, int32_t z_chunk, int32_t xcd_remap)
+{
+    if (!h) return fail(LBM_SC_EINVAL, "handle is NULL");
+    if (rows != 1 && rows != 2 && rows != 4) return fail(LBM_SC_EINVAL, "rows must be 1, 2 or 4");
+    if (z_chunk < 1) return fail(LBM_SC_EINVAL, "z_chunk must be >= 1");
+    if (xcd_remap != 0 && xcd_remap != 1) return fail(LBM_SC_EINVAL, "xcd_remap must be 0 or 1");
+    h->shape.rows = rows;
+    h->shape.z_chunk = z_chunk < h->box.nz ? z_chunk : h->box.nz;
+    h->shape.xcd_remap = xcd_remap;
+    return LBM_SC_OK;
+}
+
+void lbm_sc_destroy(lbm_sc* h) { release(h); }
+
+}  // extern "C"

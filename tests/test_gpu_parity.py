@@ -1,0 +1,317 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 oracle on the same seeded inputs.
+
+Bars (written into each test):
+  - FP64 storage: max |f_gpu - f_oracle| / max |f_oracle| <= 1e-11 after one step from an
+    identical state, and the same along the 2000-step 32^3 droplet;
+  - FP32-shifted storage: one step from the identical (FP32-representable) state within a bound
+    derived from single-precision rounding of the collision (a few ulp of the largest shifted
+    population), and after 2000 steps densities within 1e-4 n_l and dP within 1e-3 of FP64;
+  - launch shapes: bitwise identical results (the per-node arithmetic does not depend on them).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import paper_2105_08772_amd as lbm
+from oracle import core, eos, observe
+from tests import inputs
+
+pytestmark = pytest.mark.gpu
+
+XI, W, _ = core.tables()
+TOL64 = 1e-11
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel_err(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+def fp32_representable(f, rho_ref):
+    """The FP64 state that an FP32-shifted box holds after set_populations(f)."""
+    g = (f - W.reshape(19, 1, 1, 1) * rho_ref).astype(np.float32).astype(np.float64)
+    return g + W.reshape(19, 1, 1, 1) * rho_ref
+
+
+def make_box(dims, prec=lbm.LBM_SC_FP64, psi=lbm.LBM_SC_PSI_EXP, ratio=1.3, tau=1.0,
+             rho_ref=0.0):
+    nx, ny, nz = dims
+    cfg = lbm.config(nx, ny, nz, psi=psi, geom=lbm.LBM_SC_FROM_HOST, prec=prec, tau=tau,
+                     g_over_gc=ratio, rho_ref=rho_ref if rho_ref else 1.0)
+    return lbm.Box(cfg)
+
+
+SHAPES = [(4, 4, 4), (32, 32, 32), (37, 29, 11), (130, 7, 6), (5, 70, 9), (1, 1, 8), (2, 3, 5),
+          (3, 3, 3)]
+
+
+@pytest.mark.parametrize("dims", SHAPES)
+@pytest.mark.parametrize("psi,ratio,tau", [(0, 1.3, 1.0), (1, 1.2, 0.8), (0, 1.6, 1.3)])
+def test_one_step_fp64(dims, psi, ratio, tau):
+    say(f"one step FP64 dims={dims} psi={psi} G/Gc={ratio} tau={tau}")
+    f = inputs.random_populations(dims, 100 + sum(dims), W * 1.5, amp=0.3)
+    G = ratio * lbm.lbm_sc_gc(psi)
+    with make_box(dims, psi=psi, ratio=ratio, tau=tau) as b:
+        b.set(f)
+        b.step(1)
+        g = b.get()
+    ref = core.step(f, G, tau, psi)
+    assert rel_err(g, ref) <= TOL64
+
+
+@pytest.mark.parametrize("dims", [(4, 4, 4), (37, 29, 11), (130, 7, 6), (64, 40, 20)])
+@pytest.mark.parametrize("tau", [1.0, 0.7])
+def test_one_step_fp32_shifted(dims, tau):
+    say(f"one step FP32 dims={dims} tau={tau}")
+    rho_ref = 1.5
+    f = fp32_representable(inputs.random_populations(dims, 7 + sum(dims), W * 1.5, amp=0.3), rho_ref)
+    G = 1.3 * lbm.lbm_sc_gc(0)
+    with make_box(dims, prec=lbm.LBM_SC_FP32_SHIFTED, tau=tau, rho_ref=rho_ref) as b:
+        b.set(f)
+        b.step(1)
+        g = b.get()
+    ref = core.step(f, G, tau, 0)
+    # single-precision collision: each shifted population carries a few roundings of quantities
+    # no larger than the largest |f|; 1e-6 relative to max |f| leaves a margin of ~10 ulp
+    assert rel_err(g, ref) <= 1e-6
+    # mass per node is closed exactly up to the last rounding
+    n_g = g.sum(axis=0)
+    n_r = ref.sum(axis=0)
+    assert abs(n_g.sum() - n_r.sum()) / n_r.sum() < 1e-7
+
+
+@pytest.mark.parametrize("prec", [lbm.LBM_SC_FP64, lbm.LBM_SC_FP32_SHIFTED])
+def test_launch_shapes_are_bitwise_identical(prec):
+    say(f"launch shapes prec={prec}")
+    dims = (70, 45, 33)
+    rho_ref = 1.5
+    f = fp32_representable(inputs.random_populations(dims, 3, W * 1.5, amp=0.3), rho_ref)
+    outs = []
+    for rows, zc, remap in ((1, 1, 0), (2, 7, 1), (4, 33, 1), (4, 5, 0), (1, 64, 1)):
+        with make_box(dims, prec=prec, rho_ref=rho_ref) as b:
+            b.set(f)
+            b.set_launch(rows, zc, remap)
+            b.step(3)
+            outs.append(b.get())
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+
+
+def droplet_cfg(prec=lbm.LBM_SC_FP64, n=32, R=8.0, seed=1, noise=1e-6, geom=lbm.LBM_SC_DROPLET,
+                psi=lbm.LBM_SC_PSI_EXP, ratio=1.3):
+    return lbm.config(n, n, n, psi=psi, geom=geom, prec=prec, tau=1.0, g_over_gc=ratio,
+                      radius=R, width=2.0, noise_amp=noise, seed=seed)
+
+
+@pytest.mark.parametrize("geom", [lbm.LBM_SC_DROPLET, lbm.LBM_SC_BUBBLE])
+def test_initial_state_matches_oracle(geom):
+    say(f"initial state geom={geom}")
+    cfg = droplet_cfg(geom=geom, n=21, R=5.0, seed=12345)
+    with lbm.Box(cfg) as b:
+        info = b.info()
+        f = b.get()
+    G = info["G"]
+    n0 = core.init_density(21, 21, 21, core.DROPLET, 5.0, 2.0, info["n_in"], info["n_out"], 1e-6,
+                           12345)
+    ref = core.init_populations(n0, G, core.PSI_EXP)
+    assert rel_err(f, ref) <= 1e-13
+    ng, nl, _ = eos.coexistence_rule(G, core.PSI_EXP)
+    if geom == lbm.LBM_SC_DROPLET:
+        assert abs(info["n_in"] - nl) < 1e-12 and abs(info["n_out"] - ng) < 1e-12
+    else:
+        assert abs(info["n_in"] - ng) < 1e-12 and abs(info["n_out"] - nl) < 1e-12
+
+
+@pytest.fixture(scope="module")
+def droplet32_run():
+    """The 32^3 FP64 droplet (exp psi, G = 1.3 G_c, tau = 1, R = 8, width 2, noise 1e-6, seed 1)
+    stepped 2000 times on the GPU and by the oracle, compared every 250 steps."""
+    say("32^3 FP64 droplet: GPU vs oracle over 2000 steps")
+    cfg = droplet_cfg()
+    errs = []
+    with lbm.Box(cfg) as b:
+        info = b.info()
+        G = info["G"]
+        f = b.get()
+        ref = f.copy()
+        for k in range(8):
+            b.step(250)
+            ref = core.run(ref, G, 1.0, core.PSI_EXP, 250)
+            g = b.get()
+            errs.append(rel_err(g, ref))
+        obs, prof = b.observables()
+    return dict(errs=errs, g=g, ref=ref, obs=obs, prof=prof, info=info)
+
+
+def test_droplet32_trajectory_parity(droplet32_run):
+    errs = droplet32_run["errs"]
+    say("relative errors every 250 steps:", errs)
+    assert max(errs) <= TOL64
+
+
+def test_droplet32_one_step_from_late_state(droplet32_run):
+    """Per-step parity at step 2000 from the oracle's own state."""
+    ref = droplet32_run["ref"]
+    G = droplet32_run["info"]["G"]
+    with make_box((32, 32, 32)) as b:
+        b.set(ref)
+        b.step(1)
+        g = b.get()
+    assert rel_err(g, core.step(ref, G, 1.0, core.PSI_EXP)) <= TOL64
+
+
+def test_droplet32_observables(droplet32_run):
+    obs = droplet32_run["obs"]
+    G = droplet32_run["info"]["G"]
+    o = observe.observables(droplet32_run["ref"], G, core.PSI_EXP)
+    assert obs["step"] == 2000
+    assert obs["finite"] == 1
+    assert abs(obs["mass"] - o["mass"]) <= 1e-12 * o["mass"]
+    assert abs(obs["mass"] - obs["mass0"]) <= 1e-12 * obs["mass0"]
+    for k in ("n_center", "n_far", "P_in", "P_out"):
+        assert abs(obs[k] - o[k]) <= 1e-11 * abs(o[k]), k
+    assert abs(obs["dP"] - o["dP"]) <= 1e-9 * abs(o["dP"])
+    for k in ("C", "R_s", "sigma_s", "R_e"):
+        assert abs(obs[k] - o[k]) <= 1e-9 * abs(o[k]), k
+    for c in range(3):
+        assert abs(obs["com"][c] - o["com"][c]) <= 1e-10
+        assert abs(obs["mom"][c] - o["mom"][c]) <= 1e-10
+    assert np.abs(droplet32_run["prof"] - o["prof"]).max() <= 1e-11 * np.abs(o["prof"]).max()
+    # a droplet: liquid inside and higher pressure inside (Laplace); its surface of tension lies
+    # inside the equimolar surface and sigma_s is below the flat value (positive Tolman length
+    # for droplets, Sec. 4); sigma_0 = 0.0495 is the flat lattice value at G/G_c = 1.3
+    assert obs["n_center"] > 2.0 and obs["n_far"] < 0.6 and obs["dP"] > 0
+    assert obs["C"] > 0 and 0 < obs["R_s"] < obs["R_e"] and 0 < obs["sigma_s"] < 0.0495
+
+
+def test_du_against_previous_call():
+    say("du between observation calls")
+    cfg = droplet_cfg(n=16, R=4.0)
+    with lbm.Box(cfg) as b:
+        f0 = b.get()
+        o0, _ = b.observables()
+        assert o0["has_du"] == 1 and o0["du_max"] == 0.0   # nothing moved since creation
+        b.step(10)
+        o1, _ = b.observables()
+        f1 = b.get()
+    G = 1.3 * lbm.lbm_sc_gc(0)
+    _, u0 = core.velocity(f0, G, 0)
+    _, u1 = core.velocity(f1, G, 0)
+    d = np.abs(u1 - u0)
+    assert abs(o1["du_max"] - d.max()) <= 1e-12 + 1e-9 * d.max()
+    assert abs(o1["du_l1"] - d.sum() / 16**3) <= 1e-12 + 1e-9 * d.sum() / 16**3
+
+
+def test_slab_observables_match_oracle():
+    say("slab 8x6x48 FP64 observables")
+    cfg = lbm.config(8, 6, 48, geom=lbm.LBM_SC_SLAB, prec=lbm.LBM_SC_FP64, g_over_gc=1.3,
+                     slab_thickness=24.0, width=2.0, slab_axis=2)
+    with lbm.Box(cfg) as b:
+        b.step(300)
+        obs, prof = b.observables()
+        f = b.get()
+        G = b.info()["G"]
+    o = observe.observables(f, G, core.PSI_EXP, geom=core.SLAB, slab_axis=2)
+    assert np.abs(prof - o["prof"]).max() <= 1e-12 * np.abs(o["prof"]).max()
+    assert abs(obs["sigma0_flat"] - o["sigma0_flat"]) <= 1e-10 * abs(o["sigma0_flat"])
+    assert abs(obs["pn_spread"] - o["pn_spread"]) <= 1e-12
+
+
+def test_slab_along_x_equals_slab_along_z():
+    """Rotating the box rotates the answer: the x-normal slab reports the z-normal profile."""
+    say("slab orientation")
+    outs = []
+    for axis, dims in ((2, (6, 5, 40)), (0, (40, 5, 6))):
+        cfg = lbm.config(*dims, geom=lbm.LBM_SC_SLAB, g_over_gc=1.2, slab_thickness=20.0,
+                         width=2.0, slab_axis=axis)
+        with lbm.Box(cfg) as b:
+            b.step(200)
+            obs, prof = b.observables()
+        outs.append((obs, prof))
+    (oz, pz), (ox, px) = outs
+    assert np.abs(pz[0] - px[0]).max() < 1e-13
+    assert abs(oz["sigma0_flat"] - ox["sigma0_flat"]) < 1e-12
+    assert np.abs(pz[3] - px[1]).max() < 1e-13   # P_N: P^zz of the z slab = P^xx of the x slab
+
+
+def test_fp32_vs_fp64_droplet_after_2000_steps():
+    """FP32-shifted populations against FP64 on the 32^3 droplet: densities within 1e-4 n_l and
+    dP within 1e-3 dP after 2000 steps."""
+    say("32^3 droplet FP32-shifted vs FP64, 2000 steps")
+    res = {}
+    for prec in (lbm.LBM_SC_FP64, lbm.LBM_SC_FP32_SHIFTED):
+        with lbm.Box(droplet_cfg(prec=prec)) as b:
+            b.step(2000)
+            obs, prof = b.observables()
+            n = b.get().sum(axis=0)
+            res[prec] = (obs, prof, n, b.info())
+    o64, _, n64, info = res[lbm.LBM_SC_FP64]
+    o32, _, n32, _ = res[lbm.LBM_SC_FP32_SHIFTED]
+    nl = info["n_in"]
+    say("max |n32-n64| / n_l =", np.abs(n32 - n64).max() / nl,
+        " |dP32-dP64|/dP64 =", abs(o32["dP"] - o64["dP"]) / o64["dP"])
+    assert np.abs(n32 - n64).max() <= 1e-4 * nl
+    assert abs(o32["dP"] - o64["dP"]) <= 1e-3 * o64["dP"]
+    drift = abs(o32["mass"] - o32["mass0"]) / o32["mass0"]
+    say("FP32 relative mass drift after 2000 steps:", drift)
+    assert drift <= 2e-6
+
+
+def test_unstable_state_is_reported():
+    say("non-finite state detection")
+    dims = (8, 8, 8)
+    f = inputs.random_populations(dims, 5, W * 1.0, amp=0.1)
+    f[3, 2, 2, 2] = np.nan
+    with make_box(dims) as b:
+        b.set(f)
+        obs, _ = b.observables(raise_unstable=False)
+        assert obs["finite"] == 0
+        with pytest.raises(lbm.LbmScError) as e:
+            b.observables()
+        assert e.value.code == lbm.LBM_SC_EUNSTABLE
+
+
+def test_zero_steps_is_a_no_op():
+    dims = (6, 5, 4)
+    f = inputs.random_populations(dims, 8, W * 1.0, amp=0.1)
+    with make_box(dims) as b:
+        b.set(f)
+        b.step(0)
+        assert np.array_equal(b.get(), f)
+
+
+def test_full_size_bench_workload_sampled():
+    """The 256^3 FP32-shifted droplet (exp psi, G/G_c = 1.3, R = 60, width 2, noise 1e-6,
+    seed 3) in the launch shape the benchmark times: one step checked on sampled nodes against
+    the oracle's single-node collision, plus mass conservation over 20 steps."""
+    say("256^3 FP32 bench workload, sampled one-step parity")
+    cfg = lbm.config(256, 256, 256, psi=0, geom=lbm.LBM_SC_DROPLET, prec=lbm.LBM_SC_FP32_SHIFTED,
+                     g_over_gc=1.3, radius=60.0, width=2.0, noise_amp=1e-6, seed=3)
+    rng = np.random.default_rng(2024)
+    with lbm.Box(cfg) as b:
+        G = b.info()["G"]
+        f0 = b.get()
+        b.step(1)
+        f1 = b.get()
+        o0 = b.observables(profile=False)[0]
+        b.step(19)
+        o1 = b.observables(profile=False)[0]
+    # sampled nodes: random ones plus nodes across the interface and on the box faces
+    pts = [tuple(rng.integers(0, 256, 3)) for _ in range(120)]
+    pts += [(128 + 60 + d, 128, 128) for d in range(-3, 4)] + [(0, 0, 0), (255, 255, 255),
+                                                                (255, 0, 128)]
+    scale = np.abs(f0).max()
+    worst = 0.0
+    for (x, y, z) in pts:
+        fs = core.collide_at(f0, G, 1.0, 0, x, y, z)
+        for i in range(19):
+            d = ((x + XI[i, 0]) % 256, (y + XI[i, 1]) % 256, (z + XI[i, 2]) % 256)
+            worst = max(worst, abs(f1[i, d[2], d[1], d[0]] - fs[i]) / scale)
+    say("worst sampled error / max|f| =", worst)
+    assert worst <= 1e-6
+    assert abs(o1["mass"] - o0["mass"]) <= 1e-7 * o0["mass"]

@@ -1,0 +1,103 @@
+"""CPU checks of the C-ABI library: it loads, exports every declared symbol, and its host-only
+functions and argument checks behave as documented. No kernel runs here."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2105_08772_amd as lbm
+from oracle import eos
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lbm_sc.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_sc_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    L = lbm.load()
+    names = declared_functions()
+    assert len(names) >= 12
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(names) == set(lbm.EXPORTS)
+
+
+def test_critical_coupling_closed_forms():
+    assert lbm.lbm_sc_gc(lbm.LBM_SC_PSI_EXP) == pytest.approx(-np.e ** 2, rel=1e-15)
+    assert lbm.lbm_sc_gc(lbm.LBM_SC_PSI_ONEMINUS) == -4.0
+    assert np.isnan(lbm.lbm_sc_gc(7))
+
+
+@pytest.mark.parametrize("psi,ratio", [(0, 1.05), (0, 1.3), (0, 1.8), (1, 1.1), (1, 1.3)])
+def test_coexistence_matches_oracle_rule(psi, ratio):
+    ng, nl, p0 = lbm.lbm_sc_coexistence(psi, ratio)
+    rg, rl, rp = eos.coexistence_rule(eos.G_of(ratio, psi), psi)
+    assert abs(ng - rg) <= 1e-11 * rg
+    assert abs(nl - rl) <= 1e-11 * rl
+    assert abs(p0 - rp) <= 1e-11 * abs(rp)
+
+
+def test_coexistence_rejects_supercritical():
+    with pytest.raises(lbm.LbmScError) as e:
+        lbm.lbm_sc_coexistence(0, 0.9)
+    assert e.value.code == lbm.LBM_SC_EINVAL
+
+
+BAD = [
+    dict(nx=0), dict(tau=0.5), dict(psi=2), dict(geom=9), dict(prec=3), dict(radius=0.0),
+    dict(width=0.0), dict(g_over_gc=0.95), dict(n_in=1.0, n_out=0.0), dict(noise_amp=-1.0),
+    dict(geom=lbm.LBM_SC_SLAB, slab_thickness=0.0, slab_axis=2),
+    dict(geom=lbm.LBM_SC_SLAB, slab_thickness=4.0, slab_axis=3),
+]
+
+
+@pytest.mark.parametrize("bad", BAD)
+def test_invalid_configurations_are_rejected_before_any_device_work(bad):
+    kw = dict(radius=3.0, width=2.0)
+    kw.update(bad)
+    nx = kw.pop("nx", 8)
+    cfg = lbm.config(nx, 8, 8, **kw)
+    with pytest.raises(lbm.LbmScError) as e:
+        lbm.lbm_sc_create(cfg)
+    assert e.value.code == lbm.LBM_SC_EINVAL
+    assert lbm.lbm_sc_last_error()
+
+
+def test_ctypes_structs_match_the_c_layout(tmp_path):
+    """Compile a probe against include/lbm_sc.h and compare every field offset and struct size
+    with the ctypes mirrors of the Python binding."""
+    import subprocess
+    structs = {"lbm_sc_config": lbm.LbmScConfig, "lbm_sc_obs": lbm.LbmScObs,
+               "lbm_sc_info": lbm.LbmScInfo}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "lbm_sc.h"', 'int main(void){']
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} sizeof %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines.append("return 0;}")
+    src = tmp_path / "probe.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "probe"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    out = subprocess.check_output([str(exe)]).decode().split("\n")
+    seen = 0
+    for line in out:
+        if not line:
+            continue
+        cname, fname, val = line.split()
+        py = structs[cname]
+        want = ctypes_sizeof(py) if fname == "sizeof" else getattr(py, fname).offset
+        assert int(val) == want, (cname, fname)
+        seen += 1
+    assert seen == sum(len(p._fields_) + 1 for p in structs.values())
+
+
+def ctypes_sizeof(t):
+    import ctypes
+    return ctypes.sizeof(t)
