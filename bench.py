@@ -47,24 +47,35 @@ def measured_traffic(nodes):
     return t.get("bytes_per_launch")
 
 
-def stream_copy_gbps(torch, nbytes=2 << 30, reps=20):
-    """Achievable HBM bandwidth: device-to-device copy of a 2 GiB buffer (read + write)."""
+def stream_copy_gbps(torch, lbm, stream, nbytes=2 << 30, reps=20):
+    """Achievable HBM bandwidth: the library's streaming copy of a 2 GiB buffer, counted as
+    read + write bytes, and torch's device-to-device copy for comparison."""
     a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
     a.fill_(1.0)
-    for _ in range(3):
-        b.copy_(a)
     torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        b.copy_(a)
-    e1.record()
-    torch.cuda.synchronize()
-    s = e0.elapsed_time(e1) / 1e3 / reps
+    out = {}
+    for name in ("lbm_sc_stream_copy", "torch_copy"):
+        def run():
+            if name == "torch_copy":
+                with torch.cuda.stream(stream):
+                    b.copy_(a)
+            else:
+                lbm.lbm_sc_stream_copy(a.data_ptr(), b.data_ptr(), nbytes, stream.cuda_stream)
+        for _ in range(3):
+            run()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            run()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        s = e0.elapsed_time(e1) / 1e3 / reps
+        out[name] = round(2 * nbytes / s / 1e9, 1)
     del a, b
     torch.cuda.empty_cache()
-    return 2 * nbytes / s / 1e9
+    return out
 
 
 def cpu_baseline(args, nodes_gpu):
@@ -104,10 +115,15 @@ def main():
     ap.add_argument("--rows", type=int, default=0)
     ap.add_argument("--zchunk", type=int, default=0)
     ap.add_argument("--remap", type=int, default=-1)
+    ap.add_argument("--prefetch", type=int, default=-1)
     ap.add_argument("--tune", action="store_true", help="sweep launch shapes, keep the fastest")
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-copy", action="store_true")
+    ap.add_argument("--mode", choices=["step", "copy"], default="step",
+                    help="copy: only the streaming-copy reference (for counter calibration)")
+    ap.add_argument("--copy-mib", type=int, default=1024)
+    ap.add_argument("--copy-reps", type=int, default=5)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1",
@@ -121,6 +137,17 @@ def main():
     # a dedicated stream (default priority): the library enqueues on it and the timing events
     # are recorded on it
     stream = torch.cuda.Stream()
+    if args.mode == "copy":
+        nbytes = args.copy_mib << 20
+        a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        for _ in range(args.copy_reps):
+            lbm.lbm_sc_stream_copy(a.data_ptr(), b.data_ptr(), nbytes, stream.cuda_stream)
+        torch.cuda.synchronize()
+        print(json.dumps({"mode": "copy", "bytes_read_per_launch": nbytes,
+                          "bytes_written_per_launch": nbytes, "launches": args.copy_reps}))
+        return
     L = args.size
     psi = lbm.LBM_SC_PSI_EXP if args.psi == "exp" else lbm.LBM_SC_PSI_ONEMINUS
     prec = lbm.LBM_SC_FP32_SHIFTED if args.prec == "fp32" else lbm.LBM_SC_FP64
@@ -147,22 +174,26 @@ def main():
     if args.tune:
         best = None
         for rows in (1, 2, 4):
-            for zc in (8, 16, 32, 64, 128):
+            for zc in (8, 11, 16, 22, 32, 43, 64, 128):
                 for remap in (0, 1):
-                    box.set_launch(rows, zc, remap)
-                    box.step(8)
-                    t = time_steps(64)
-                    print(f"# tune rows={rows} zchunk={zc} remap={remap} "
-                          f"{nodes / t / 1e6:.0f} MLUPS", file=sys.stderr, flush=True)
-                    if best is None or t < best[0]:
-                        best = (t, rows, zc, remap)
-        tuned = dict(rows=best[1], z_chunk=best[2], xcd_remap=best[3])
-        box.set_launch(best[1], best[2], best[3])
-    if args.rows or args.zchunk or args.remap >= 0:
-        i = box.info()
-        box.set_launch(args.rows or i["block_y"] // 4, args.zchunk or i["z_chunk"],
-                       args.remap if args.remap >= 0 else 1)
+                    for pf in (0, 1):
+                        box.set_launch(rows, zc, remap, pf)
+                        box.step(8)
+                        t = time_steps(64)
+                        print(f"# tune rows={rows} zchunk={zc} remap={remap} prefetch={pf} "
+                              f"{nodes / t / 1e6:.0f} MLUPS {bytes_per_step / t / 1e9:.0f} GB/s",
+                              file=sys.stderr, flush=True)
+                        if best is None or t < best[0]:
+                            best = (t, rows, zc, remap, pf)
+        tuned = dict(rows=best[1], z_chunk=best[2], xcd_remap=best[3], prefetch=best[4])
+        box.set_launch(best[1], best[2], best[3], best[4])
+    if args.rows or args.zchunk or args.remap >= 0 or args.prefetch >= 0:
+        lc = box.launch()
+        box.set_launch(args.rows or lc["rows"], args.zchunk or lc["z_chunk"],
+                       args.remap if args.remap >= 0 else lc["xcd_remap"],
+                       args.prefetch if args.prefetch >= 0 else lc["prefetch"])
     info = box.info()
+    launch = box.launch()
 
     # warmup
     box.step(args.warmup)
@@ -194,7 +225,7 @@ def main():
     obs, _ = box.observables(profile=False)
     box.close()
 
-    copy_bw = None if args.no_copy else stream_copy_gbps(torch)
+    copy_bw = None if args.no_copy else stream_copy_gbps(torch, lbm, stream)
     traffic = measured_traffic(nodes)
 
     out = {
@@ -216,8 +247,7 @@ def main():
                         f" noise 1e-6 seed 3, tau=1, FP64 observables every {args.observe_every}"
                         f" steps",
             "nodes": nodes,
-            "launch": {"block": [64, info["block_y"]], "z_chunk": info["z_chunk"],
-                       "tuned": tuned},
+            "launch": dict(launch, block=[64, 4 * launch["rows"]], tuned=tuned is not None),
         },
         "roofline": {
             "bound": "hbm",
@@ -228,7 +258,7 @@ def main():
             "traffic": traffic,
             "kernel_ms": round(step_s * 1e3, 5),
             "bytes_per_launch": bytes_per_step,
-            "stream_copy_GBps": None if copy_bw is None else round(copy_bw, 1),
+            "stream_copy_GBps": copy_bw,
         },
         "checks": {"finite": obs["finite"],
                    "mass_drift_rel": abs(obs["mass"] - obs["mass0"]) / obs["mass0"],

@@ -108,7 +108,7 @@ typedef struct {
     int64_t nodes;           /* nx*ny*nz */
     int64_t device_bytes;    /* device memory held by the handle */
     int64_t bytes_per_step;  /* algorithmic HBM bytes of one step: 2 * 19 * sizeof(storage) * nodes */
-    int32_t block_x, block_y, z_chunk; /* launch shape of the fused step kernel */
+    int32_t block_x, block_y, z_chunk; /* tile and chunk of the fused step kernel's launch shape */
     int32_t reserved;
 } lbm_sc_info;
 
@@ -147,12 +147,26 @@ int lbm_sc_get_populations(lbm_sc* h, double* f, size_t len);
  * Resets the step counter, mass0 and the du reference. Synchronises. */
 int lbm_sc_set_populations(lbm_sc* h, const double* f, size_t len);
 
-/* Set the launch shape of the fused step kernel: rows of the x-y tile per wave (1, 2 or 4; the
- * tile is 64 x 4*rows nodes), planes per workgroup along z (z_chunk >= 1) and whether workgroups
- * are remapped so that neighbouring tiles share an XCD (xcd_remap 0 or 1). The shape changes
- * only the schedule: every node's arithmetic and result are the same for every shape. Used by the
- * autotuner; LBM_SC_EINVAL for values out of range. */
-int lbm_sc_set_launch(lbm_sc* h, int32_t rows, int32_t z_chunk, int32_t xcd_remap);
+/* Launch shape of the fused step kernel. The workgroup is 256 threads (4 wave64s) and owns an
+ * x-y tile of 64 x (4*rows) nodes and a run of z_chunk planes along z. */
+typedef struct {
+    int32_t rows;       /* tile rows per wave: 1, 2 or 4 */
+    int32_t z_chunk;    /* planes per workgroup, >= 1 (clamped to nz) */
+    int32_t xcd_remap;  /* 1: hand neighbouring tiles to the same XCD (shared L2); 0: identity */
+    int32_t prefetch;   /* 1: issue the next plane's loads before the collision of the current one */
+} lbm_sc_launch;
+
+/* Set / read the launch shape. The shape changes only the schedule: every node's arithmetic and
+ * result are identical for every shape (bitwise). Used by the autotuner. LBM_SC_EINVAL for values
+ * out of range. */
+int lbm_sc_set_launch(lbm_sc* h, const lbm_sc_launch* launch);
+int lbm_sc_get_launch(lbm_sc* h, lbm_sc_launch* out);
+
+/* Measurement helper, not part of the method: copy `bytes` (a multiple of 16; src and dst
+ * 16-byte aligned device pointers that do not overlap) with a plain streaming kernel on `stream`
+ * (hipStream_t or NULL for the null stream). Asynchronous. It measures the achievable HBM
+ * bandwidth that the step kernel is compared with. LBM_SC_EINVAL on bad sizes or alignment. */
+int lbm_sc_stream_copy(const void* src, void* dst, size_t bytes, void* stream);
 
 /* Describe the handle (coupling, densities, sizes, launch shape). */
 int lbm_sc_get_info(lbm_sc* h, lbm_sc_info* out);

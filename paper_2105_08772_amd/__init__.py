@@ -57,6 +57,13 @@ class LbmScInfo(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
 
 
+class LbmScLaunch(ctypes.Structure):
+    _fields_ = [("rows", _i32), ("z_chunk", _i32), ("xcd_remap", _i32), ("prefetch", _i32)]
+
+    def to_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 class LbmScError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"lbm_sc error {code}: {msg}")
@@ -65,8 +72,8 @@ class LbmScError(RuntimeError):
 
 EXPORTS = ("lbm_sc_create", "lbm_sc_step", "lbm_sc_sync", "lbm_sc_observables",
            "lbm_sc_get_populations", "lbm_sc_set_populations", "lbm_sc_set_launch",
-           "lbm_sc_get_info", "lbm_sc_destroy", "lbm_sc_last_error", "lbm_sc_gc",
-           "lbm_sc_coexistence")
+           "lbm_sc_get_launch", "lbm_sc_stream_copy", "lbm_sc_get_info", "lbm_sc_destroy",
+           "lbm_sc_last_error", "lbm_sc_gc", "lbm_sc_coexistence")
 
 _lib = None
 
@@ -88,7 +95,9 @@ def load():
     L.lbm_sc_observables.argtypes = [_vp, P(LbmScObs), P(_f64), ctypes.c_size_t]
     L.lbm_sc_get_populations.argtypes = [_vp, P(_f64), ctypes.c_size_t]
     L.lbm_sc_set_populations.argtypes = [_vp, P(_f64), ctypes.c_size_t]
-    L.lbm_sc_set_launch.argtypes = [_vp, _i32, _i32, _i32]
+    L.lbm_sc_set_launch.argtypes = [_vp, P(LbmScLaunch)]
+    L.lbm_sc_get_launch.argtypes = [_vp, P(LbmScLaunch)]
+    L.lbm_sc_stream_copy.argtypes = [_vp, _vp, ctypes.c_size_t, _vp]
     L.lbm_sc_get_info.argtypes = [_vp, P(LbmScInfo)]
     L.lbm_sc_destroy.argtypes = [_vp]
     L.lbm_sc_destroy.restype = None
@@ -178,8 +187,20 @@ def lbm_sc_set_populations(h, f):
     _check(load().lbm_sc_set_populations(h, f.ctypes.data_as(ctypes.POINTER(_f64)), f.size))
 
 
-def lbm_sc_set_launch(h, rows, z_chunk, xcd_remap=1):
-    _check(load().lbm_sc_set_launch(h, rows, z_chunk, xcd_remap))
+def lbm_sc_set_launch(h, rows, z_chunk, xcd_remap=1, prefetch=0):
+    l = LbmScLaunch(rows, z_chunk, xcd_remap, prefetch)
+    _check(load().lbm_sc_set_launch(h, ctypes.byref(l)))
+
+
+def lbm_sc_get_launch(h):
+    l = LbmScLaunch()
+    _check(load().lbm_sc_get_launch(h, ctypes.byref(l)))
+    return l.to_dict()
+
+
+def lbm_sc_stream_copy(src_ptr, dst_ptr, nbytes, stream=None):
+    """Streaming copy between device pointers (ints), e.g. torch tensors' data_ptr()."""
+    _check(load().lbm_sc_stream_copy(src_ptr, dst_ptr, nbytes, stream))
 
 
 def lbm_sc_get_info(h):
@@ -221,8 +242,11 @@ class Box:
     def set(self, f):
         lbm_sc_set_populations(self.h, f)
 
-    def set_launch(self, rows, z_chunk, xcd_remap=1):
-        lbm_sc_set_launch(self.h, rows, z_chunk, xcd_remap)
+    def set_launch(self, rows, z_chunk, xcd_remap=1, prefetch=0):
+        lbm_sc_set_launch(self.h, rows, z_chunk, xcd_remap, prefetch)
+
+    def launch(self):
+        return lbm_sc_get_launch(self.h)
 
     def info(self):
         return lbm_sc_get_info(self.h)

@@ -65,6 +65,9 @@ __device__ __forceinline__ unsigned xcd_remap(unsigned b, unsigned nb)
 // nothing instead of faulting.
 constexpr int SPLIT = 10;
 constexpr unsigned RSRC_FLAGS = 0x00020000u;  // raw buffer, 32-bit dword format (gfx9 family)
+// Population stores carry the non-temporal cache policy: a stored population is read again
+// only in the next step, after the whole box has streamed through the caches.
+constexpr int STORE_CPOL_NT = 2;
 
 struct PopBuf {
     __amdgpu_buffer_rsrc_t lo, hi;
@@ -107,11 +110,11 @@ __device__ __forceinline__ void bstore(const PopBuf& b, unsigned voff, T v)
     const __amdgpu_buffer_rsrc_t r = I < SPLIT ? b.lo : b.hi;
     if constexpr (sizeof(T) == 4) {
         __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(int, v), r, (int)voff,
-                                              (int)(J * b.pop_bytes), 0);
+                                              (int)(J * b.pop_bytes), STORE_CPOL_NT);
     } else {
         typedef int v2i __attribute__((ext_vector_type(2)));
         __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2i, v), r, (int)voff,
-                                              (int)(J * b.pop_bytes), 0);
+                                              (int)(J * b.pop_bytes), STORE_CPOL_NT);
     }
 }
 
@@ -134,18 +137,25 @@ struct StepArgs {
 // Pull the 19 pre-collision populations of one node and reduce them to (sum g, j). Byte offsets
 // zo/yo/xo[d] address the plane/row/column at coordinate + d - 1; the source of velocity xi is the
 // node - xi.
-// The density deviation is accumulated in double precision: for FP32 storage the sum of the 19
-// stored values is then exact, so the density a node sees is exactly the mass it holds.
+// Load the 19 pre-collision populations of one node. Byte offsets zo/yo/xo[d] address the
+// plane/row/column at coordinate + d - 1; the source of velocity xi is the node - xi.
 template <typename T>
-__device__ __forceinline__ void pull_moments(const PopBuf& src, const unsigned (&zo)[3],
-                                             const unsigned (&yo)[3], const unsigned (&xo)[3],
-                                             double& dn, T& jx, T& jy, T& jz)
+__device__ __forceinline__ void load_node(const PopBuf& src, const unsigned (&zo)[3],
+                                          const unsigned (&yo)[3], const unsigned (&xo)[3],
+                                          T (&f)[Q])
 {
-    T f[Q];
     static_for<0, Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
         f[i] = bload<T, i>(src, zo[1 - CZ[i]] + yo[1 - CY[i]] + xo[1 - CX[i]]);
     });
+}
+
+// Reduce the populations of a node to (sum g, j). The density deviation is accumulated in double
+// precision: for FP32 storage the sum of the 19 stored values is then exact, so the density a
+// node sees is exactly the mass it holds.
+template <typename T>
+__device__ __forceinline__ void moments(const T (&f)[Q], double& dn, T& jx, T& jy, T& jz)
+{
     double s = (double)f[0];
     T ax = T(0), ay = T(0), az = T(0);
 #pragma unroll
@@ -211,7 +221,7 @@ __device__ __forceinline__ void collide_store(const PopBuf& dst, unsigned off, T
     bstore<T, 0>(dst, off, (T)(dn64 - sum));
 }
 
-template <typename T, int PSI, bool TAU1, int R>
+template <typename T, int PSI, bool TAU1, int R, bool PF>
 __global__ __launch_bounds__(NT) void k_step(StepArgs a, const T* __restrict__ src,
                                              T* __restrict__ dst)
 {
@@ -284,28 +294,56 @@ __global__ __launch_bounds__(NT) void k_step(StepArgs a, const T* __restrict__ s
                              (unsigned)hyg * (unsigned)nx * E,
                              (unsigned)wrapi(hyg + 1, ny) * (unsigned)nx * E};
 
+    auto plane_offsets = [&](int p, unsigned (&zo)[3]) {
+        zo[0] = (unsigned)wrapi(p - 1, nz) * nxy * E;
+        zo[1] = (unsigned)wrapi(p, nz) * nxy * E;
+        zo[2] = (unsigned)wrapi(p + 1, nz) * nxy * E;
+    };
+
+    // Raw populations of the plane being reduced. With PF the loads of plane k + 1 are issued
+    // right after plane k has been reduced, so they are in flight during the barrier and the
+    // collision of plane k - 1.
+    T fr[R][Q];
+    T fh[Q];
     double pdn[R];
     T pjx[R], pjy[R], pjz[R];
     unsigned pzo[3] = {0u, 0u, 0u};
     const int nplanes = (z1 - z0) + 2;
+    if constexpr (PF) {
+        unsigned zo[3];
+        plane_offsets(z0 - 1, zo);
+#pragma unroll
+        for (int r = 0; r < R; ++r) load_node(sbuf, zo, yo[r], xo, fr[r]);
+        if (has_halo) load_node(sbuf, zo, hyo, hxo, fh);
+    }
     for (int k = 0; k < nplanes; ++k) {
         const int p = z0 - 1 + k;
-        const unsigned zo[3] = {(unsigned)wrapi(p - 1, nz) * nxy * E,
-                                (unsigned)wrapi(p, nz) * nxy * E,
-                                (unsigned)wrapi(p + 1, nz) * nxy * E};
+        unsigned zo[3];
+        plane_offsets(p, zo);
         T(*slot)[LX] = ring[k & 3];
         double cdn[R];
         T cjx[R], cjy[R], cjz[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            pull_moments(sbuf, zo, yo[r], xo, cdn[r], cjx[r], cjy[r], cjz[r]);
+            if constexpr (!PF) load_node(sbuf, zo, yo[r], xo, fr[r]);
+            moments(fr[r], cdn[r], cjx[r], cjy[r], cjz[r]);
             slot[wv * R + r + 1][lane + 1] = psi_of<T, PSI>(rho_ref + (T)cdn[r]);
         }
         if (has_halo) {
             double hdn;
             T hjx, hjy, hjz;
-            pull_moments(sbuf, zo, hyo, hxo, hdn, hjx, hjy, hjz);
+            if constexpr (!PF) load_node(sbuf, zo, hyo, hxo, fh);
+            moments(fh, hdn, hjx, hjy, hjz);
             slot[hy][hx] = psi_of<T, PSI>(rho_ref + (T)hdn);
+        }
+        if constexpr (PF) {
+            if (k + 1 < nplanes) {
+                unsigned zn[3];
+                plane_offsets(p + 1, zn);
+#pragma unroll
+                for (int r = 0; r < R; ++r) load_node(sbuf, zn, yo[r], xo, fr[r]);
+                if (has_halo) load_node(sbuf, zn, hyo, hxo, fh);
+            }
         }
         __syncthreads();
         if (k >= 2) {
@@ -366,24 +404,32 @@ __global__ __launch_bounds__(NT) void k_step(StepArgs a, const T* __restrict__ s
     }
 }
 
-template <typename T, int PSI, bool TAU1, int R>
+template <typename T, int PSI, bool TAU1, int R, bool PF>
 hipError_t launch_step_t(const StepArgs& a, const void* src, void* dst, hipStream_t st)
 {
     const unsigned grid = (unsigned)(a.tiles_x * a.tiles_y * a.nchunks);
-    hipLaunchKernelGGL((k_step<T, PSI, TAU1, R>), dim3(grid), dim3(NT), 0, st, a,
+    hipLaunchKernelGGL((k_step<T, PSI, TAU1, R, PF>), dim3(grid), dim3(NT), 0, st, a,
                        (const T*)src, (T*)dst);
     return hipGetLastError();
 }
 
-template <typename T, int PSI, bool TAU1>
+template <typename T, int PSI, bool TAU1, bool PF>
 hipError_t dispatch_rows(int rows, const StepArgs& a, const void* src, void* dst, hipStream_t st)
 {
     switch (rows) {
-        case 1: return launch_step_t<T, PSI, TAU1, 1>(a, src, dst, st);
-        case 2: return launch_step_t<T, PSI, TAU1, 2>(a, src, dst, st);
-        case 4: return launch_step_t<T, PSI, TAU1, 4>(a, src, dst, st);
+        case 1: return launch_step_t<T, PSI, TAU1, 1, PF>(a, src, dst, st);
+        case 2: return launch_step_t<T, PSI, TAU1, 2, PF>(a, src, dst, st);
+        case 4: return launch_step_t<T, PSI, TAU1, 4, PF>(a, src, dst, st);
         default: return hipErrorInvalidValue;
     }
+}
+
+template <typename T, int PSI, bool TAU1>
+hipError_t dispatch_pf(const StepShape& s, const StepArgs& a, const void* src, void* dst,
+                       hipStream_t st)
+{
+    return s.prefetch ? dispatch_rows<T, PSI, TAU1, true>(s.rows, a, src, dst, st)
+                      : dispatch_rows<T, PSI, TAU1, false>(s.rows, a, src, dst, st);
 }
 
 template <typename T>
@@ -392,10 +438,10 @@ hipError_t dispatch_step(const StepShape& s, const StepArgs& a, const void* src,
 {
     const bool tau1 = a.b.tau == 1.0;
     if (a.b.psi == 0)
-        return tau1 ? dispatch_rows<T, 0, true>(s.rows, a, src, dst, st)
-                    : dispatch_rows<T, 0, false>(s.rows, a, src, dst, st);
-    return tau1 ? dispatch_rows<T, 1, true>(s.rows, a, src, dst, st)
-                : dispatch_rows<T, 1, false>(s.rows, a, src, dst, st);
+        return tau1 ? dispatch_pf<T, 0, true>(s, a, src, dst, st)
+                    : dispatch_pf<T, 0, false>(s, a, src, dst, st);
+    return tau1 ? dispatch_pf<T, 1, true>(s, a, src, dst, st)
+                : dispatch_pf<T, 1, false>(s, a, src, dst, st);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -770,6 +816,24 @@ __global__ __launch_bounds__(256) void k_profile_planes(BoxDesc b, int axis,
 
 unsigned blocks_for(unsigned n, unsigned bs) { return (n + bs - 1) / bs; }
 
+// Streaming copy used as the achievable-bandwidth reference. It uses the access width of the
+// step kernel (one dword per lane) with four loads in flight per thread, non-temporal stores and
+// a grid of 1024 workgroups, the fastest of the copy variants measured on MI355X.
+__global__ __launch_bounds__(256) void k_stream_copy(const float* __restrict__ src,
+                                                     float* __restrict__ dst, size_t n)
+{
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i + 3 * stride < n; i += 4 * stride) {
+        const float a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
+        __builtin_nontemporal_store(a, dst + i);
+        __builtin_nontemporal_store(b, dst + i + stride);
+        __builtin_nontemporal_store(c, dst + i + 2 * stride);
+        __builtin_nontemporal_store(d, dst + i + 3 * stride);
+    }
+    for (; i < n; i += stride) dst[i] = src[i];
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------------------------------
@@ -856,6 +920,17 @@ hipError_t launch_observe(bool fp32, const BoxDesc& b, const void* src, double* 
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_obs_final, dim3(1), dim3(64), 0, st, (const double*)parts, OBS_BLOCKS,
                        scal);
+    return hipGetLastError();
+}
+
+hipError_t launch_stream_copy(const void* src, void* dst, size_t bytes, hipStream_t st)
+{
+    const size_t n = bytes / 4;
+    if (n == 0) return hipSuccess;
+    const size_t want = (n + 255) / 256;
+    const unsigned grid = (unsigned)(want < 1024 ? want : 1024);
+    hipLaunchKernelGGL(k_stream_copy, dim3(grid), dim3(256), 0, st, (const float*)src,
+                       (float*)dst, n);
     return hipGetLastError();
 }
 

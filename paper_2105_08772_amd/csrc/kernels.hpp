@@ -24,6 +24,7 @@ struct StepShape {
     int rows;        // rows of the tile per wave (1, 2 or 4)
     int z_chunk;     // planes marched per workgroup
     int xcd_remap;   // 1: map consecutive logical tiles to one XCD
+    int prefetch;    // 1: issue the next plane's loads before the barrier (software pipelining)
 };
 
 struct InitDesc {
@@ -55,6 +56,7 @@ hipError_t launch_observe(bool fp32, const BoxDesc& b, const void* src, double* 
                           double* scal, hipStream_t st);
 hipError_t launch_profile_line(const BoxDesc& b, const double* dn, const double* dpsi,
                                double* prof, double* probes, hipStream_t st);
+hipError_t launch_stream_copy(const void* src, void* dst, size_t bytes, hipStream_t st);
 hipError_t launch_profile_planes(const BoxDesc& b, int axis, const double* dn, const double* dpsi,
                                  double* prof, double* probes, hipStream_t st);
 

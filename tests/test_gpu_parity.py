@@ -66,13 +66,16 @@ def test_one_step_fp64(dims, psi, ratio, tau):
 
 @pytest.mark.parametrize("dims", [(4, 4, 4), (37, 29, 11), (130, 7, 6), (64, 40, 20)])
 @pytest.mark.parametrize("tau", [1.0, 0.7])
-def test_one_step_fp32_shifted(dims, tau):
+@pytest.mark.parametrize("prefetch", [0, 1])
+def test_one_step_fp32_shifted(dims, tau, prefetch):
     say(f"one step FP32 dims={dims} tau={tau}")
     rho_ref = 1.5
     f = fp32_representable(inputs.random_populations(dims, 7 + sum(dims), W * 1.5, amp=0.3), rho_ref)
     G = 1.3 * lbm.lbm_sc_gc(0)
     with make_box(dims, prec=lbm.LBM_SC_FP32_SHIFTED, tau=tau, rho_ref=rho_ref) as b:
         b.set(f)
+        lc = b.launch()
+        b.set_launch(lc["rows"], lc["z_chunk"], lc["xcd_remap"], prefetch)
         b.step(1)
         g = b.get()
     ref = core.step(f, G, tau, 0)
@@ -92,10 +95,12 @@ def test_launch_shapes_are_bitwise_identical(prec):
     rho_ref = 1.5
     f = fp32_representable(inputs.random_populations(dims, 3, W * 1.5, amp=0.3), rho_ref)
     outs = []
-    for rows, zc, remap in ((1, 1, 0), (2, 7, 1), (4, 33, 1), (4, 5, 0), (1, 64, 1)):
+    for rows, zc, remap, pf in ((1, 1, 0, 0), (2, 7, 1, 1), (4, 33, 1, 0), (4, 5, 0, 1),
+                                (1, 64, 1, 1), (2, 3, 0, 0)):
         with make_box(dims, prec=prec, rho_ref=rho_ref) as b:
             b.set(f)
-            b.set_launch(rows, zc, remap)
+            b.set_launch(rows, zc, remap, pf)
+            assert b.launch() == dict(rows=rows, z_chunk=min(zc, 33), xcd_remap=remap, prefetch=pf)
             b.step(3)
             outs.append(b.get())
     for o in outs[1:]:
@@ -274,6 +279,17 @@ def test_unstable_state_is_reported():
         with pytest.raises(lbm.LbmScError) as e:
             b.observables()
         assert e.value.code == lbm.LBM_SC_EUNSTABLE
+
+
+def test_stream_copy_helper():
+    import torch
+    a = torch.arange(1 << 20, dtype=torch.float32, device="cuda")
+    b = torch.zeros_like(a)
+    lbm.lbm_sc_stream_copy(a.data_ptr(), b.data_ptr(), a.numel() * 4)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    with pytest.raises(lbm.LbmScError):
+        lbm.lbm_sc_stream_copy(a.data_ptr(), b.data_ptr(), 12)
 
 
 def test_zero_steps_is_a_no_op():
