@@ -162,6 +162,57 @@ typedef struct {
 int lbm_sc_set_launch(lbm_sc* h, const lbm_sc_launch* launch);
 int lbm_sc_get_launch(lbm_sc* h, lbm_sc_launch* out);
 
+/* ------------------------------------------------------------------------------------------
+ * Groups: many boxes advanced by one fused launch per time step.
+ *
+ * A group steps a set of existing boxes (handles made by lbm_sc_create) together: every step is
+ * one launch of the multi-box step kernel over the flattened list of (box, x-y tile, z chunk)
+ * work items, so boxes of different sizes, pseudopotentials, couplings and relaxation times share
+ * the GPU in a single launch. The per-node arithmetic is the same as lbm_sc_step, so a box
+ * stepped in a group ends bitwise equal to the same box stepped alone. All boxes of a group must
+ * have the same storage precision and must have been created on the group's stream. Boxes stay
+ * owned by the caller; the group keeps their handles until the next lbm_sc_group_set or
+ * lbm_sc_group_destroy, and they must not be destroyed in between.
+ * ------------------------------------------------------------------------------------------ */
+typedef struct lbm_sc_group lbm_sc_group;
+
+typedef struct {
+    int32_t rows;        /* tile rows per wave: 1, 2 or 4 (tile 64 x 4*rows) */
+    int32_t z_chunk;     /* planes per work item, >= 1 (clamped to each box's nz) */
+    int32_t xcd_remap;   /* non-persistent launch: hand neighbouring items to the same XCD */
+    int32_t prefetch;    /* issue the next plane's loads before the current collision */
+    int32_t persistent;  /* 1: fixed grid of `workers` workgroups drawing items from 8 per-XCD
+                            work queues; 0: one workgroup per item */
+    int32_t workers;     /* persistent grid size, a multiple of 8 (0 = 256) */
+    int32_t graph_steps; /* steps captured per hipGraph and replayed (even, 0 = no graph) */
+    int32_t reserved;    /* must be 0 */
+} lbm_sc_group_launch;
+
+/* Create an empty group that enqueues on `stream` (a hipStream_t, required: the boxes of the
+ * group must have been created with this same stream). */
+int lbm_sc_group_create(void* stream, lbm_sc_group** out);
+
+/* Set the boxes stepped by the group (nbox >= 0; an empty group steps nothing). Validates that
+ * every box has the group's stream and that all share one precision (LBM_SC_EINVAL otherwise),
+ * builds the work list for the current launch shape and uploads it (stream-ordered). */
+int lbm_sc_group_set(lbm_sc_group* g, lbm_sc* const* boxes, int32_t nbox);
+
+/* Enqueue nsteps (>= 0) time steps of every box of the group: one multi-box launch per step,
+ * replayed from a captured hipGraph in chunks of graph_steps. Each box's step counter advances by
+ * nsteps. Asynchronous. */
+int lbm_sc_group_step(lbm_sc_group* g, int64_t nsteps);
+
+/* Set / read the group's launch shape (the work list is rebuilt; results are unchanged). */
+int lbm_sc_group_set_launch(lbm_sc_group* g, const lbm_sc_group_launch* launch);
+int lbm_sc_group_get_launch(lbm_sc_group* g, lbm_sc_group_launch* out);
+
+/* Number of boxes, work items, nodes and algorithmic HBM bytes of one group step. */
+int lbm_sc_group_info(lbm_sc_group* g, int32_t* nbox, int64_t* items, int64_t* nodes,
+                      int64_t* bytes_per_step);
+
+/* Release the group (after waiting for its stream); the boxes are untouched. NULL is ignored. */
+void lbm_sc_group_destroy(lbm_sc_group* g);
+
 /* Measurement helper, not part of the method: copy `bytes` (a multiple of 16; src and dst
  * 16-byte aligned device pointers that do not overlap) with a plain streaming kernel on `stream`
  * (hipStream_t or NULL for the null stream). Asynchronous. It measures the achievable HBM

@@ -64,6 +64,14 @@ class LbmScLaunch(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class LbmScGroupLaunch(ctypes.Structure):
+    _fields_ = [("rows", _i32), ("z_chunk", _i32), ("xcd_remap", _i32), ("prefetch", _i32),
+                ("persistent", _i32), ("workers", _i32), ("graph_steps", _i32), ("reserved", _i32)]
+
+    def to_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+
+
 class LbmScError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"lbm_sc error {code}: {msg}")
@@ -73,7 +81,9 @@ class LbmScError(RuntimeError):
 EXPORTS = ("lbm_sc_create", "lbm_sc_step", "lbm_sc_sync", "lbm_sc_observables",
            "lbm_sc_get_populations", "lbm_sc_set_populations", "lbm_sc_set_launch",
            "lbm_sc_get_launch", "lbm_sc_stream_copy", "lbm_sc_get_info", "lbm_sc_destroy",
-           "lbm_sc_last_error", "lbm_sc_gc", "lbm_sc_coexistence")
+           "lbm_sc_last_error", "lbm_sc_gc", "lbm_sc_coexistence", "lbm_sc_group_create",
+           "lbm_sc_group_set", "lbm_sc_group_step", "lbm_sc_group_set_launch",
+           "lbm_sc_group_get_launch", "lbm_sc_group_info", "lbm_sc_group_destroy")
 
 _lib = None
 
@@ -106,8 +116,17 @@ def load():
     L.lbm_sc_gc.argtypes = [_i32]
     L.lbm_sc_gc.restype = _f64
     L.lbm_sc_coexistence.argtypes = [_i32, _f64, P(_f64), P(_f64), P(_f64)]
+    L.lbm_sc_group_create.argtypes = [_vp, P(_vp)]
+    L.lbm_sc_group_set.argtypes = [_vp, P(_vp), _i32]
+    L.lbm_sc_group_step.argtypes = [_vp, _i64]
+    L.lbm_sc_group_set_launch.argtypes = [_vp, P(LbmScGroupLaunch)]
+    L.lbm_sc_group_get_launch.argtypes = [_vp, P(LbmScGroupLaunch)]
+    L.lbm_sc_group_info.argtypes = [_vp, P(_i32), P(_i64), P(_i64), P(_i64)]
+    L.lbm_sc_group_destroy.argtypes = [_vp]
+    L.lbm_sc_group_destroy.restype = None
     for name in EXPORTS:
-        if name not in ("lbm_sc_destroy", "lbm_sc_last_error", "lbm_sc_gc"):
+        if name not in ("lbm_sc_destroy", "lbm_sc_last_error", "lbm_sc_gc",
+                        "lbm_sc_group_destroy"):
             getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -255,6 +274,89 @@ class Box:
         if self.h is not None:
             lbm_sc_destroy(self.h)
             self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def lbm_sc_group_create(stream):
+    g = _vp()
+    _check(load().lbm_sc_group_create(stream, ctypes.byref(g)))
+    return g
+
+
+def lbm_sc_group_set(g, handles):
+    arr = (_vp * max(len(handles), 1))(*[h.value for h in handles])
+    _check(load().lbm_sc_group_set(g, arr, len(handles)))
+
+
+def lbm_sc_group_step(g, nsteps):
+    _check(load().lbm_sc_group_step(g, int(nsteps)))
+
+
+def lbm_sc_group_get_launch(g):
+    l = LbmScGroupLaunch()
+    _check(load().lbm_sc_group_get_launch(g, ctypes.byref(l)))
+    return l.to_dict()
+
+
+def lbm_sc_group_set_launch(g, **kw):
+    cur = lbm_sc_group_get_launch(g)
+    cur.update(kw)
+    l = LbmScGroupLaunch(**cur)
+    _check(load().lbm_sc_group_set_launch(g, ctypes.byref(l)))
+
+
+def lbm_sc_group_info(g):
+    nb, it, nn, bb = _i32(), _i64(), _i64(), _i64()
+    _check(load().lbm_sc_group_info(g, ctypes.byref(nb), ctypes.byref(it), ctypes.byref(nn),
+                                    ctypes.byref(bb)))
+    return dict(nbox=nb.value, items=it.value, nodes=nn.value, bytes_per_step=bb.value)
+
+
+def lbm_sc_group_destroy(g):
+    if g is not None and g.value:
+        load().lbm_sc_group_destroy(g)
+
+
+class Group:
+    """Owner of one lbm_sc_group handle. `stream` is a hipStream_t (int); the boxes added must
+    have been created with the same stream."""
+
+    def __init__(self, stream):
+        self.stream = stream
+        self.g = lbm_sc_group_create(stream)
+        self.boxes = []
+
+    def set(self, boxes):
+        lbm_sc_group_set(self.g, [b.h for b in boxes])
+        self.boxes = list(boxes)
+
+    def step(self, n):
+        lbm_sc_group_step(self.g, n)
+
+    def set_launch(self, **kw):
+        lbm_sc_group_set_launch(self.g, **kw)
+
+    def launch(self):
+        return lbm_sc_group_get_launch(self.g)
+
+    def info(self):
+        return lbm_sc_group_info(self.g)
+
+    def close(self):
+        if self.g is not None:
+            lbm_sc_group_destroy(self.g)
+            self.g = None
 
     def __del__(self):
         try:

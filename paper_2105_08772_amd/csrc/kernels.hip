@@ -23,8 +23,6 @@ namespace lbm {
 namespace {
 
 constexpr int BX = 64;       // tile width = one wave64 row
-constexpr int NT = 256;      // threads per workgroup
-constexpr int NWAVE = NT / 64;
 
 __device__ __forceinline__ int wrapi(int v, int L)
 {
@@ -131,7 +129,6 @@ __device__ __forceinline__ void static_for(F&& f)
 struct StepArgs {
     BoxDesc b;
     int tiles_x, tiles_y, nchunks, zc, remap;
-    double inv_tau, guo_pref;
 };
 
 // Pull the 19 pre-collision populations of one node and reduce them to (sum g, j). Byte offsets
@@ -221,33 +218,38 @@ __device__ __forceinline__ void collide_store(const PopBuf& dst, unsigned off, T
     bstore<T, 0>(dst, off, (T)(dn64 - sum));
 }
 
-template <typename T, int PSI, bool TAU1, int R, bool PF>
-__global__ __launch_bounds__(NT) void k_step(StepArgs a, const T* __restrict__ src,
-                                             T* __restrict__ dst)
+// LDS ring of four psi planes of a (64 + 2) x (4*rows... ) tile, shared by the single-box and
+// the multi-box kernels.
+template <typename T, int R, int WAVES>
+struct Ring {
+    static constexpr int BY = WAVES * R;
+    static constexpr int LX = BX + 2, LY = BY + 2;
+    T v[4][LY][LX];
+};
+
+// One workgroup's share of a step: the tile (tix, tiy) of box b, planes [z0, z1). The caller
+// provides the LDS ring; the routine ends with every thread past its last read of the ring.
+template <typename T, int PSI, bool TAU1, int R, bool PF, int WAVES>
+__device__ __forceinline__ void step_tile(const BoxDesc& bd, const T* __restrict__ src,
+                                          T* __restrict__ dst, int tix, int tiy, int z0, int z1,
+                                          Ring<T, R, WAVES>& rg)
 {
-    constexpr int BY = NWAVE * R;
-    constexpr int LX = BX + 2, LY = BY + 2;
+    constexpr int NT = 64 * WAVES;
+    constexpr int BY = WAVES * R;
+    constexpr int LX = BX + 2;
     constexpr int NH = 2 * LX + 2 * BY;
     static_assert(NH <= NT, "halo ring larger than the workgroup");
-    __shared__ T ring[4][LY][LX];
+    auto& ring = rg.v;
 
-    const int nx = a.b.nx, ny = a.b.ny, nz = a.b.nz;
-    const unsigned nxy = a.b.nxy;
-    const PopBuf sbuf = make_popbuf(src, a.b.stride);
-    const PopBuf dbuf = make_popbuf(dst, a.b.stride);
-    const T rho_ref = (T)a.b.rho_ref;
-    const T G = (T)a.b.G;
-    const T inv_tau = (T)a.inv_tau;
-    const T guo_pref = (T)a.guo_pref;
-
-    const unsigned logical = a.remap ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
-    const int tix = (int)(logical % (unsigned)a.tiles_x);
-    const unsigned t2 = logical / (unsigned)a.tiles_x;
-    const int tiy = (int)(t2 % (unsigned)a.tiles_y);
-    const int ch = (int)(t2 / (unsigned)a.tiles_y);
+    const int nx = bd.nx, ny = bd.ny, nz = bd.nz;
+    const unsigned nxy = bd.nxy;
+    const PopBuf sbuf = make_popbuf(src, bd.stride);
+    const PopBuf dbuf = make_popbuf(dst, bd.stride);
+    const T rho_ref = (T)bd.rho_ref;
+    const T G = (T)bd.G;
+    const T inv_tau = (T)(1.0 / bd.tau);
+    const T guo_pref = (T)(1.0 - 0.5 / bd.tau);
     const int x0 = tix * BX, y0 = tiy * BY;
-    const int z0 = ch * a.zc;
-    const int z1 = min(z0 + a.zc, nz);
 
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
@@ -404,11 +406,109 @@ __global__ __launch_bounds__(NT) void k_step(StepArgs a, const T* __restrict__ s
     }
 }
 
+template <typename T, int PSI, bool TAU1, int R, bool PF, int WAVES = 4>
+__global__ __launch_bounds__(64 * WAVES) void k_step(StepArgs a, const T* __restrict__ src,
+                                                     T* __restrict__ dst)
+{
+    __shared__ Ring<T, R, WAVES> ring;
+    const unsigned logical = a.remap ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
+    const int tix = (int)(logical % (unsigned)a.tiles_x);
+    const unsigned t2 = logical / (unsigned)a.tiles_x;
+    const int tiy = (int)(t2 % (unsigned)a.tiles_y);
+    const int ch = (int)(t2 / (unsigned)a.tiles_y);
+    const int z0 = ch * a.zc;
+    const int z1 = min(z0 + a.zc, a.b.nz);
+    step_tile<T, PSI, TAU1, R, PF, WAVES>(a.b, src, dst, tix, tiy, z0, z1, ring);
+}
+
+// ------------------------------------------------------------------------------------------
+// Multi-box step: one launch advances every box of a group by one time step. Work items are
+// (box, tile, z chunk) in box-major order; item_begin[b] is the first item of box b. Each box
+// has its own size, psi, tau, G, rho_ref, population buffers and chunk length; the launch shape
+// (rows, prefetch) is shared. Box b reads pop[(phase_b + parity) & 1] and writes the other.
+// ------------------------------------------------------------------------------------------
+
+template <typename T, int R, bool PF, int WAVES>
+__device__ __forceinline__ void group_item(const GroupBox* __restrict__ boxes, int nbox,
+                                           unsigned item, int parity, Ring<T, R, WAVES>& ring)
+{
+    // box of the item: last box whose first item is <= item
+    int lo = 0, hi = nbox - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (boxes[mid].item_begin <= item) lo = mid;
+        else hi = mid - 1;
+    }
+    const GroupBox& g = boxes[lo];
+    const unsigned local = item - g.item_begin;
+    const int tix = (int)(local % (unsigned)g.tiles_x);
+    const unsigned t2 = local / (unsigned)g.tiles_x;
+    const int tiy = (int)(t2 % (unsigned)g.tiles_y);
+    const int ch = (int)(t2 / (unsigned)g.tiles_y);
+    const int z0 = ch * g.zc;
+    const int z1 = min(z0 + g.zc, g.b.nz);
+    const int s = (g.phase + parity) & 1;
+    const T* src = (const T*)g.pop[s];
+    T* dst = (T*)g.pop[1 - s];
+    const bool tau1 = g.b.tau == 1.0;
+    if (g.b.psi == 0) {
+        if (tau1) step_tile<T, 0, true, R, PF, WAVES>(g.b, src, dst, tix, tiy, z0, z1, ring);
+        else step_tile<T, 0, false, R, PF, WAVES>(g.b, src, dst, tix, tiy, z0, z1, ring);
+    } else {
+        if (tau1) step_tile<T, 1, true, R, PF, WAVES>(g.b, src, dst, tix, tiy, z0, z1, ring);
+        else step_tile<T, 1, false, R, PF, WAVES>(g.b, src, dst, tix, tiy, z0, z1, ring);
+    }
+}
+
+// One workgroup per work item (the hardware dispatcher balances the uneven items).
+template <typename T, int R, bool PF, int WAVES = 4>
+__global__ __launch_bounds__(64 * WAVES) void k_step_group(const GroupBox* __restrict__ boxes,
+                                                           int nbox, int parity, int remap)
+{
+    __shared__ Ring<T, R, WAVES> ring;
+    const unsigned item = remap ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
+    group_item<T, R, PF, WAVES>(boxes, nbox, item, parity, ring);
+}
+
+// Persistent variant: a fixed grid whose workgroups take items from eight work queues, one per
+// XCD (workgroup w runs on XCD w mod 8 and serves queue w mod 8, so the items of a queue - a
+// contiguous, work-balanced run of the box-major list - share that XCD's L2). Every workgroup
+// draws tickets until its queue is exhausted; the last workgroup to finish clears the queues and
+// the finish counter for the next launch, so the kernel needs no host-side reset and can be
+// replayed from a captured graph.
+template <typename T, int R, bool PF, int WAVES = 4>
+__global__ __launch_bounds__(64 * WAVES) void k_step_group_persistent(
+    const GroupBox* __restrict__ boxes, int nbox, int parity, QueueState* __restrict__ q)
+{
+    __shared__ Ring<T, R, WAVES> ring;
+    __shared__ unsigned ticket;
+    const unsigned xcd = blockIdx.x % 8u;
+    const unsigned begin = q->range[xcd], end = q->range[xcd + 1];
+    for (;;) {
+        if (threadIdx.x == 0) ticket = begin + atomicAdd(&q->next[xcd], 1u);
+        __syncthreads();
+        const unsigned item = ticket;
+        __syncthreads();
+        if (item >= end) break;
+        group_item<T, R, PF, WAVES>(boxes, nbox, item, parity, ring);
+        __syncthreads();  // the next item rewrites the LDS ring
+    }
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const unsigned done = atomicAdd(&q->done, 1u);
+        if (done == gridDim.x - 1) {
+            for (int k = 0; k < 8; ++k) atomicExch(&q->next[k], 0u);
+            atomicExch(&q->done, 0u);
+            __threadfence();
+        }
+    }
+}
+
 template <typename T, int PSI, bool TAU1, int R, bool PF>
 hipError_t launch_step_t(const StepArgs& a, const void* src, void* dst, hipStream_t st)
 {
     const unsigned grid = (unsigned)(a.tiles_x * a.tiles_y * a.nchunks);
-    hipLaunchKernelGGL((k_step<T, PSI, TAU1, R, PF>), dim3(grid), dim3(NT), 0, st, a,
+    hipLaunchKernelGGL((k_step<T, PSI, TAU1, R, PF, 4>), dim3(grid), dim3(256), 0, st, a,
                        (const T*)src, (T*)dst);
     return hipGetLastError();
 }
@@ -848,15 +948,58 @@ hipError_t launch_step(bool fp32, const BoxDesc& b, const StepShape& s, const vo
     StepArgs a;
     a.b = b;
     a.tiles_x = (b.nx + BX - 1) / BX;
-    const int by = NWAVE * s.rows;
+    const int by = 4 * s.rows;
     a.tiles_y = (b.ny + by - 1) / by;
     a.zc = s.z_chunk < b.nz ? s.z_chunk : b.nz;
     a.nchunks = (b.nz + a.zc - 1) / a.zc;
     a.remap = s.xcd_remap;
-    a.inv_tau = 1.0 / b.tau;
-    a.guo_pref = 1.0 - 0.5 / b.tau;
     return fp32 ? dispatch_step<float>(s, a, src, dst, st)
                 : dispatch_step<double>(s, a, src, dst, st);
+}
+
+template <typename T, int R, bool PF>
+hipError_t launch_group_t(const GroupBox* boxes, int nbox, unsigned nitems, int parity,
+                          int persistent, int remap, unsigned workers, QueueState* q,
+                          hipStream_t st)
+{
+    if (persistent)
+        hipLaunchKernelGGL((k_step_group_persistent<T, R, PF, 4>), dim3(workers), dim3(256), 0, st,
+                           boxes, nbox, parity, q);
+    else
+        hipLaunchKernelGGL((k_step_group<T, R, PF, 4>), dim3(nitems), dim3(256), 0, st, boxes, nbox,
+                           parity, remap);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_group_rows(const StepShape& s, const GroupBox* boxes, int nbox, unsigned nitems,
+                             int parity, int persistent, unsigned workers, QueueState* q,
+                             hipStream_t st)
+{
+    const int r = s.xcd_remap;
+    if (s.prefetch) {
+        switch (s.rows) {
+            case 1: return launch_group_t<T, 1, true>(boxes, nbox, nitems, parity, persistent, r, workers, q, st);
+            case 2: return launch_group_t<T, 2, true>(boxes, nbox, nitems, parity, persistent, r, workers, q, st);
+            case 4: return launch_group_t<T, 4, true>(boxes, nbox, nitems, parity, persistent, r, workers, q, st);
+        }
+    } else {
+        switch (s.rows) {
+            case 1: return launch_group_t<T, 1, false>(boxes, nbox, nitems, parity, persistent, r, workers, q, st);
+            case 2: return launch_group_t<T, 2, false>(boxes, nbox, nitems, parity, persistent, r, workers, q, st);
+            case 4: return launch_group_t<T, 4, false>(boxes, nbox, nitems, parity, persistent, r, workers, q, st);
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_step_group(bool fp32, const StepShape& s, const GroupBox* boxes, int nbox,
+                             unsigned nitems, int parity, int persistent, unsigned workers,
+                             QueueState* q, hipStream_t st)
+{
+    if (nbox <= 0 || nitems == 0) return hipSuccess;
+    return fp32 ? launch_group_rows<float>(s, boxes, nbox, nitems, parity, persistent, workers, q, st)
+                : launch_group_rows<double>(s, boxes, nbox, nitems, parity, persistent, workers, q, st);
 }
 
 hipError_t launch_init(bool fp32, const BoxDesc& b, const InitDesc& d, double* dn, double* dpsi,

@@ -27,6 +27,24 @@ struct StepShape {
     int prefetch;    // 1: issue the next plane's loads before the barrier (software pipelining)
 };
 
+// One box of a multi-box step.
+struct GroupBox {
+    BoxDesc b;
+    const void* pop[2];     // the box's two population buffers
+    int phase;              // pop[phase] holds the box's current state when the group's step
+                            // counter is even
+    int tiles_x, tiles_y, zc;
+    unsigned item_begin;    // first work item of the box
+    unsigned items;         // tiles_x * tiles_y * ceil(nz / zc)
+};
+
+// Work queues of the persistent multi-box kernel (device memory, zero-initialised once).
+struct QueueState {
+    unsigned next[8];       // next ticket of each XCD's queue
+    unsigned done;          // workgroups finished in the current launch
+    unsigned range[9];      // queue x serves items [range[x], range[x+1])
+};
+
 struct InitDesc {
     int geom;            // 0 droplet, 1 bubble, 2 slab
     int slab_axis;
@@ -44,6 +62,10 @@ constexpr int OBS_BLOCKS = 512;
 
 hipError_t launch_step(bool fp32, const BoxDesc& b, const StepShape& s, const void* src, void* dst,
                        hipStream_t st);
+// Multi-box step. nitems work items; persistent: grid of `workers` workgroups over the queues.
+hipError_t launch_step_group(bool fp32, const StepShape& s, const GroupBox* boxes, int nbox,
+                             unsigned nitems, int parity, int persistent, unsigned workers,
+                             QueueState* q, hipStream_t st);
 hipError_t launch_init(bool fp32, const BoxDesc& b, const InitDesc& d, double* dn, double* dpsi,
                        void* dst, hipStream_t st);
 hipError_t launch_get(bool fp32, const BoxDesc& b, int i, const void* src, double* out,

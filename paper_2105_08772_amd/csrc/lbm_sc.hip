@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstdint>
+#include <algorithm>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -627,5 +628,272 @@ int lbm_sc_stream_copy(const void* src, void* dst, size_t bytes, void* stream)
 }
 
 void lbm_sc_destroy(lbm_sc* h) { release(h); }
+
+}  // extern "C"
+
+// ------------------------------------------------------------------------------------------
+// Groups
+// ------------------------------------------------------------------------------------------
+
+struct lbm_sc_group {
+    hipStream_t stream = nullptr;
+    std::vector<lbm_sc*> boxes;
+    std::vector<lbm::GroupBox> desc;
+    lbm::GroupBox* d_desc = nullptr;
+    size_t d_desc_cap = 0;
+    lbm::QueueState* d_queue = nullptr;
+    lbm_sc_group_launch launch;
+    bool fp32 = false;
+    unsigned nitems = 0;
+    int64_t nodes = 0;
+    int64_t bytes_per_step = 0;
+    bool dirty = true;            // work list must be rebuilt and uploaded
+    int par = 0;                  // steps since the last rebuild, mod 2 (kernel parity)
+    hipGraphExec_t graph = nullptr;
+    int graph_len = 0;
+};
+
+namespace {
+
+void drop_graph(lbm_sc_group* g)
+{
+    if (g->graph) (void)hipGraphExecDestroy(g->graph);
+    g->graph = nullptr;
+    g->graph_len = 0;
+}
+
+// Build the work list and queue ranges for the current boxes and launch shape, and upload them.
+// Phases align every box's current buffer with parity 0.
+int group_rebuild(lbm_sc_group* g)
+{
+    const lbm_sc_group_launch& L = g->launch;
+    g->desc.clear();
+    g->nitems = 0;
+    g->nodes = 0;
+    g->bytes_per_step = 0;
+    std::vector<double> work;   // nodes per item, box-major
+    const int by = 4 * L.rows;
+    for (lbm_sc* h : g->boxes) {
+        lbm::GroupBox d;
+        std::memset(&d, 0, sizeof(d));
+        d.b = h->box;
+        d.pop[0] = h->pop[0];
+        d.pop[1] = h->pop[1];
+        d.phase = h->cur;
+        d.tiles_x = (h->box.nx + 63) / 64;
+        d.tiles_y = (h->box.ny + by - 1) / by;
+        d.zc = L.z_chunk < h->box.nz ? L.z_chunk : h->box.nz;
+        const unsigned nch = (unsigned)((h->box.nz + d.zc - 1) / d.zc);
+        d.item_begin = g->nitems;
+        d.items = (unsigned)d.tiles_x * (unsigned)d.tiles_y * nch;
+        for (unsigned it = 0; it < d.items; ++it) {
+            const unsigned tix = it % d.tiles_x, t2 = it / d.tiles_x;
+            const unsigned tiy = t2 % d.tiles_y, ch = t2 / d.tiles_y;
+            const int w = std::min(64, h->box.nx - (int)tix * 64);
+            const int hgt = std::min(by, h->box.ny - (int)tiy * by);
+            const int dz = std::min(d.zc, h->box.nz - (int)ch * d.zc);
+            work.push_back((double)std::max(w, 1) * std::max(hgt, 1) * std::max(dz, 1));
+        }
+        g->nitems += d.items;
+        g->nodes += (int64_t)h->box.n;
+        g->bytes_per_step += (int64_t)2 * 19 * (int64_t)h->elem * (int64_t)h->box.n;
+        g->desc.push_back(d);
+    }
+    if (!g->desc.empty()) {
+        const size_t bytes = g->desc.size() * sizeof(lbm::GroupBox);
+        if (bytes > g->d_desc_cap) {
+            if (g->d_desc) (void)hipFree(g->d_desc);
+            g->d_desc = nullptr;
+            g->d_desc_cap = 0;
+            hipError_t e = hipMalloc((void**)&g->d_desc, bytes);
+            if (e != hipSuccess) return fail(LBM_SC_ENOMEM, "group descriptor allocation failed");
+            g->d_desc_cap = bytes;
+        }
+        HIP_TRY(hipMemcpyAsync(g->d_desc, g->desc.data(), bytes, hipMemcpyHostToDevice, g->stream));
+    }
+    // eight contiguous, work-balanced queue ranges
+    lbm::QueueState q;
+    std::memset(&q, 0, sizeof(q));
+    double total = 0.0;
+    for (double w : work) total += w;
+    unsigned k = 0;
+    double acc = 0.0;
+    q.range[0] = 0;
+    for (int x = 1; x < 8; ++x) {
+        const double target = total * x / 8.0;
+        while (k < g->nitems && acc + 0.5 * work[k] < target) acc += work[k++];
+        q.range[x] = k;
+    }
+    q.range[8] = g->nitems;
+    HIP_TRY(hipMemcpyAsync(g->d_queue, &q, sizeof(q), hipMemcpyHostToDevice, g->stream));
+    // the queue state is read by later launches: keep the host copy alive until it has landed
+    HIP_TRY(hipStreamSynchronize(g->stream));
+    drop_graph(g);
+    g->dirty = false;
+    g->par = 0;
+    return LBM_SC_OK;
+}
+
+hipError_t group_launch(lbm_sc_group* g, int parity)
+{
+    lbm::StepShape s;
+    s.rows = g->launch.rows;
+    s.z_chunk = g->launch.z_chunk;
+    s.xcd_remap = g->launch.xcd_remap;
+    s.prefetch = g->launch.prefetch;
+    const unsigned workers = g->launch.workers ? (unsigned)g->launch.workers : 256u;
+    return lbm::launch_step_group(g->fp32, s, g->d_desc, (int)g->desc.size(), g->nitems, parity,
+                                  g->launch.persistent, workers, g->d_queue, g->stream);
+}
+
+int check_group_launch(const lbm_sc_group_launch* l)
+{
+    if (l->rows != 1 && l->rows != 2 && l->rows != 4) return fail(LBM_SC_EINVAL, "rows must be 1, 2 or 4");
+    if (l->z_chunk < 1) return fail(LBM_SC_EINVAL, "z_chunk must be >= 1");
+    if ((l->xcd_remap | l->prefetch | l->persistent) & ~1) return fail(LBM_SC_EINVAL, "flags must be 0 or 1");
+    if (l->workers < 0 || l->workers % 8 || l->workers > 65536)
+        return fail(LBM_SC_EINVAL, "workers must be a multiple of 8 in [0, 65536]");
+    if (l->graph_steps < 0 || l->graph_steps % 2 || l->graph_steps > 4096)
+        return fail(LBM_SC_EINVAL, "graph_steps must be even, in [0, 4096]");
+    if (l->reserved != 0) return fail(LBM_SC_EINVAL, "reserved must be 0");
+    return LBM_SC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_sc_group_create(void* stream, lbm_sc_group** out)
+{
+    if (!out) return fail(LBM_SC_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!stream) return fail(LBM_SC_EINVAL, "a group needs an explicit stream");
+    lbm_sc_group* g = new (std::nothrow) lbm_sc_group();
+    if (!g) return fail(LBM_SC_ENOMEM, "host allocation failed");
+    g->stream = (hipStream_t)stream;
+    g->launch = {2, 32, 1, 1, 0, 0, 64, 0};
+    hipError_t e = hipMalloc((void**)&g->d_queue, sizeof(lbm::QueueState));
+    if (e != hipSuccess) {
+        delete g;
+        return fail(LBM_SC_ENOMEM, "queue allocation failed");
+    }
+    e = hipMemsetAsync(g->d_queue, 0, sizeof(lbm::QueueState), g->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+    if (e != hipSuccess) {
+        (void)hipFree(g->d_queue);
+        delete g;
+        return fail_hip("hipMemsetAsync", e);
+    }
+    *out = g;
+    return LBM_SC_OK;
+}
+
+int lbm_sc_group_set(lbm_sc_group* g, lbm_sc* const* boxes, int32_t nbox)
+{
+    if (!g) return fail(LBM_SC_EINVAL, "group is NULL");
+    if (nbox < 0 || (nbox > 0 && !boxes)) return fail(LBM_SC_EINVAL, "bad box list");
+    for (int i = 0; i < nbox; ++i) {
+        if (!boxes[i]) return fail(LBM_SC_EINVAL, "box " + std::to_string(i) + " is NULL");
+        if (boxes[i]->stream != g->stream)
+            return fail(LBM_SC_EINVAL, "box " + std::to_string(i) + " was not created on the group's stream");
+        if (boxes[i]->fp32 != boxes[0]->fp32)
+            return fail(LBM_SC_EINVAL, "all boxes of a group must share one precision");
+        for (int j = 0; j < i; ++j)
+            if (boxes[j] == boxes[i]) return fail(LBM_SC_EINVAL, "a box appears twice");
+    }
+    g->boxes.assign(boxes, boxes + nbox);
+    g->fp32 = nbox > 0 && boxes[0]->fp32;
+    return group_rebuild(g);
+}
+
+int lbm_sc_group_step(lbm_sc_group* g, int64_t nsteps)
+{
+    if (!g) return fail(LBM_SC_EINVAL, "group is NULL");
+    if (nsteps < 0) return fail(LBM_SC_EINVAL, "nsteps must be >= 0");
+    if (g->boxes.empty() || nsteps == 0) return LBM_SC_OK;
+    // a box stepped alone since the last call is out of phase with the work list: rebuild
+    for (size_t i = 0; i < g->boxes.size(); ++i)
+        if (((g->desc[i].phase + g->par) & 1) != g->boxes[i]->cur) g->dirty = true;
+    if (g->dirty) {
+        int rc = group_rebuild(g);
+        if (rc) return rc;
+    }
+    const int K = g->launch.graph_steps;
+    if (K > 0 && nsteps >= K && (!g->graph || g->graph_len != K)) {
+        // capture K launches with parities 0, 1, ..., replayed whenever the parity is 0
+        drop_graph(g);
+        hipGraph_t graph = nullptr;
+        HIP_TRY(hipStreamBeginCapture(g->stream, hipStreamCaptureModeThreadLocal));
+        hipError_t le = hipSuccess;
+        for (int k = 0; k < K && le == hipSuccess; ++k) le = group_launch(g, k & 1);
+        hipError_t ce = hipStreamEndCapture(g->stream, &graph);
+        if (le != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return fail_hip("group launch during capture", le);
+        }
+        if (ce != hipSuccess) return fail_hip("hipStreamEndCapture", ce);
+        hipError_t ie = hipGraphInstantiate(&g->graph, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ie != hipSuccess) {
+            g->graph = nullptr;
+            return fail_hip("hipGraphInstantiate", ie);
+        }
+        g->graph_len = K;
+    }
+    int64_t done = 0;
+    while (done < nsteps) {
+        if (g->graph && g->par == 0 && nsteps - done >= g->graph_len) {
+            HIP_TRY(hipGraphLaunch(g->graph, g->stream));
+            done += g->graph_len;
+        } else {
+            HIP_TRY(group_launch(g, g->par));
+            g->par ^= 1;
+            ++done;
+        }
+    }
+    for (size_t i = 0; i < g->boxes.size(); ++i) {
+        lbm_sc* h = g->boxes[i];
+        h->cur = (g->desc[i].phase + g->par) & 1;
+        h->step += nsteps;
+    }
+    return LBM_SC_OK;
+}
+
+int lbm_sc_group_set_launch(lbm_sc_group* g, const lbm_sc_group_launch* l)
+{
+    if (!g || !l) return fail(LBM_SC_EINVAL, "group or launch is NULL");
+    int rc = check_group_launch(l);
+    if (rc) return rc;
+    g->launch = *l;
+    return group_rebuild(g);
+}
+
+int lbm_sc_group_get_launch(lbm_sc_group* g, lbm_sc_group_launch* out)
+{
+    if (!g || !out) return fail(LBM_SC_EINVAL, "group or out is NULL");
+    *out = g->launch;
+    return LBM_SC_OK;
+}
+
+int lbm_sc_group_info(lbm_sc_group* g, int32_t* nbox, int64_t* items, int64_t* nodes,
+                      int64_t* bytes_per_step)
+{
+    if (!g) return fail(LBM_SC_EINVAL, "group is NULL");
+    if (nbox) *nbox = (int32_t)g->boxes.size();
+    if (items) *items = g->nitems;
+    if (nodes) *nodes = g->nodes;
+    if (bytes_per_step) *bytes_per_step = g->bytes_per_step;
+    return LBM_SC_OK;
+}
+
+void lbm_sc_group_destroy(lbm_sc_group* g)
+{
+    if (!g) return;
+    (void)hipStreamSynchronize(g->stream);
+    drop_graph(g);
+    if (g->d_desc) (void)hipFree(g->d_desc);
+    if (g->d_queue) (void)hipFree(g->d_queue);
+    delete g;
+}
 
 }  // extern "C"

@@ -74,7 +74,8 @@ def test_ctypes_structs_match_the_c_layout(tmp_path):
     with the ctypes mirrors of the Python binding."""
     import subprocess
     structs = {"lbm_sc_config": lbm.LbmScConfig, "lbm_sc_obs": lbm.LbmScObs,
-               "lbm_sc_info": lbm.LbmScInfo, "lbm_sc_launch": lbm.LbmScLaunch}
+               "lbm_sc_info": lbm.LbmScInfo, "lbm_sc_launch": lbm.LbmScLaunch,
+               "lbm_sc_group_launch": lbm.LbmScGroupLaunch}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "lbm_sc.h"', 'int main(void){']
     for cname, py in structs.items():
         lines.append(f'printf("{cname} sizeof %zu\\n", sizeof({cname}));')
