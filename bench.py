@@ -78,6 +78,102 @@ def stream_copy_gbps(torch, lbm, stream, nbytes=2 << 30, reps=20):
     return out
 
 
+def run_batched(args, torch, lbm, stream, steps, log):
+    """The batched workload: 64 cubic boxes (L ~ U{48..160}, R ~ U[0.15, 0.35] L, G/G_c ~
+    U[1.05, 1.8], droplet or bubble, exp psi, FP32-shifted, tanh width 2, noise 1e-6), seeded
+    2105, advanced together by one multi-box launch per step with an autotuned launch shape and
+    FP64 observations of every box every 2048 steps. Compared with the plain single-box FP64
+    path on a subset of the same boxes (throughput and dP after the same number of steps)."""
+    from tests import inputs
+    from paper_2105_08772_amd import tune
+    spec = inputs.batched_boxes()
+
+    def cfg(b, prec, st):
+        return lbm.config(b["L"], psi=lbm.LBM_SC_PSI_EXP,
+                          geom=lbm.LBM_SC_BUBBLE if b["bubble"] else lbm.LBM_SC_DROPLET,
+                          prec=prec, tau=1.0, g_over_gc=b["g_over_gc"], radius=b["radius"],
+                          width=2.0, noise_amp=1e-6, seed=b["seed"], stream=st)
+
+    boxes = [lbm.Box(cfg(b, lbm.LBM_SC_FP32_SHIFTED, stream.cuda_stream)) for b in spec]
+    group = lbm.Group(stream.cuda_stream)
+    group.set(boxes)
+    ginfo = group.info()
+    log(f"# batched: {len(boxes)} boxes, {ginfo['nodes'] / 1e6:.1f} M nodes, tuning")
+    best = tune.tune_group(group, steps=8)
+    group.set_launch(graph_steps=64)
+    log(f"# batched: tuned {best}")
+    # timed: `steps` steps of all boxes, FP64 observation of every box every 2048 steps
+    for b in boxes:
+        b.observables(profile=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = 0
+    while done < steps:
+        n = min(2048 - done % 2048, steps - done)
+        group.step(n)
+        done += n
+        if done % 2048 == 0:
+            for b in boxes:
+                b.observables(profile=False, raise_unstable=False)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    # kernel time of one group step (graph replays, no observations)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    group.step(128)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_step = e0.elapsed_time(e1) / 1e3 / 128
+    obs32 = [b.observables(profile=False, raise_unstable=False)[0] for b in boxes]
+    steps_done = boxes[0].observables(profile=False, raise_unstable=False)[0]["step"]
+    unstable = sum(1 for o in obs32 if not o["finite"])
+    # plain single-box FP64 path on a subset, same number of steps from the same initial state
+    subset = list(range(0, len(spec), 16))
+    fp64 = []
+    fp64_time = 0.0
+    fp64_nodes = 0
+    for k in subset:
+        with lbm.Box(cfg(spec[k], lbm.LBM_SC_FP64, stream.cuda_stream)) as b64:
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            b64.step(steps_done)
+            torch.cuda.synchronize()
+            fp64_time += time.perf_counter() - t1
+            fp64_nodes += spec[k]["L"] ** 3
+            fp64.append(b64.observables(profile=False, raise_unstable=False)[0])
+    dP_err = [abs(obs32[k]["dP"] - o["dP"]) / abs(o["dP"]) for k, o in zip(subset, fp64)
+              if o["finite"] and obs32[k]["finite"] and o["dP"] != 0]
+    group.close()
+    for b in boxes:
+        b.close()
+    torch.cuda.empty_cache()
+    total_nodes = ginfo["nodes"]
+    mlups = total_nodes * steps / wall / 1e6
+    mlups64 = fp64_nodes * steps_done / fp64_time / 1e6
+    solve_steps = 20000
+    return {
+        "workload": "64 boxes L~U{48..160}, R~U[0.15,0.35]L, G/G_c~U[1.05,1.8], droplet/bubble, "
+                    "exp psi, FP32-shifted, seed 2105, one multi-box launch per step, FP64 "
+                    "observations every 2048 steps",
+        "boxes": len(boxes), "nodes": total_nodes, "steps": steps, "seconds": round(wall, 3),
+        "MLUPS": round(mlups, 1),
+        "droplets_per_hour": round(len(boxes) * 3600.0 / (wall * solve_steps / steps), 1),
+        "kernel_ms_per_step": round(t_step * 1e3, 4),
+        "kernel_GBps": round(ginfo["bytes_per_step"] / t_step / 1e9, 1),
+        "kernel_frac_of_8TBps": round(ginfo["bytes_per_step"] / t_step / 1e9 / HBM_PEAK_GBPS, 4),
+        "launch": {k: v for k, v in best.items() if k != "seconds_per_step"},
+        "unstable_boxes": unstable,
+        "fp64_single_path": {"boxes": len(subset), "MLUPS": round(mlups64, 1),
+                             "droplets_per_hour": round(3600.0 / (total_nodes * solve_steps /
+                                                                  (mlups64 * 1e6)) * len(boxes), 1),
+                             "dP_rel_err_fp32_vs_fp64_max": max(dP_err) if dP_err else None,
+                             "dP_rel_err_fp32_vs_fp64_median": float(sorted(dP_err)[len(dP_err) // 2])
+                             if dP_err else None},
+        "speedup_vs_fp64_single": round(mlups / mlups64, 2),
+    }
+
+
 def cpu_baseline(args, nodes_gpu):
     """The FP64 oracle on the host cores: its own initial state of the same droplet, then
     `cpu_steps` plain steps of the whole box."""
@@ -124,6 +220,9 @@ def main():
                     help="copy: only the streaming-copy reference (for counter calibration)")
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--copy-reps", type=int, default=5)
+    ap.add_argument("--batched-steps", type=int, default=2048,
+                    help="steps of the batched 64-box workload measured after the main timing "
+                         "(0 = skip; 20000 = the full batched configuration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1",
@@ -264,6 +363,9 @@ def main():
                    "mass_drift_rel": abs(obs["mass"] - obs["mass0"]) / obs["mass0"],
                    "dP": obs["dP"], "R_s": obs["R_s"]},
     }
+    if args.batched_steps > 0:
+        out["batched"] = run_batched(args, torch, lbm, stream, args.batched_steps,
+                                     lambda m: print(m, file=sys.stderr, flush=True))
     if not args.no_cpu:
         print("# timing the oracle on the host cores", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args, nodes)

@@ -1,0 +1,71 @@
+"""Autotuner of launch shapes: times candidate shapes on the real boxes and keeps the fastest.
+
+Every candidate is measured with real steps of the boxes it is given (they advance the
+simulation), after one untimed step that absorbs graph capture. The shapes change only the
+schedule, never the results, so tuning on a running simulation is safe.
+"""
+import itertools
+import time
+
+
+def _sync():
+    import torch
+    torch.cuda.synchronize()
+
+
+def group_candidates():
+    out = []
+    for rows, zc, pf in itertools.product((1, 2, 4), (16, 32, 64), (0, 1)):
+        out.append(dict(rows=rows, z_chunk=zc, prefetch=pf, xcd_remap=1, persistent=0, workers=0))
+        for workers in (256, 512):
+            out.append(dict(rows=rows, z_chunk=zc, prefetch=pf, xcd_remap=1, persistent=1,
+                            workers=workers))
+    return out
+
+
+def tune_group(group, steps=8, candidates=None, log=None):
+    """Try each candidate on `group` (a paper_2105_08772_amd.Group) for `steps` steps; set and
+    return the fastest as a dict with its seconds per step."""
+    best = None
+    for cand in candidates or group_candidates():
+        group.set_launch(graph_steps=steps, **cand)
+        group.step(steps)          # warm-up: first capture and replay
+        _sync()
+        t0 = time.perf_counter()
+        group.step(steps)
+        _sync()
+        t = (time.perf_counter() - t0) / steps
+        if log:
+            log(f"tune group {cand}: {t * 1e3:.3f} ms/step")
+        if best is None or t < best[0]:
+            best = (t, cand)
+    group.set_launch(**best[1])
+    return dict(best[1], seconds_per_step=best[0])
+
+
+def box_candidates(nz):
+    out = []
+    for rows, zc, pf, remap in itertools.product((1, 2, 4), (8, 16, 32, 64, 128), (0, 1), (0, 1)):
+        if zc <= max(nz, 8):
+            out.append(dict(rows=rows, z_chunk=zc, prefetch=pf, xcd_remap=remap))
+    return out
+
+
+def tune_box(box, steps=16, candidates=None, log=None):
+    """Same for one box (a paper_2105_08772_amd.Box)."""
+    best = None
+    for cand in candidates or box_candidates(box.dims[2]):
+        box.set_launch(cand["rows"], cand["z_chunk"], cand["xcd_remap"], cand["prefetch"])
+        box.step(2)
+        _sync()
+        t0 = time.perf_counter()
+        box.step(steps)
+        _sync()
+        t = (time.perf_counter() - t0) / steps
+        if log:
+            log(f"tune box {cand}: {t * 1e3:.3f} ms/step")
+        if best is None or t < best[0]:
+            best = (t, cand)
+    c = best[1]
+    box.set_launch(c["rows"], c["z_chunk"], c["xcd_remap"], c["prefetch"])
+    return dict(c, seconds_per_step=best[0])

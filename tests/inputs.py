@@ -17,3 +17,17 @@ def random_populations(dims, seed, scale, amp=0.2):
 def random_field(shape, seed, lo, hi):
     rng = np.random.default_rng(seed)
     return rng.uniform(lo, hi, size=shape)
+
+
+def batched_boxes(seed=2105, count=64, lmin=48, lmax=160, rmin=0.15, rmax=0.35, gmin=1.05,
+                  gmax=1.8):
+    """The batched workload: `count` cubic boxes with L ~ U{lmin..lmax}, radius ~ U[rmin, rmax] L,
+    G/G_c ~ U[gmin, gmax], droplet or bubble with probability 1/2, each with its own noise seed."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(count):
+        L = int(rng.integers(lmin, lmax + 1))
+        out.append(dict(L=L, radius=float(rng.uniform(rmin, rmax) * L),
+                        g_over_gc=float(rng.uniform(gmin, gmax)),
+                        bubble=bool(rng.integers(0, 2)), seed=seed * 1000 + k))
+    return out
