@@ -174,6 +174,90 @@ def run_batched(args, torch, lbm, stream, steps, log):
     }
 
 
+def run_served(args, torch, lbm, log):
+    """The served workload: seeded Poisson arrivals of droplet/bubble requests (L ~ U{32..192},
+    radius ~ U[max(6, 0.15 L), min(60, 0.35 L)], G/G_c ~ U[1.05, 1.8], exp psi, FP32-shifted),
+    continuously batched into one multi-box launch per step, admitted by free HBM (less an 8 GiB
+    reserve), each run until its stop rule holds (dP change < 1e-5 or max |du| < 1e-9 between
+    observations 2048 steps apart; at most 100000 steps). Reports p50/p99 time to equilibrium
+    and aggregate MLUPS, and compares with the plain single-box FP64 path: its step rate is
+    measured on boxes of three sizes, dP is compared on a subset of the served requests after the
+    same number of steps, and a first-come-first-served queue of single FP64 boxes with the same
+    arrivals and step counts is evaluated from those measured rates."""
+    from tests import inputs
+    from paper_2105_08772_amd import serve
+    rate = args.served_rate
+    spec = inputs.served_requests(seed=8772, count=args.served_count, rate=rate)
+    be = serve.GpuBackend()
+    be.set_launch(rows=2, z_chunk=16, prefetch=0, persistent=1, workers=512, graph_steps=64)
+    budget = be.free_bytes() - (8 << 30)
+    srv = serve.Server(be, budget, chunk=512, observe_every=2048, max_steps=100000,
+                       dp_tol=1e-5, du_tol=1e-9, log=log)
+    for r in spec:
+        srv.submit(serve.Request(**r))
+    recs = srv.run()
+    summ = srv.summary()
+    be.close()
+    torch.cuda.empty_cache()
+    # FP64 single-box path: measured step rates
+    stream = torch.cuda.Stream()
+    rates = {}
+    for L in (32, 96, 192):
+        cfg = lbm.config(L, psi=0, geom=lbm.LBM_SC_DROPLET, prec=lbm.LBM_SC_FP64,
+                         g_over_gc=1.3, radius=L / 4, width=2.0, noise_amp=1e-6, seed=1,
+                         stream=stream.cuda_stream)
+        with lbm.Box(cfg) as b:
+            b.step(64)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            n = 2048 if L <= 96 else 512
+            b.step(n)
+            torch.cuda.synchronize()
+            rates[L] = L ** 3 * n / (time.perf_counter() - t0)
+    def rate64(L):
+        ks = sorted(rates)
+        for a, b in zip(ks, ks[1:]):
+            if L <= b:
+                w = (L - a) / (b - a)
+                return rates[a] * (1 - w) + rates[b] * w
+        return rates[ks[-1]]
+    t_free, tte64 = 0.0, []
+    for rec, r in zip(recs, spec):
+        if rec.status != "converged":
+            continue
+        start = max(t_free, r["arrival"])
+        t_free = start + r["L"] ** 3 * rec.steps / rate64(r["L"])
+        tte64.append(t_free - r["arrival"])
+    # dP of FP32 served results against FP64 runs of the same requests and step counts
+    errs = []
+    for rec, r in [(rec, r) for rec, r in zip(recs, spec) if rec.status == "converged"][:4]:
+        cfg = lbm.config(r["L"], psi=0, geom=lbm.LBM_SC_BUBBLE if r["bubble"] else lbm.LBM_SC_DROPLET,
+                         prec=lbm.LBM_SC_FP64, g_over_gc=r["g_over_gc"], radius=r["radius"],
+                         width=2.0, noise_amp=1e-6, seed=r["seed"], stream=stream.cuda_stream)
+        with lbm.Box(cfg) as b:
+            b.step(rec.steps)
+            o64 = b.observables(profile=False, raise_unstable=False)[0]
+        errs.append(abs(rec.obs["dP"] - o64["dP"]) / abs(o64["dP"]))
+    out = dict(summ)
+    out.update({
+        "workload": f"{len(spec)} requests, Poisson arrivals rate {rate}/s (seed 8772), L~U{{32..192}}, "
+                    "R~U[max(6,0.15L),min(60,0.35L)], G/G_c~U[1.05,1.8], droplet/bubble, exp psi, "
+                    "FP32-shifted, stop: dP change <1e-5 or max|du|<1e-9 per 2048 steps",
+        "budget_GiB": round(budget / 2**30, 1),
+        "droplets_per_hour": round(summ["converged"] * 3600.0 / summ["wall_s"], 1),
+        "fp64_single_path": {
+            "MLUPS_by_L": {str(k): round(v / 1e6, 1) for k, v in rates.items()},
+            "p50_time_to_equilibrium_s_modeled": round(serve.percentile(tte64, 50), 3) if tte64 else None,
+            "p99_time_to_equilibrium_s_modeled": round(serve.percentile(tte64, 99), 3) if tte64 else None,
+            "dP_rel_err_fp32_vs_fp64": errs,
+        },
+        "per_request": [dict(rid=r.rid, L=r.L, status=r.status, criterion=r.criterion,
+                             steps=r.steps, tte_s=None if r.finished is None else
+                             round(r.time_to_equilibrium, 3)) for r in recs],
+    })
+    return out
+
+
 def cpu_baseline(args, nodes_gpu):
     """The FP64 oracle on the host cores: its own initial state of the same droplet, then
     `cpu_steps` plain steps of the whole box."""
@@ -220,6 +304,9 @@ def main():
                     help="copy: only the streaming-copy reference (for counter calibration)")
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--copy-reps", type=int, default=5)
+    ap.add_argument("--served-count", type=int, default=0,
+                    help="requests of the served workload to run after the main timing (0 = skip)")
+    ap.add_argument("--served-rate", type=float, default=1.2, help="request arrival rate (1/s)")
     ap.add_argument("--batched-steps", type=int, default=2048,
                     help="steps of the batched 64-box workload measured after the main timing "
                          "(0 = skip; 20000 = the full batched configuration)")
@@ -366,6 +453,9 @@ def main():
     if args.batched_steps > 0:
         out["batched"] = run_batched(args, torch, lbm, stream, args.batched_steps,
                                      lambda m: print(m, file=sys.stderr, flush=True))
+    if args.served_count > 0:
+        out["served"] = run_served(args, torch, lbm,
+                                   lambda m: print("# " + m, file=sys.stderr, flush=True))
     if not args.no_cpu:
         print("# timing the oracle on the host cores", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args, nodes)

@@ -234,6 +234,11 @@ const char* lbm_sc_last_error(void);
  * for an unknown psi. Host only. */
 double lbm_sc_gc(int32_t psi);
 
+/* Device memory a box with this configuration will hold (populations, observation scratch and
+ * small buffers), in bytes, without allocating anything; used to admit work by free HBM. Returns
+ * a negative lbm_sc_status if cfg is invalid. Host only. */
+int64_t lbm_sc_device_bytes(const lbm_sc_config* cfg);
+
 /* Flat-interface coexistence densities and pressure for G = g_over_gc * G_c (the "equilibrium
  * values of n_g, n_l for a flat interface" of Sec. 4), from the leading-order lattice rule
  * P(n_g) = P(n_l) = p0 and int_{n_g}^{n_l} (p0 - P(n)) psi'(n)/psi(n) dn = 0, which follows from

@@ -83,7 +83,8 @@ EXPORTS = ("lbm_sc_create", "lbm_sc_step", "lbm_sc_sync", "lbm_sc_observables",
            "lbm_sc_get_launch", "lbm_sc_stream_copy", "lbm_sc_get_info", "lbm_sc_destroy",
            "lbm_sc_last_error", "lbm_sc_gc", "lbm_sc_coexistence", "lbm_sc_group_create",
            "lbm_sc_group_set", "lbm_sc_group_step", "lbm_sc_group_set_launch",
-           "lbm_sc_group_get_launch", "lbm_sc_group_info", "lbm_sc_group_destroy")
+           "lbm_sc_group_get_launch", "lbm_sc_group_info", "lbm_sc_group_destroy",
+           "lbm_sc_device_bytes")
 
 _lib = None
 
@@ -124,9 +125,11 @@ def load():
     L.lbm_sc_group_info.argtypes = [_vp, P(_i32), P(_i64), P(_i64), P(_i64)]
     L.lbm_sc_group_destroy.argtypes = [_vp]
     L.lbm_sc_group_destroy.restype = None
+    L.lbm_sc_device_bytes.argtypes = [P(LbmScConfig)]
+    L.lbm_sc_device_bytes.restype = _i64
     for name in EXPORTS:
         if name not in ("lbm_sc_destroy", "lbm_sc_last_error", "lbm_sc_gc",
-                        "lbm_sc_group_destroy"):
+                        "lbm_sc_group_destroy", "lbm_sc_device_bytes"):
             getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -161,6 +164,13 @@ def lbm_sc_coexistence(psi, g_over_gc):
     _check(load().lbm_sc_coexistence(psi, g_over_gc, ctypes.byref(ng), ctypes.byref(nl),
                                       ctypes.byref(p0)))
     return ng.value, nl.value, p0.value
+
+
+def lbm_sc_device_bytes(cfg):
+    v = load().lbm_sc_device_bytes(ctypes.byref(cfg))
+    if v < 0:
+        raise LbmScError(v, lbm_sc_last_error())
+    return v
 
 
 def lbm_sc_create(cfg):

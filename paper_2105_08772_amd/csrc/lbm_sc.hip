@@ -368,11 +368,38 @@ unsigned long long population_stride(unsigned long long n, size_t elem)
     return s;
 }
 
+struct Sizes {
+    size_t popbytes, n8, n24, parts, small, prof;
+    size_t total() const { return 2 * popbytes + 2 * n8 + 2 * n24 + parts + small + prof; }
+};
+
+Sizes sizes_for(const lbm_sc_config* c)
+{
+    const size_t elem = c->prec == LBM_SC_FP32_SHIFTED ? 4 : 8;
+    const unsigned long long n = (unsigned long long)c->nx * c->ny * c->nz;
+    const int Lmax = std::max(c->nx, std::max(c->ny, c->nz));
+    Sizes s;
+    s.popbytes = (size_t)19 * population_stride(n, elem) * elem;
+    s.n8 = (size_t)n * 8;
+    s.n24 = 3 * (size_t)n * 8;
+    s.parts = (size_t)lbm::OBS_BLOCKS * lbm::OBS_PARTS * 8;
+    s.small = (lbm::OBS_PARTS + 4) * 8;
+    s.prof = 4 * (size_t)Lmax * 8;
+    return s;
+}
+
 }  // namespace
 
 extern "C" {
 
 const char* lbm_sc_last_error(void) { return g_err.c_str(); }
+
+int64_t lbm_sc_device_bytes(const lbm_sc_config* cfg)
+{
+    int rc = validate(cfg);
+    if (rc) return rc;
+    return (int64_t)sizes_for(cfg).total();
+}
 
 double lbm_sc_gc(int32_t psi)
 {
@@ -457,20 +484,18 @@ int lbm_sc_create(const lbm_sc_config* cfg, lbm_sc** out)
         h->own_stream = true;
     }
 
-    const size_t N = b.n;
-    const size_t popbytes = (size_t)19 * b.stride * h->elem;
-    int Lmax = b.nx > b.ny ? b.nx : b.ny;
-    Lmax = Lmax > b.nz ? Lmax : b.nz;
-    if ((rc = alloc(h, &h->pop[0], popbytes)) || (rc = alloc(h, &h->pop[1], popbytes)) ||
-        (rc = alloc(h, (void**)&h->d_n, N * 8)) || (rc = alloc(h, (void**)&h->d_psi, N * 8)) ||
-        (rc = alloc(h, (void**)&h->d_u, 3 * N * 8)) || (rc = alloc(h, (void**)&h->d_uprev, 3 * N * 8)) ||
-        (rc = alloc(h, (void**)&h->d_parts, (size_t)lbm::OBS_BLOCKS * lbm::OBS_PARTS * 8)) ||
-        (rc = alloc(h, (void**)&h->d_small, (lbm::OBS_PARTS + 4) * 8)) ||
-        (rc = alloc(h, (void**)&h->d_prof, 4 * (size_t)Lmax * 8))) {
+    const Sizes sz = sizes_for(cfg);
+    if ((rc = alloc(h, &h->pop[0], sz.popbytes)) || (rc = alloc(h, &h->pop[1], sz.popbytes)) ||
+        (rc = alloc(h, (void**)&h->d_n, sz.n8)) || (rc = alloc(h, (void**)&h->d_psi, sz.n8)) ||
+        (rc = alloc(h, (void**)&h->d_u, sz.n24)) || (rc = alloc(h, (void**)&h->d_uprev, sz.n24)) ||
+        (rc = alloc(h, (void**)&h->d_parts, sz.parts)) ||
+        (rc = alloc(h, (void**)&h->d_small, sz.small)) ||
+        (rc = alloc(h, (void**)&h->d_prof, sz.prof))) {
         std::string msg = g_err;
         release(h);
         return fail(rc, msg);
     }
+    const size_t popbytes = sz.popbytes;
 
     if (cfg->geom != LBM_SC_FROM_HOST) {
         lbm::InitDesc& d = h->init;

@@ -1,0 +1,165 @@
+"""Scheduler of the continuous-batching server, exercised on the CPU with a scripted backend:
+admission by memory in arrival order, retirement on the stop rule, unstable and cancelled
+requests, step limit, rejection, and the bookkeeping of time to equilibrium."""
+import math
+
+import pytest
+
+from paper_2105_08772_amd import serve
+
+
+class Clock:
+    def __init__(self):
+        self.t = 0.0
+
+    def __call__(self):
+        return self.t
+
+    def sleep(self, dt):
+        self.t += dt
+
+
+class FakeBox:
+    def __init__(self, req):
+        self.req = req
+        self.steps = 0
+
+
+class ScriptedBackend:
+    """dP relaxes as dP_inf (1 + exp(-steps / relax)); boxes named in `fail_at` turn non-finite
+    at that step; each step call advances the clock by `dt` per chunk."""
+
+    def __init__(self, clock, dt=1.0, relax=None, fail_at=None, never=(), evaporate=None):
+        self.clock, self.dt = clock, dt
+        self.evaporate = evaporate or {}
+        self.relax = relax or {}
+        self.fail_at = fail_at or {}
+        self.never = set(never)
+        self.active = []
+        self.live = set()
+        self.hook = None
+
+    def bytes_needed(self, r):
+        return r.L ** 3
+
+    def create(self, r):
+        b = FakeBox(r)
+        self.live.add(r.rid)
+        return b
+
+    def set_active(self, boxes):
+        self.active = list(boxes)
+
+    def step(self, n):
+        for b in self.active:
+            b.steps += n
+        self.clock.t += self.dt
+        if self.hook:
+            self.hook()
+
+    def observe(self, b):
+        rid = b.req.rid
+        finite = not (rid in self.fail_at and b.steps >= self.fail_at[rid])
+        if rid in self.never:
+            dP = 1.0 + 0.5 * (b.steps // 2048 % 2)  # alternates between observations forever
+        else:
+            dP = 1.0 + math.exp(-b.steps / self.relax.get(rid, 1000.0))
+        gone = rid in self.evaporate and b.steps >= self.evaporate[rid]
+        return dict(finite=int(finite), dP=dP, has_du=1, du_max=1.0, mass=1.0, mass0=1.0,
+                    n_center=0.4 if gone else 2.5, n_far=0.4, com=[b.req.L // 2] * 3)
+
+    def destroy(self, b):
+        self.live.discard(b.req.rid)
+
+    def snapshot(self, b):
+        return b.steps
+
+
+def make(requests, budget, **kw):
+    clock = Clock()
+    be = ScriptedBackend(clock, **{k: kw.pop(k) for k in list(kw) if k in
+                                   ("dt", "relax", "fail_at", "never", "evaporate")})
+    srv = serve.Server(be, budget, chunk=512, observe_every=2048, clock=clock, sleep=clock.sleep,
+                       **kw)
+    for r in requests:
+        srv.submit(r)
+    return srv, be, clock
+
+
+def req(rid, L, arrival):
+    return serve.Request(rid=rid, L=L, radius=L / 4, g_over_gc=1.3, bubble=False, seed=rid,
+                         arrival=arrival)
+
+
+def test_admission_by_memory_in_arrival_order():
+    reqs = [req(k, 10, 0.0) for k in range(5)]
+    srv, be, _ = make(reqs, budget=2 * 1000)
+    recs = srv.run()
+    assert srv.max_active == 2
+    assert all(r.status == "converged" for r in recs)
+    admitted = sorted(recs, key=lambda r: r.admitted)
+    assert [r.rid for r in admitted] == [0, 1, 2, 3, 4]
+    assert srv.used == 0 and not be.live
+    for r in recs:
+        assert r.time_to_equilibrium == r.finished - r.arrival
+
+
+def test_unstable_request_is_retired_and_others_continue():
+    reqs = [req(k, 10, 0.0) for k in range(3)]
+    srv, be, _ = make(reqs, budget=10 ** 6, fail_at={1: 4096})
+    recs = {r.rid: r for r in srv.run()}
+    assert recs[1].status == "unstable" and recs[1].steps == 4096
+    assert recs[0].status == "converged" and recs[2].status == "converged"
+    assert not be.live and srv.used == 0
+
+
+def test_evaporated_request_is_retired_and_flagged():
+    reqs = [req(k, 10, 0.0) for k in range(3)]
+    srv, be, _ = make(reqs, budget=10 ** 6, evaporate={2: 2048})
+    recs = {r.rid: r for r in srv.run()}
+    assert recs[2].status == "evaporated" and recs[2].steps == 2048
+    assert recs[0].status == "converged" and recs[0].valid is True
+    assert recs[2].valid is None
+
+
+def test_cancel_queued_and_running_requests():
+    reqs = [req(k, 10, 0.0) for k in range(4)]
+    srv, be, clock = make(reqs, budget=2 * 1000)
+    srv.cancel(3)                               # still queued when the loop starts
+
+    def hook():
+        if clock.t >= 2.0:
+            srv.cancel(0)                       # running
+    be.hook = hook
+    recs = {r.rid: r for r in srv.run()}
+    assert recs[3].status == "cancelled" and recs[3].admitted is None
+    assert recs[0].status == "cancelled" and recs[0].admitted is not None
+    assert recs[1].status == "converged" and recs[2].status == "converged"
+    assert not be.live
+
+
+def test_step_limit_and_rejection():
+    reqs = [req(0, 10, 0.0), req(1, 100, 0.0), req(2, 10, 0.5)]
+    srv, be, _ = make(reqs, budget=5000, never={0}, max_steps=8192, relax={2: 200.0})
+    recs = {r.rid: r for r in srv.run()}
+    assert recs[0].status == "step_limit" and recs[0].steps == 8192
+    assert recs[1].status == "rejected"
+    assert recs[2].status == "converged"
+
+
+def test_late_arrivals_wait_and_join_running_boxes():
+    reqs = [req(0, 10, 0.0), req(1, 10, 2.5), req(2, 10, 40.0)]
+    srv, be, clock = make(reqs, budget=10 ** 6, relax={0: 4000.0, 1: 500.0, 2: 500.0})
+    recs = {r.rid: r for r in srv.run()}
+    assert recs[1].admitted >= 2.5 and recs[1].admitted < recs[0].finished   # overlapped
+    assert recs[2].admitted >= 40.0                                          # idle wait
+    s = srv.summary()
+    assert s["converged"] == 3 and s["p50_time_to_equilibrium_s"] > 0
+
+
+def test_percentile_nearest_rank():
+    v = list(range(1, 101))
+    assert serve.percentile(v, 50) == 50
+    assert serve.percentile(v, 99) == 99
+    assert serve.percentile([3.0], 99) == 3.0
+    assert serve.percentile([1, 2, 3, 4], 50) == 2
