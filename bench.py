@@ -258,6 +258,70 @@ def run_served(args, torch, lbm, log):
     return out
 
 
+def run_tolman(args, torch, lbm, log):
+    """A scaled version of the paper's droplet/bubble sweep (Sec. 4): couplings G/G_c - 1 in
+    {0.159, 0.215, 0.293}, odd box sizes L in {41, ..., 123}, R = L/4, droplets and
+    bubbles, exp psi, the paper's tanh profile (width 1), FP32-shifted populations, all boxes
+    served together until the paper's criterion (relative dP change < 1e-5 over 2048 steps). The
+    Tolman fit per coupling gives sigma_0 and delta; sigma_0 is compared with the flat value from
+    a converged FP64 slab (the paper reports that the two agree)."""
+    from paper_2105_08772_amd import analysis, serve
+    ratios = (1.159, 1.215, 1.293)
+    sizes = (41, 47, 55, 61, 67, 77, 87, 103, 123)
+    be = serve.GpuBackend(width=1.0)
+    be.set_launch(rows=2, z_chunk=16, prefetch=0, persistent=1, workers=512, graph_steps=64)
+    srv = serve.Server(be, be.free_bytes() - (8 << 30), chunk=512, observe_every=2048,
+                       max_steps=100000, dp_tol=1e-5, du_tol=0.0, log=log)
+    spec = {}
+    rid = 0
+    for g in ratios:
+        for L in sizes:
+            for bubble in (False, True):
+                spec[rid] = dict(g_over_gc=g, L=L, bubble=bubble)
+                srv.submit(serve.Request(rid=rid, L=L, radius=L / 4.0, g_over_gc=g, bubble=bubble,
+                                         seed=1000 + rid, arrival=0.0))
+                rid += 1
+    recs = srv.run()
+    be.close()
+    runs = [dict(spec[r.rid], obs=r.obs) for r in recs if r.status == "converged"]
+    fits = analysis.analyse(runs)
+    # flat sigma_0: FP64 slab 4 x 4 x 64, liquid thickness 32, width 1, 40000 steps
+    stream = torch.cuda.Stream()
+    flat = {}
+    for g in ratios:
+        cfg = lbm.config(4, 4, 64, psi=0, geom=lbm.LBM_SC_SLAB, prec=lbm.LBM_SC_FP64, g_over_gc=g,
+                         slab_thickness=32.0, width=1.0, slab_axis=2, stream=stream.cuda_stream)
+        with lbm.Box(cfg) as b:
+            b.step(40000)
+            o, _ = b.observables()
+        flat[g] = dict(sigma0=o["sigma0_flat"], pn_spread_rel=o["pn_spread"] / o["P_out"])
+    out = {"workload": "G/G_c-1 in {0.159,0.215,0.293} x L in {41,47,55,61,67,77,87,103,123} x "
+                       "{droplet,bubble}, R=L/4, tanh width 1, exp psi, FP32-shifted, served "
+                       "together until |dP change|/dP < 1e-5 per 2048 steps",
+           "wall_s": round(srv.wall, 2), "statuses": srv.summary()["statuses"], "couplings": {}}
+    for g in ratios:
+        f = fits.get(round(g, 10))
+        entry = {"flat_sigma0": flat[g]["sigma0"], "flat_pn_spread_rel": flat[g]["pn_spread_rel"]}
+        if f:
+            entry.update({k: f[k] for k in ("sigma0", "delta", "rms", "npoints", "delta_hat0",
+                                            "no_minimum")})
+            entry["sigma0_fit_over_flat"] = f["sigma0"] / flat[g]["sigma0"]
+            entry["points"] = [dict(kappa=round(p["kappa"], 6), sigma_s=round(p["sigma_s"], 8),
+                                    R_s=round(p["R_s"], 4), R_e=round(p["R_e"], 4),
+                                    bubble=p["bubble"]) for p in f["points"]]
+        out["couplings"][str(g)] = entry
+    gs = [g for g in ratios if fits.get(round(g, 10))]
+    if len(gs) >= 2:
+        x = [g - 1 for g in gs]
+        out["sigma0_exponent"] = analysis.scaling_exponent(
+            x, [fits[round(g, 10)]["sigma0"] for g in gs])["exponent"]
+        out["flat_sigma0_exponent"] = analysis.scaling_exponent(x, [flat[g]["sigma0"] for g in gs])["exponent"]
+        if all(fits[round(g, 10)]["delta"] > 0 for g in gs):
+            out["delta_exponent"] = analysis.scaling_exponent(
+                x, [fits[round(g, 10)]["delta"] for g in gs])["exponent"]
+    return out
+
+
 def cpu_baseline(args, nodes_gpu):
     """The FP64 oracle on the host cores: its own initial state of the same droplet, then
     `cpu_steps` plain steps of the whole box."""
@@ -307,6 +371,8 @@ def main():
     ap.add_argument("--served-count", type=int, default=0,
                     help="requests of the served workload to run after the main timing (0 = skip)")
     ap.add_argument("--served-rate", type=float, default=1.2, help="request arrival rate (1/s)")
+    ap.add_argument("--tolman", action="store_true",
+                    help="run the scaled droplet/bubble sweep and the Tolman analysis")
     ap.add_argument("--batched-steps", type=int, default=2048,
                     help="steps of the batched 64-box workload measured after the main timing "
                          "(0 = skip; 20000 = the full batched configuration)")
@@ -453,6 +519,9 @@ def main():
     if args.batched_steps > 0:
         out["batched"] = run_batched(args, torch, lbm, stream, args.batched_steps,
                                      lambda m: print(m, file=sys.stderr, flush=True))
+    if args.tolman:
+        out["tolman"] = run_tolman(args, torch, lbm,
+                                   lambda m: print("# " + m, file=sys.stderr, flush=True))
     if args.served_count > 0:
         out["served"] = run_served(args, torch, lbm,
                                    lambda m: print("# " + m, file=sys.stderr, flush=True))
