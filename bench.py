@@ -13,6 +13,7 @@ timed on the host cores on a bounded sample of the same workload.
 """
 import argparse
 import hashlib
+import itertools
 import json
 import os
 import sys
@@ -34,15 +35,16 @@ def kernel_hash():
         return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
-def measured_traffic(nodes):
+def measured_traffic(nodes, prec, launch):
     """HBM bytes per step launch from committed rocprofv3 counter summaries, if they were taken
-    on the current kernel source (else None)."""
+    on the current kernel source, precision and launch shape (else None)."""
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
         return None
-    if t.get("kernel_sha256_16") != kernel_hash() or t.get("nodes") != nodes:
+    if (t.get("kernel_sha256_16") != kernel_hash() or t.get("nodes") != nodes
+            or t.get("prec") != prec or t.get("launch") != launch):
         return None
     return t.get("bytes_per_launch")
 
@@ -346,6 +348,10 @@ def cpu_baseline(args, nodes_gpu):
                       f"{dt:.1f} s)"}
 
 
+PREC_NAMES = {"fp32": "FP32-shifted", "fp32m64": "FP32-shifted (FP64 arithmetic)",
+              "fp64": "FP64"}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -354,12 +360,15 @@ def main():
     ap.add_argument("--size", type=int, default=256)
     ap.add_argument("--radius", type=float, default=60.0)
     ap.add_argument("--psi", choices=["exp", "oneminus"], default="exp")
-    ap.add_argument("--prec", choices=["fp32", "fp64"], default="fp32")
+    ap.add_argument("--prec", choices=["fp32", "fp32m64", "fp64"], default="fp32",
+                    help="fp32: FP32-shifted storage and arithmetic; fp32m64: FP32-shifted storage,"
+                         " FP64 arithmetic; fp64: FP64 storage and arithmetic")
     ap.add_argument("--observe-every", type=int, default=2048)
     ap.add_argument("--rows", type=int, default=0)
     ap.add_argument("--zchunk", type=int, default=0)
     ap.add_argument("--remap", type=int, default=-1)
     ap.add_argument("--prefetch", type=int, default=-1)
+    ap.add_argument("--waves", type=int, default=0)
     ap.add_argument("--tune", action="store_true", help="sweep launch shapes, keep the fastest")
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
@@ -402,7 +411,8 @@ def main():
         return
     L = args.size
     psi = lbm.LBM_SC_PSI_EXP if args.psi == "exp" else lbm.LBM_SC_PSI_ONEMINUS
-    prec = lbm.LBM_SC_FP32_SHIFTED if args.prec == "fp32" else lbm.LBM_SC_FP64
+    prec = {"fp32": lbm.LBM_SC_FP32_SHIFTED, "fp32m64": lbm.LBM_SC_FP32_SHIFTED_MATH64,
+            "fp64": lbm.LBM_SC_FP64}[args.prec]
     cfg = lbm.config(L, L, L, psi=psi, geom=lbm.LBM_SC_DROPLET, prec=prec, tau=1.0,
                      g_over_gc=1.3, radius=args.radius, width=2.0, noise_amp=1e-6, seed=3,
                      stream=stream.cuda_stream)
@@ -425,25 +435,25 @@ def main():
     tuned = None
     if args.tune:
         best = None
-        for rows in (1, 2, 4):
-            for zc in (8, 11, 16, 22, 32, 43, 64, 128):
-                for remap in (0, 1):
-                    for pf in (0, 1):
-                        box.set_launch(rows, zc, remap, pf)
-                        box.step(8)
-                        t = time_steps(64)
-                        print(f"# tune rows={rows} zchunk={zc} remap={remap} prefetch={pf} "
-                              f"{nodes / t / 1e6:.0f} MLUPS {bytes_per_step / t / 1e9:.0f} GB/s",
-                              file=sys.stderr, flush=True)
-                        if best is None or t < best[0]:
-                            best = (t, rows, zc, remap, pf)
-        tuned = dict(rows=best[1], z_chunk=best[2], xcd_remap=best[3], prefetch=best[4])
-        box.set_launch(best[1], best[2], best[3], best[4])
-    if args.rows or args.zchunk or args.remap >= 0 or args.prefetch >= 0:
+        for waves, rows, zc, remap, pf in itertools.product(
+                (4, 8), (1, 2, 4), (8, 16, 32, 64, 128), (0, 1), (0, 1)):
+            box.set_launch(rows, zc, remap, pf, waves)
+            box.step(8)
+            t = time_steps(64)
+            print(f"# tune waves={waves} rows={rows} zchunk={zc} remap={remap} prefetch={pf} "
+                  f"{nodes / t / 1e6:.0f} MLUPS {bytes_per_step / t / 1e9:.0f} GB/s",
+                  file=sys.stderr, flush=True)
+            if best is None or t < best[0]:
+                best = (t, rows, zc, remap, pf, waves)
+        tuned = dict(rows=best[1], z_chunk=best[2], xcd_remap=best[3], prefetch=best[4],
+                     waves=best[5])
+        box.set_launch(*best[1:])
+    if args.rows or args.zchunk or args.remap >= 0 or args.prefetch >= 0 or args.waves:
         lc = box.launch()
         box.set_launch(args.rows or lc["rows"], args.zchunk or lc["z_chunk"],
                        args.remap if args.remap >= 0 else lc["xcd_remap"],
-                       args.prefetch if args.prefetch >= 0 else lc["prefetch"])
+                       args.prefetch if args.prefetch >= 0 else lc["prefetch"],
+                       args.waves or lc["waves"])
     info = box.info()
     launch = box.launch()
 
@@ -478,7 +488,7 @@ def main():
     box.close()
 
     copy_bw = None if args.no_copy else stream_copy_gbps(torch, lbm, stream)
-    traffic = measured_traffic(nodes)
+    traffic = measured_traffic(nodes, args.prec, launch)
 
     out = {
         "metric": METRIC,
@@ -494,12 +504,13 @@ def main():
         "dtype": "f32" if prec == lbm.LBM_SC_FP32_SHIFTED else "f64",
         "data": "synthetic",
         "config": {
-            "workload": f"droplet {L}^3 periodic, {'FP32-shifted' if args.prec == 'fp32' else 'FP64'}"
-                        f" populations, psi={args.psi}, G/G_c=1.3, R={args.radius:g}, tanh width 2,"
+            "workload": f"droplet {L}^3 periodic, {PREC_NAMES[args.prec]} populations,"
+                        f" psi={args.psi}, G/G_c=1.3, R={args.radius:g}, tanh width 2,"
                         f" noise 1e-6 seed 3, tau=1, FP64 observables every {args.observe_every}"
                         f" steps",
             "nodes": nodes,
-            "launch": dict(launch, block=[64, 4 * launch["rows"]], tuned=tuned is not None),
+            "launch": dict(launch, block=[64, launch["waves"] * launch["rows"]],
+                           tuned=tuned is not None),
         },
         "roofline": {
             "bound": "hbm",

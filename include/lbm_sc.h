@@ -55,14 +55,17 @@ enum { LBM_SC_DROPLET = 0, LBM_SC_BUBBLE = 1, LBM_SC_SLAB = 2, LBM_SC_FROM_HOST 
 
 /* Population storage. FP64 stores f_i in double precision and computes in double precision.
  * FP32_SHIFTED stores g_i = f_i - w_i rho_ref in single precision and computes the step in
- * single precision; its observables are computed in double precision. */
-enum { LBM_SC_FP64 = 0, LBM_SC_FP32_SHIFTED = 1 };
+ * single precision. FP32_SHIFTED_MATH64 stores the same single-precision g_i (same memory and
+ * HBM traffic) but does the step's arithmetic (psi, force, velocity, equilibrium, collision) in
+ * double precision, rounding only the stored populations. Observables are always computed in
+ * double precision. */
+enum { LBM_SC_FP64 = 0, LBM_SC_FP32_SHIFTED = 1, LBM_SC_FP32_SHIFTED_MATH64 = 2 };
 
 typedef struct {
     int32_t nx, ny, nz;      /* periodic box, each >= 1; x is the fastest axis */
     int32_t psi;             /* LBM_SC_PSI_* */
     int32_t geom;            /* LBM_SC_DROPLET / BUBBLE / SLAB / FROM_HOST */
-    int32_t prec;            /* LBM_SC_FP64 / LBM_SC_FP32_SHIFTED */
+    int32_t prec;            /* LBM_SC_FP64 / LBM_SC_FP32_SHIFTED / LBM_SC_FP32_SHIFTED_MATH64 */
     int32_t slab_axis;       /* slab normal: 0 = x, 1 = y, 2 = z */
     int32_t reserved0;       /* must be 0 */
     double tau;              /* BGK relaxation time, > 0.5 */
@@ -75,7 +78,7 @@ typedef struct {
                                 BUBBLE) */
     double noise_amp;        /* additive uniform noise in [-noise_amp, noise_amp) on the initial n */
     uint64_t seed;           /* noise of node k = SplitMix64(seed ^ k), k = (z*ny + y)*nx + x */
-    double rho_ref;          /* FP32_SHIFTED reference density; 0 => (n_in + n_out)/2 */
+    double rho_ref;          /* shifted FP32 reference density; 0 => (n_in + n_out)/2 */
     void* stream;            /* hipStream_t to enqueue on, or NULL for a stream the handle owns */
 } lbm_sc_config;
 
@@ -104,7 +107,7 @@ typedef struct {
     double G;                /* coupling used */
     double Gc;               /* critical coupling of the pseudopotential */
     double n_in, n_out;      /* densities used for the initial profile */
-    double rho_ref;          /* FP32_SHIFTED reference density (0 for FP64) */
+    double rho_ref;          /* shifted FP32 reference density (0 for FP64) */
     int64_t nodes;           /* nx*ny*nz */
     int64_t device_bytes;    /* device memory held by the handle */
     int64_t bytes_per_step;  /* algorithmic HBM bytes of one step: 2 * 19 * sizeof(storage) * nodes */
@@ -138,22 +141,24 @@ int lbm_sc_sync(lbm_sc* h);
 int lbm_sc_observables(lbm_sc* h, lbm_sc_obs* out, double* prof, size_t prof_len);
 
 /* Copy the current pre-collision populations f_i(x, t) to the host array f (canonical layout,
- * len must be 19*nx*ny*nz). FP32_SHIFTED states are widened to FP64 and the shift w_i rho_ref
+ * len must be 19*nx*ny*nz). Shifted FP32 states are widened to FP64 and the shift w_i rho_ref
  * added back. Synchronises. */
 int lbm_sc_get_populations(lbm_sc* h, double* f, size_t len);
 
 /* Replace the state by the host array f (canonical layout, pre-collision populations at the
- * current time, len 19*nx*ny*nz). FP32_SHIFTED stores them rounded after subtracting w_i rho_ref.
+ * current time, len 19*nx*ny*nz). Shifted FP32 storage holds them rounded after subtracting w_i rho_ref.
  * Resets the step counter, mass0 and the du reference. Synchronises. */
 int lbm_sc_set_populations(lbm_sc* h, const double* f, size_t len);
 
-/* Launch shape of the fused step kernel. The workgroup is 256 threads (4 wave64s) and owns an
- * x-y tile of 64 x (4*rows) nodes and a run of z_chunk planes along z. */
+/* Launch shape of the fused step kernel. The workgroup is 64*waves threads (waves wave64s) and
+ * owns an x-y tile of 64 x (waves*rows) nodes and a run of z_chunk planes along z. */
 typedef struct {
     int32_t rows;       /* tile rows per wave: 1, 2 or 4 */
     int32_t z_chunk;    /* planes per workgroup, >= 1 (clamped to nz) */
     int32_t xcd_remap;  /* 1: hand neighbouring tiles to the same XCD (shared L2); 0: identity */
     int32_t prefetch;   /* 1: issue the next plane's loads before the collision of the current one */
+    int32_t waves;      /* wave64s per workgroup: 4 or 8 */
+    int32_t reserved;   /* must be 0 */
 } lbm_sc_launch;
 
 /* Set / read the launch shape. The shape changes only the schedule: every node's arithmetic and
@@ -170,7 +175,8 @@ int lbm_sc_get_launch(lbm_sc* h, lbm_sc_launch* out);
  * work items, so boxes of different sizes, pseudopotentials, couplings and relaxation times share
  * the GPU in a single launch. The per-node arithmetic is the same as lbm_sc_step, so a box
  * stepped in a group ends bitwise equal to the same box stepped alone. All boxes of a group must
- * have the same storage precision and must have been created on the group's stream. Boxes stay
+ * have the same precision, LBM_SC_FP64 or LBM_SC_FP32_SHIFTED (FP32_SHIFTED_MATH64 boxes are
+ * stepped alone), and must have been created on the group's stream. Boxes stay
  * owned by the caller; the group keeps their handles until the next lbm_sc_group_set or
  * lbm_sc_group_destroy, and they must not be destroyed in between.
  * ------------------------------------------------------------------------------------------ */
@@ -193,7 +199,8 @@ typedef struct {
 int lbm_sc_group_create(void* stream, lbm_sc_group** out);
 
 /* Set the boxes stepped by the group (nbox >= 0; an empty group steps nothing). Validates that
- * every box has the group's stream and that all share one precision (LBM_SC_EINVAL otherwise),
+ * every box has the group's stream and that all share one precision, FP64 or FP32_SHIFTED
+ * (LBM_SC_EINVAL otherwise),
  * builds the work list for the current launch shape and uploads it (stream-ordered). */
 int lbm_sc_group_set(lbm_sc_group* g, lbm_sc* const* boxes, int32_t nbox);
 

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "liblbm_sc.so")
 LBM_SC_OK, LBM_SC_EINVAL, LBM_SC_ENOMEM, LBM_SC_EDEVICE, LBM_SC_EUNSTABLE = 0, -1, -2, -3, -4
 LBM_SC_PSI_EXP, LBM_SC_PSI_ONEMINUS = 0, 1
 LBM_SC_DROPLET, LBM_SC_BUBBLE, LBM_SC_SLAB, LBM_SC_FROM_HOST = 0, 1, 2, 3
-LBM_SC_FP64, LBM_SC_FP32_SHIFTED = 0, 1
+LBM_SC_FP64, LBM_SC_FP32_SHIFTED, LBM_SC_FP32_SHIFTED_MATH64 = 0, 1, 2
 
 _i32, _i64, _u64, _f64, _vp = (ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double,
                                ctypes.c_void_p)
@@ -58,10 +58,11 @@ class LbmScInfo(ctypes.Structure):
 
 
 class LbmScLaunch(ctypes.Structure):
-    _fields_ = [("rows", _i32), ("z_chunk", _i32), ("xcd_remap", _i32), ("prefetch", _i32)]
+    _fields_ = [("rows", _i32), ("z_chunk", _i32), ("xcd_remap", _i32), ("prefetch", _i32),
+                ("waves", _i32), ("reserved", _i32)]
 
     def to_dict(self):
-        return {name: getattr(self, name) for name, _ in self._fields_}
+        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
 
 
 class LbmScGroupLaunch(ctypes.Structure):
@@ -216,8 +217,8 @@ def lbm_sc_set_populations(h, f):
     _check(load().lbm_sc_set_populations(h, f.ctypes.data_as(ctypes.POINTER(_f64)), f.size))
 
 
-def lbm_sc_set_launch(h, rows, z_chunk, xcd_remap=1, prefetch=0):
-    l = LbmScLaunch(rows, z_chunk, xcd_remap, prefetch)
+def lbm_sc_set_launch(h, rows, z_chunk, xcd_remap=1, prefetch=0, waves=4):
+    l = LbmScLaunch(rows, z_chunk, xcd_remap, prefetch, waves, 0)
     _check(load().lbm_sc_set_launch(h, ctypes.byref(l)))
 
 
@@ -271,8 +272,8 @@ class Box:
     def set(self, f):
         lbm_sc_set_populations(self.h, f)
 
-    def set_launch(self, rows, z_chunk, xcd_remap=1, prefetch=0):
-        lbm_sc_set_launch(self.h, rows, z_chunk, xcd_remap, prefetch)
+    def set_launch(self, rows, z_chunk, xcd_remap=1, prefetch=0, waves=4):
+        lbm_sc_set_launch(self.h, rows, z_chunk, xcd_remap, prefetch, waves)
 
     def launch(self):
         return lbm_sc_get_launch(self.h)

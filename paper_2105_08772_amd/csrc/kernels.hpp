@@ -18,10 +18,11 @@ struct BoxDesc {
     double rho_ref;          // 0 for FP64 storage
 };
 
-// Launch shape of the fused step kernel. The workgroup is 256 threads = 4 wave64s; the tile is
-// 64 x (4 * rows) nodes in x-y and z_chunk planes in z.
+// Launch shape of the fused step kernel. The workgroup is 64 * waves threads (waves wave64s); the
+// tile is 64 x (waves * rows) nodes in x-y and z_chunk planes in z.
 struct StepShape {
     int rows;        // rows of the tile per wave (1, 2 or 4)
+    int waves;       // wave64s per workgroup (4 or 8); the multi-box kernels use 4
     int z_chunk;     // planes marched per workgroup
     int xcd_remap;   // 1: map consecutive logical tiles to one XCD
     int prefetch;    // 1: issue the next plane's loads before the barrier (software pipelining)
@@ -60,8 +61,10 @@ constexpr int OBS_PARTS = 14;
 // Fixed grid of the observation reduction (deterministic order of the partial sums).
 constexpr int OBS_BLOCKS = 512;
 
-hipError_t launch_step(bool fp32, const BoxDesc& b, const StepShape& s, const void* src, void* dst,
-                       hipStream_t st);
+// One step of one box. fp32: populations stored as float (shifted); math64: with fp32, the step's
+// arithmetic is done in double precision (storage and traffic unchanged).
+hipError_t launch_step(bool fp32, bool math64, const BoxDesc& b, const StepShape& s,
+                       const void* src, void* dst, hipStream_t st);
 // Multi-box step. nitems work items; persistent: grid of `workers` workgroups over the queues.
 hipError_t launch_step_group(bool fp32, const StepShape& s, const GroupBox* boxes, int nbox,
                              unsigned nitems, int parity, int persistent, unsigned workers,

@@ -171,7 +171,8 @@ struct lbm_sc {
     lbm::BoxDesc box;
     lbm::StepShape shape;
     lbm::InitDesc init;
-    bool fp32 = false;
+    bool fp32 = false;    // populations stored as float (shifted)
+    bool math64 = false;  // with fp32: step arithmetic in double precision
     size_t elem = 8;
     void* pop[2] = {nullptr, nullptr};
     int cur = 0;
@@ -203,8 +204,9 @@ int validate(const lbm_sc_config* c)
         return fail(LBM_SC_EINVAL, "psi must be LBM_SC_PSI_EXP or LBM_SC_PSI_ONEMINUS");
     if (c->geom < LBM_SC_DROPLET || c->geom > LBM_SC_FROM_HOST)
         return fail(LBM_SC_EINVAL, "unknown geom");
-    if (c->prec != LBM_SC_FP64 && c->prec != LBM_SC_FP32_SHIFTED)
-        return fail(LBM_SC_EINVAL, "prec must be LBM_SC_FP64 or LBM_SC_FP32_SHIFTED");
+    if (c->prec != LBM_SC_FP64 && c->prec != LBM_SC_FP32_SHIFTED && c->prec != LBM_SC_FP32_SHIFTED_MATH64)
+        return fail(LBM_SC_EINVAL,
+                    "prec must be LBM_SC_FP64, LBM_SC_FP32_SHIFTED or LBM_SC_FP32_SHIFTED_MATH64");
     if (c->reserved0 != 0) return fail(LBM_SC_EINVAL, "reserved0 must be 0");
     if (!(c->tau > 0.5) || !std::isfinite(c->tau)) return fail(LBM_SC_EINVAL, "tau must be > 0.5");
     if (!std::isfinite(c->g_over_gc)) return fail(LBM_SC_EINVAL, "g_over_gc must be finite");
@@ -343,14 +345,15 @@ int observe(lbm_sc* h, lbm_sc_obs* o, double* prof_out)
     return LBM_SC_OK;
 }
 
-// Default launch shape (measured on MI355X at 256^3): two rows per wave, the next plane
-// prefetched, XCD remap on, and z chunks long enough that about one workgroup runs per CU.
+// Default launch shape (measured on MI355X at 256^3): 8-wave workgroups with two rows per wave
+// (64 x 16 tiles), XCD remap on, and z chunks long enough that about one workgroup runs per CU.
 void default_shape(lbm_sc* h)
 {
     h->shape.rows = 2;
+    h->shape.waves = 8;
     h->shape.xcd_remap = 1;
-    h->shape.prefetch = 1;
-    const int by = 4 * h->shape.rows;
+    h->shape.prefetch = 0;
+    const int by = h->shape.waves * h->shape.rows;
     const long tiles = (long)((h->box.nx + 63) / 64) * ((h->box.ny + by - 1) / by);
     long chunks = (256 + tiles - 1) / tiles;
     if (chunks > h->box.nz) chunks = h->box.nz;
@@ -375,7 +378,7 @@ struct Sizes {
 
 Sizes sizes_for(const lbm_sc_config* c)
 {
-    const size_t elem = c->prec == LBM_SC_FP32_SHIFTED ? 4 : 8;
+    const size_t elem = c->prec == LBM_SC_FP64 ? 8 : 4;
     const unsigned long long n = (unsigned long long)c->nx * c->ny * c->nz;
     const int Lmax = std::max(c->nx, std::max(c->ny, c->nz));
     Sizes s;
@@ -428,7 +431,8 @@ int lbm_sc_create(const lbm_sc_config* cfg, lbm_sc** out)
     lbm_sc* h = new (std::nothrow) lbm_sc();
     if (!h) return fail(LBM_SC_ENOMEM, "host allocation failed");
     h->cfg = *cfg;
-    h->fp32 = cfg->prec == LBM_SC_FP32_SHIFTED;
+    h->fp32 = cfg->prec != LBM_SC_FP64;
+    h->math64 = cfg->prec == LBM_SC_FP32_SHIFTED_MATH64;
     h->elem = h->fp32 ? 4 : 8;
     h->Gc = gc_h(cfg->psi);
     h->G = cfg->g_over_gc * h->Gc;
@@ -449,7 +453,7 @@ int lbm_sc_create(const lbm_sc_config* cfg, lbm_sc** out)
     if (h->fp32) rho_ref = cfg->rho_ref > 0.0 ? cfg->rho_ref : 0.5 * (n_in + n_out);
     if (h->fp32 && !(rho_ref > 0.0)) {
         release(h);
-        return fail(LBM_SC_EINVAL, "FP32_SHIFTED with geom FROM_HOST needs rho_ref > 0");
+        return fail(LBM_SC_EINVAL, "shifted FP32 storage with geom FROM_HOST needs rho_ref > 0");
     }
     h->cfg.rho_ref = rho_ref;
 
@@ -539,7 +543,7 @@ int lbm_sc_step(lbm_sc* h, int64_t nsteps)
     if (!h) return fail(LBM_SC_EINVAL, "handle is NULL");
     if (nsteps < 0) return fail(LBM_SC_EINVAL, "nsteps must be >= 0");
     for (int64_t s = 0; s < nsteps; ++s) {
-        hipError_t e = lbm::launch_step(h->fp32, h->box, h->shape, h->pop[h->cur],
+        hipError_t e = lbm::launch_step(h->fp32, h->math64, h->box, h->shape, h->pop[h->cur],
                                         h->pop[1 - h->cur], h->stream);
         if (e != hipSuccess) return fail_hip("launch_step", e);
         h->cur = 1 - h->cur;
@@ -611,7 +615,7 @@ int lbm_sc_get_info(lbm_sc* h, lbm_sc_info* out)
     out->device_bytes = h->device_bytes;
     out->bytes_per_step = (int64_t)2 * 19 * (int64_t)h->elem * (int64_t)h->box.n;
     out->block_x = 64;
-    out->block_y = 4 * h->shape.rows;
+    out->block_y = h->shape.waves * h->shape.rows;
     out->z_chunk = h->shape.z_chunk;
     return LBM_SC_OK;
 }
@@ -623,7 +627,10 @@ int lbm_sc_set_launch(lbm_sc* h, const lbm_sc_launch* l)
     if (l->z_chunk < 1) return fail(LBM_SC_EINVAL, "z_chunk must be >= 1");
     if (l->xcd_remap != 0 && l->xcd_remap != 1) return fail(LBM_SC_EINVAL, "xcd_remap must be 0 or 1");
     if (l->prefetch != 0 && l->prefetch != 1) return fail(LBM_SC_EINVAL, "prefetch must be 0 or 1");
+    if (l->waves != 4 && l->waves != 8) return fail(LBM_SC_EINVAL, "waves must be 4 or 8");
+    if (l->reserved != 0) return fail(LBM_SC_EINVAL, "reserved must be 0");
     h->shape.rows = l->rows;
+    h->shape.waves = l->waves;
     h->shape.z_chunk = l->z_chunk < h->box.nz ? l->z_chunk : h->box.nz;
     h->shape.xcd_remap = l->xcd_remap;
     h->shape.prefetch = l->prefetch;
@@ -637,6 +644,8 @@ int lbm_sc_get_launch(lbm_sc* h, lbm_sc_launch* out)
     out->z_chunk = h->shape.z_chunk;
     out->xcd_remap = h->shape.xcd_remap;
     out->prefetch = h->shape.prefetch;
+    out->waves = h->shape.waves;
+    out->reserved = 0;
     return LBM_SC_OK;
 }
 
@@ -763,6 +772,7 @@ hipError_t group_launch(lbm_sc_group* g, int parity)
 {
     lbm::StepShape s;
     s.rows = g->launch.rows;
+    s.waves = 4;
     s.z_chunk = g->launch.z_chunk;
     s.xcd_remap = g->launch.xcd_remap;
     s.prefetch = g->launch.prefetch;
@@ -821,6 +831,9 @@ int lbm_sc_group_set(lbm_sc_group* g, lbm_sc* const* boxes, int32_t nbox)
         if (!boxes[i]) return fail(LBM_SC_EINVAL, "box " + std::to_string(i) + " is NULL");
         if (boxes[i]->stream != g->stream)
             return fail(LBM_SC_EINVAL, "box " + std::to_string(i) + " was not created on the group's stream");
+        if (boxes[i]->math64)
+            return fail(LBM_SC_EINVAL, "box " + std::to_string(i) +
+                                           ": groups take FP64 and FP32_SHIFTED boxes only");
         if (boxes[i]->fp32 != boxes[0]->fp32)
             return fail(LBM_SC_EINVAL, "all boxes of a group must share one precision");
         for (int j = 0; j < i; ++j)

@@ -45,9 +45,10 @@ def tune_group(group, steps=8, candidates=None, log=None):
 
 def box_candidates(nz):
     out = []
-    for rows, zc, pf, remap in itertools.product((1, 2, 4), (8, 16, 32, 64, 128), (0, 1), (0, 1)):
+    for waves, rows, zc, pf, remap in itertools.product((4, 8), (1, 2, 4), (8, 16, 32, 64, 128),
+                                                        (0, 1), (0, 1)):
         if zc <= max(nz, 8):
-            out.append(dict(rows=rows, z_chunk=zc, prefetch=pf, xcd_remap=remap))
+            out.append(dict(rows=rows, z_chunk=zc, prefetch=pf, xcd_remap=remap, waves=waves))
     return out
 
 
@@ -55,7 +56,8 @@ def tune_box(box, steps=16, candidates=None, log=None):
     """Same for one box (a paper_2105_08772_amd.Box)."""
     best = None
     for cand in candidates or box_candidates(box.dims[2]):
-        box.set_launch(cand["rows"], cand["z_chunk"], cand["xcd_remap"], cand["prefetch"])
+        box.set_launch(cand["rows"], cand["z_chunk"], cand["xcd_remap"], cand["prefetch"],
+                       cand["waves"])
         box.step(2)
         _sync()
         t0 = time.perf_counter()
@@ -67,5 +69,5 @@ def tune_box(box, steps=16, candidates=None, log=None):
         if best is None or t < best[0]:
             best = (t, cand)
     c = best[1]
-    box.set_launch(c["rows"], c["z_chunk"], c["xcd_remap"], c["prefetch"])
+    box.set_launch(c["rows"], c["z_chunk"], c["xcd_remap"], c["prefetch"], c["waves"])
     return dict(c, seconds_per_step=best[0])

@@ -109,8 +109,10 @@ def test_group_rejects_mixed_precision_and_foreign_streams():
     a = lbm.Box(lbm.config(8, 8, 8, radius=2.0, prec=lbm.LBM_SC_FP64, stream=s.cuda_stream))
     b = lbm.Box(lbm.config(8, 8, 8, radius=2.0, prec=lbm.LBM_SC_FP32_SHIFTED, stream=s.cuda_stream))
     c = lbm.Box(lbm.config(8, 8, 8, radius=2.0, prec=lbm.LBM_SC_FP64, stream=other.cuda_stream))
+    d = lbm.Box(lbm.config(8, 8, 8, radius=2.0, prec=lbm.LBM_SC_FP32_SHIFTED_MATH64,
+                           stream=s.cuda_stream))
     with lbm.Group(s.cuda_stream) as g:
-        for bad in ([a, b], [a, c], [a, a]):
+        for bad in ([a, b], [a, c], [a, a], [d]):
             with pytest.raises(lbm.LbmScError) as e:
                 g.set(bad)
             assert e.value.code == lbm.LBM_SC_EINVAL
@@ -118,5 +120,5 @@ def test_group_rejects_mixed_precision_and_foreign_streams():
             g.set_launch(workers=12)
         with pytest.raises(lbm.LbmScError):
             g.set_launch(graph_steps=3)
-    for x in (a, b, c):
+    for x in (a, b, c, d):
         x.close()

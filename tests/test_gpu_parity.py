@@ -6,6 +6,8 @@ Bars (written into each test):
   - FP32-shifted storage: one step from the identical (FP32-representable) state within a bound
     derived from single-precision rounding of the collision (a few ulp of the largest shifted
     population), and after 2000 steps densities within 1e-4 n_l and dP within 1e-3 of FP64;
+  - FP32-shifted storage with FP64 arithmetic: one step within half an ulp of the oracle per
+    stored population (the rest population within the sum of the others' rounding errors);
   - launch shapes: bitwise identical results (the per-node arithmetic does not depend on them).
 """
 import sys
@@ -75,7 +77,7 @@ def test_one_step_fp32_shifted(dims, tau, prefetch):
     with make_box(dims, prec=lbm.LBM_SC_FP32_SHIFTED, tau=tau, rho_ref=rho_ref) as b:
         b.set(f)
         lc = b.launch()
-        b.set_launch(lc["rows"], lc["z_chunk"], lc["xcd_remap"], prefetch)
+        b.set_launch(lc["rows"], lc["z_chunk"], lc["xcd_remap"], prefetch, lc["waves"])
         b.step(1)
         g = b.get()
     ref = core.step(f, G, tau, 0)
@@ -88,23 +90,60 @@ def test_one_step_fp32_shifted(dims, tau, prefetch):
     assert abs(n_g.sum() - n_r.sum()) / n_r.sum() < 1e-7
 
 
-@pytest.mark.parametrize("prec", [lbm.LBM_SC_FP64, lbm.LBM_SC_FP32_SHIFTED])
+@pytest.mark.parametrize("dims", [(4, 4, 4), (37, 29, 11), (130, 7, 6), (64, 40, 20)])
+@pytest.mark.parametrize("psi,ratio,tau", [(0, 1.3, 1.0), (1, 1.2, 0.8)])
+def test_one_step_fp32_storage_fp64_arithmetic(dims, psi, ratio, tau):
+    """FP32-shifted storage with FP64 arithmetic, one step from an identical state: each stored
+    population i > 0 is the oracle's value rounded once to single precision (within half an ulp
+    of it, plus 1e-12 max|f| for the different FP64 rounding orders); the rest population, closed
+    from the 18 rounded values, within the sum of their errors plus its own half ulp."""
+    say(f"one step FP32 storage / FP64 arithmetic dims={dims} psi={psi} tau={tau}")
+    rho_ref = 1.5
+    f = fp32_representable(inputs.random_populations(dims, 11 + sum(dims), W * 1.5, amp=0.3), rho_ref)
+    G = ratio * lbm.lbm_sc_gc(psi)
+    with make_box(dims, prec=lbm.LBM_SC_FP32_SHIFTED_MATH64, psi=psi, ratio=ratio, tau=tau,
+                  rho_ref=rho_ref) as b:
+        b.set(f)
+        b.step(1)
+        g = b.get()
+    ref = core.step(f, G, tau, psi)
+    shift = W.reshape(19, 1, 1, 1) * rho_ref
+    gs, rs = g - shift, ref - shift
+    slack = 1e-12 * np.abs(ref).max()
+    half_ulp = 0.5 * np.spacing(np.abs(rs).astype(np.float32)).astype(np.float64)
+    err = np.abs(gs - rs)
+    assert np.all(err[1:] <= half_ulp[1:] + slack)
+    # population i at node x was collided at x - xi_i: move the errors back to the colliding node
+    src_err = np.stack([np.roll(err[i], shift=(-XI[i, 2], -XI[i, 1], -XI[i, 0]), axis=(0, 1, 2))
+                        for i in range(1, 19)])
+    assert np.all(err[0] <= src_err.sum(axis=0) + half_ulp[0] + 19 * slack)
+    say(f"  max error / half ulp (i > 0): {float((err[1:] / (half_ulp[1:] + slack)).max()):.3f}")
+
+
+@pytest.mark.parametrize("prec", [lbm.LBM_SC_FP64, lbm.LBM_SC_FP32_SHIFTED,
+                                  lbm.LBM_SC_FP32_SHIFTED_MATH64])
 def test_launch_shapes_are_bitwise_identical(prec):
     say(f"launch shapes prec={prec}")
     dims = (70, 45, 33)
     rho_ref = 1.5
     f = fp32_representable(inputs.random_populations(dims, 3, W * 1.5, amp=0.3), rho_ref)
     outs = []
-    for rows, zc, remap, pf in ((1, 1, 0, 0), (2, 7, 1, 1), (4, 33, 1, 0), (4, 5, 0, 1),
-                                (1, 64, 1, 1), (2, 3, 0, 0)):
+    for rows, zc, remap, pf, waves in ((1, 1, 0, 0, 4), (2, 7, 1, 1, 4), (4, 33, 1, 0, 4),
+                                       (4, 5, 0, 1, 4), (1, 64, 1, 1, 4), (2, 3, 0, 0, 4),
+                                       (2, 9, 1, 0, 8), (4, 33, 0, 1, 8), (1, 2, 1, 1, 8)):
         with make_box(dims, prec=prec, rho_ref=rho_ref) as b:
             b.set(f)
-            b.set_launch(rows, zc, remap, pf)
-            assert b.launch() == dict(rows=rows, z_chunk=min(zc, 33), xcd_remap=remap, prefetch=pf)
+            b.set_launch(rows, zc, remap, pf, waves)
+            assert b.launch() == dict(rows=rows, z_chunk=min(zc, 33), xcd_remap=remap, prefetch=pf,
+                                      waves=waves)
             b.step(3)
             outs.append(b.get())
     for o in outs[1:]:
         assert np.array_equal(o, outs[0])
+    with make_box(dims, prec=prec, rho_ref=rho_ref) as b:
+        for bad in ((3, 4, 1, 0, 4), (2, 0, 1, 0, 4), (2, 4, 2, 0, 4), (2, 4, 1, 0, 6)):
+            with pytest.raises(lbm.LbmScError):
+                b.set_launch(*bad)
 
 
 def droplet_cfg(prec=lbm.LBM_SC_FP64, n=32, R=8.0, seed=1, noise=1e-6, geom=lbm.LBM_SC_DROPLET,
@@ -245,26 +284,27 @@ def test_slab_along_x_equals_slab_along_z():
 
 
 def test_fp32_vs_fp64_droplet_after_2000_steps():
-    """FP32-shifted populations against FP64 on the 32^3 droplet: densities within 1e-4 n_l and
-    dP within 1e-3 dP after 2000 steps."""
+    """FP32-shifted populations (single- or double-precision arithmetic) against FP64 on the 32^3
+    droplet: densities within 1e-4 n_l and dP within 1e-3 dP after 2000 steps."""
     say("32^3 droplet FP32-shifted vs FP64, 2000 steps")
     res = {}
-    for prec in (lbm.LBM_SC_FP64, lbm.LBM_SC_FP32_SHIFTED):
+    for prec in (lbm.LBM_SC_FP64, lbm.LBM_SC_FP32_SHIFTED, lbm.LBM_SC_FP32_SHIFTED_MATH64):
         with lbm.Box(droplet_cfg(prec=prec)) as b:
             b.step(2000)
             obs, prof = b.observables()
             n = b.get().sum(axis=0)
             res[prec] = (obs, prof, n, b.info())
     o64, _, n64, info = res[lbm.LBM_SC_FP64]
-    o32, _, n32, _ = res[lbm.LBM_SC_FP32_SHIFTED]
     nl = info["n_in"]
-    say("max |n32-n64| / n_l =", np.abs(n32 - n64).max() / nl,
-        " |dP32-dP64|/dP64 =", abs(o32["dP"] - o64["dP"]) / o64["dP"])
-    assert np.abs(n32 - n64).max() <= 1e-4 * nl
-    assert abs(o32["dP"] - o64["dP"]) <= 1e-3 * o64["dP"]
-    drift = abs(o32["mass"] - o32["mass0"]) / o32["mass0"]
-    say("FP32 relative mass drift after 2000 steps:", drift)
-    assert drift <= 2e-6
+    for prec in (lbm.LBM_SC_FP32_SHIFTED, lbm.LBM_SC_FP32_SHIFTED_MATH64):
+        o32, _, n32, _ = res[prec]
+        drift = abs(o32["mass"] - o32["mass0"]) / o32["mass0"]
+        say(f"prec {prec}: max |n32-n64| / n_l = {np.abs(n32 - n64).max() / nl:.3e}, "
+            f"|dP32-dP64|/dP64 = {abs(o32['dP'] - o64['dP']) / o64['dP']:.3e}, "
+            f"relative mass drift {drift:.3e}")
+        assert np.abs(n32 - n64).max() <= 1e-4 * nl
+        assert abs(o32["dP"] - o64["dP"]) <= 1e-3 * o64["dP"]
+        assert drift <= 2e-6
 
 
 def test_unstable_state_is_reported():
