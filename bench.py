@@ -13,7 +13,6 @@ timed on the host cores on a bounded sample of the same workload.
 """
 import argparse
 import hashlib
-import itertools
 import json
 import os
 import sys
@@ -101,7 +100,7 @@ def run_batched(args, torch, lbm, stream, steps, log):
     group.set(boxes)
     ginfo = group.info()
     log(f"# batched: {len(boxes)} boxes, {ginfo['nodes'] / 1e6:.1f} M nodes, tuning")
-    best = tune.tune_group(group, steps=8)
+    best = tune.tune_group(group, steps=8, log=lambda m: log("# " + m))
     group.set_launch(graph_steps=64)
     log(f"# batched: tuned {best}")
     # timed: `steps` steps of all boxes, FP64 observation of every box every 2048 steps
@@ -191,7 +190,7 @@ def run_served(args, torch, lbm, log):
     rate = args.served_rate
     spec = inputs.served_requests(seed=8772, count=args.served_count, rate=rate)
     be = serve.GpuBackend()
-    be.set_launch(rows=2, z_chunk=16, prefetch=0, persistent=1, workers=512, graph_steps=64)
+    be.set_launch(rows=2, z_chunk=16, prefetch=0, persistent=0, workers=0, graph_steps=64)
     budget = be.free_bytes() - (8 << 30)
     srv = serve.Server(be, budget, chunk=512, observe_every=2048, max_steps=100000,
                        dp_tol=1e-5, du_tol=1e-9, log=log)
@@ -263,30 +262,43 @@ def run_served(args, torch, lbm, log):
 def run_tolman(args, torch, lbm, log):
     """A scaled version of the paper's droplet/bubble sweep (Sec. 4): couplings G/G_c - 1 in
     {0.159, 0.215, 0.293}, odd box sizes L in {41, ..., 123}, R = L/4, droplets and
-    bubbles, exp psi, the paper's tanh profile (width 1), FP32-shifted populations, all boxes
-    served together until the paper's criterion (relative dP change < 1e-5 over 2048 steps). The
-    Tolman fit per coupling gives sigma_0 and delta; sigma_0 is compared with the flat value from
-    a converged FP64 slab (the paper reports that the two agree)."""
+    bubbles, exp psi, the paper's tanh profile (width 1), all boxes served together until the
+    paper's criterion (relative dP change < 1e-5 over 2048 steps), once with FP32-shifted and
+    once with FP64 populations. The Tolman fit per coupling gives sigma_0 and delta; sigma_0 is
+    compared with the flat value from a converged FP64 slab (the paper reports that the two
+    agree), and every FP32 result (dP, sigma_s, R_s, and the fitted sigma_0 and delta) is stated
+    against its FP64 counterpart."""
     from paper_2105_08772_amd import analysis, serve
     ratios = (1.159, 1.215, 1.293)
     sizes = (41, 47, 55, 61, 67, 77, 87, 103, 123)
-    be = serve.GpuBackend(width=1.0)
-    be.set_launch(rows=2, z_chunk=16, prefetch=0, persistent=1, workers=512, graph_steps=64)
-    srv = serve.Server(be, be.free_bytes() - (8 << 30), chunk=512, observe_every=2048,
-                       max_steps=100000, dp_tol=1e-5, du_tol=0.0, log=log)
     spec = {}
     rid = 0
     for g in ratios:
         for L in sizes:
             for bubble in (False, True):
                 spec[rid] = dict(g_over_gc=g, L=L, bubble=bubble)
-                srv.submit(serve.Request(rid=rid, L=L, radius=L / 4.0, g_over_gc=g, bubble=bubble,
-                                         seed=1000 + rid, arrival=0.0))
                 rid += 1
-    recs = srv.run()
-    be.close()
-    runs = [dict(spec[r.rid], obs=r.obs) for r in recs if r.status == "converged"]
-    fits = analysis.analyse(runs)
+
+    def sweep(prec):
+        be = serve.GpuBackend(prec=prec, width=1.0)
+        be.set_launch(rows=2, z_chunk=16, prefetch=0, persistent=0, workers=0, graph_steps=64)
+        srv = serve.Server(be, be.free_bytes() - (8 << 30), chunk=512, observe_every=2048,
+                           max_steps=100000, dp_tol=1e-5, du_tol=0.0, log=log)
+        for k, v in spec.items():
+            srv.submit(serve.Request(rid=k, L=v["L"], radius=v["L"] / 4.0,
+                                     g_over_gc=v["g_over_gc"], bubble=v["bubble"],
+                                     seed=1000 + k, arrival=0.0))
+        recs = srv.run()
+        be.close()
+        torch.cuda.empty_cache()
+        conv = {r.rid: r for r in recs if r.status == "converged"}
+        fits = analysis.analyse([dict(spec[k], obs=r.obs) for k, r in conv.items()])
+        return srv, conv, fits
+
+    res = {}
+    for name, prec in (("fp32", lbm.LBM_SC_FP32_SHIFTED), ("fp64", lbm.LBM_SC_FP64)):
+        log(f"tolman sweep {name}")
+        res[name] = sweep(prec)
     # flat sigma_0: FP64 slab 4 x 4 x 64, liquid thickness 32, width 1, 40000 steps
     stream = torch.cuda.Stream()
     flat = {}
@@ -297,12 +309,17 @@ def run_tolman(args, torch, lbm, log):
             b.step(40000)
             o, _ = b.observables()
         flat[g] = dict(sigma0=o["sigma0_flat"], pn_spread_rel=o["pn_spread"] / o["P_out"])
+    srv32, conv32, fits32 = res["fp32"]
+    srv64, conv64, fits64 = res["fp64"]
     out = {"workload": "G/G_c-1 in {0.159,0.215,0.293} x L in {41,47,55,61,67,77,87,103,123} x "
-                       "{droplet,bubble}, R=L/4, tanh width 1, exp psi, FP32-shifted, served "
-                       "together until |dP change|/dP < 1e-5 per 2048 steps",
-           "wall_s": round(srv.wall, 2), "statuses": srv.summary()["statuses"], "couplings": {}}
+                       "{droplet,bubble}, R=L/4, tanh width 1, exp psi, served together until "
+                       "|dP change|/dP < 1e-5 per 2048 steps; FP32-shifted and FP64 sweeps",
+           "wall_s": {"fp32": round(srv32.wall, 2), "fp64": round(srv64.wall, 2)},
+           "statuses": {"fp32": srv32.summary()["statuses"], "fp64": srv64.summary()["statuses"]},
+           "couplings": {}}
     for g in ratios:
-        f = fits.get(round(g, 10))
+        f = fits32.get(round(g, 10))
+        f64 = fits64.get(round(g, 10))
         entry = {"flat_sigma0": flat[g]["sigma0"], "flat_pn_spread_rel": flat[g]["pn_spread_rel"]}
         if f:
             entry.update({k: f[k] for k in ("sigma0", "delta", "rms", "npoints", "delta_hat0",
@@ -311,16 +328,35 @@ def run_tolman(args, torch, lbm, log):
             entry["points"] = [dict(kappa=round(p["kappa"], 6), sigma_s=round(p["sigma_s"], 8),
                                     R_s=round(p["R_s"], 4), R_e=round(p["R_e"], 4),
                                     bubble=p["bubble"]) for p in f["points"]]
+        if f and f64:
+            entry["fp64"] = {k: f64[k] for k in ("sigma0", "delta", "delta_hat0", "npoints")}
+            entry["sigma0_rel_err_fp32_vs_fp64"] = abs(f["sigma0"] - f64["sigma0"]) / f64["sigma0"]
+            entry["delta_err_fp32_vs_fp64"] = abs(f["delta"] - f64["delta"])
+        # per run, where both precisions converged
+        errs = {"dP": [], "sigma_s": [], "R_s": []}
+        for k in sorted(set(conv32) & set(conv64)):
+            if spec[k]["g_over_gc"] != g:
+                continue
+            a, b = conv32[k].obs, conv64[k].obs
+            if not (a["R_s"] > 0 and b["R_s"] > 0):
+                continue
+            errs["dP"].append(abs(a["dP"] - b["dP"]) / abs(b["dP"]))
+            sa, sb = 0.5 * a["dP"] * a["R_s"], 0.5 * b["dP"] * b["R_s"]
+            errs["sigma_s"].append(abs(sa - sb) / abs(sb))
+            errs["R_s"].append(abs(a["R_s"] - b["R_s"]) / b["R_s"])
+        entry["per_run_rel_err_fp32_vs_fp64"] = {
+            k: {"max": max(v), "median": sorted(v)[len(v) // 2], "runs": len(v)}
+            for k, v in errs.items() if v}
         out["couplings"][str(g)] = entry
-    gs = [g for g in ratios if fits.get(round(g, 10))]
+    gs = [g for g in ratios if fits32.get(round(g, 10))]
     if len(gs) >= 2:
         x = [g - 1 for g in gs]
         out["sigma0_exponent"] = analysis.scaling_exponent(
-            x, [fits[round(g, 10)]["sigma0"] for g in gs])["exponent"]
+            x, [fits32[round(g, 10)]["sigma0"] for g in gs])["exponent"]
         out["flat_sigma0_exponent"] = analysis.scaling_exponent(x, [flat[g]["sigma0"] for g in gs])["exponent"]
-        if all(fits[round(g, 10)]["delta"] > 0 for g in gs):
+        if all(fits32[round(g, 10)]["delta"] > 0 for g in gs):
             out["delta_exponent"] = analysis.scaling_exponent(
-                x, [fits[round(g, 10)]["delta"] for g in gs])["exponent"]
+                x, [fits32[round(g, 10)]["delta"] for g in gs])["exponent"]
     return out
 
 
@@ -369,6 +405,7 @@ def main():
     ap.add_argument("--remap", type=int, default=-1)
     ap.add_argument("--prefetch", type=int, default=-1)
     ap.add_argument("--waves", type=int, default=0)
+    ap.add_argument("--tile-x", type=int, default=0)
     ap.add_argument("--tune", action="store_true", help="sweep launch shapes, keep the fastest")
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
@@ -435,25 +472,26 @@ def main():
     tuned = None
     if args.tune:
         best = None
-        for waves, rows, zc, remap, pf in itertools.product(
-                (4, 8), (1, 2, 4), (8, 16, 32, 64, 128), (0, 1), (0, 1)):
-            box.set_launch(rows, zc, remap, pf, waves)
+        from paper_2105_08772_amd import tune
+        for c in tune.box_candidates(L):
+            box.set_launch(c["rows"], c["z_chunk"], c["xcd_remap"], c["prefetch"], c["waves"],
+                           c["tile_x"])
             box.step(8)
             t = time_steps(64)
-            print(f"# tune waves={waves} rows={rows} zchunk={zc} remap={remap} prefetch={pf} "
-                  f"{nodes / t / 1e6:.0f} MLUPS {bytes_per_step / t / 1e9:.0f} GB/s",
+            print(f"# tune {c} {nodes / t / 1e6:.0f} MLUPS {bytes_per_step / t / 1e9:.0f} GB/s",
                   file=sys.stderr, flush=True)
             if best is None or t < best[0]:
-                best = (t, rows, zc, remap, pf, waves)
-        tuned = dict(rows=best[1], z_chunk=best[2], xcd_remap=best[3], prefetch=best[4],
-                     waves=best[5])
-        box.set_launch(*best[1:])
-    if args.rows or args.zchunk or args.remap >= 0 or args.prefetch >= 0 or args.waves:
+                best = (t, c)
+        tuned = best[1]
+        box.set_launch(tuned["rows"], tuned["z_chunk"], tuned["xcd_remap"], tuned["prefetch"],
+                       tuned["waves"], tuned["tile_x"])
+    if (args.rows or args.zchunk or args.remap >= 0 or args.prefetch >= 0 or args.waves
+            or args.tile_x):
         lc = box.launch()
         box.set_launch(args.rows or lc["rows"], args.zchunk or lc["z_chunk"],
                        args.remap if args.remap >= 0 else lc["xcd_remap"],
                        args.prefetch if args.prefetch >= 0 else lc["prefetch"],
-                       args.waves or lc["waves"])
+                       args.waves or lc["waves"], args.tile_x or lc["tile_x"])
     info = box.info()
     launch = box.launch()
 
@@ -509,7 +547,7 @@ def main():
                         f" noise 1e-6 seed 3, tau=1, FP64 observables every {args.observe_every}"
                         f" steps",
             "nodes": nodes,
-            "launch": dict(launch, block=[64, launch["waves"] * launch["rows"]],
+            "launch": dict(launch, block=[info["block_x"], info["block_y"]],
                            tuned=tuned is not None),
         },
         "roofline": {

@@ -151,14 +151,17 @@ int lbm_sc_get_populations(lbm_sc* h, double* f, size_t len);
 int lbm_sc_set_populations(lbm_sc* h, const double* f, size_t len);
 
 /* Launch shape of the fused step kernel. The workgroup is 64*waves threads (waves wave64s) and
- * owns an x-y tile of 64 x (waves*rows) nodes and a run of z_chunk planes along z. */
+ * owns an x-y tile tile_x nodes wide and waves*rows*(64/tile_x) rows high (at tile_x = 32 each
+ * wave row covers two rows of 32 nodes), and a run of z_chunk planes along z. Supported shapes:
+ * waves 4 with rows 1, 2 or 4 (rows 1 or 2 at tile_x 32) and either prefetch setting; waves 8
+ * with rows 1 or 2 and prefetch 0. */
 typedef struct {
     int32_t rows;       /* tile rows per wave: 1, 2 or 4 */
     int32_t z_chunk;    /* planes per workgroup, >= 1 (clamped to nz) */
     int32_t xcd_remap;  /* 1: hand neighbouring tiles to the same XCD (shared L2); 0: identity */
     int32_t prefetch;   /* 1: issue the next plane's loads before the collision of the current one */
     int32_t waves;      /* wave64s per workgroup: 4 or 8 */
-    int32_t reserved;   /* must be 0 */
+    int32_t tile_x;     /* tile width: 64 or 32 */
 } lbm_sc_launch;
 
 /* Set / read the launch shape. The shape changes only the schedule: every node's arithmetic and
@@ -183,7 +186,7 @@ int lbm_sc_get_launch(lbm_sc* h, lbm_sc_launch* out);
 typedef struct lbm_sc_group lbm_sc_group;
 
 typedef struct {
-    int32_t rows;        /* tile rows per wave: 1, 2 or 4 (tile 64 x 4*rows) */
+    int32_t rows;        /* tile rows per wave (supported tile shapes as for lbm_sc_launch) */
     int32_t z_chunk;     /* planes per work item, >= 1 (clamped to each box's nz) */
     int32_t xcd_remap;   /* non-persistent launch: hand neighbouring items to the same XCD */
     int32_t prefetch;    /* issue the next plane's loads before the current collision */
@@ -191,6 +194,8 @@ typedef struct {
                             work queues; 0: one workgroup per item */
     int32_t workers;     /* persistent grid size, a multiple of 8 (0 = 256) */
     int32_t graph_steps; /* steps captured per hipGraph and replayed (even, 0 = no graph) */
+    int32_t waves;       /* wave64s per workgroup: 4 or 8 */
+    int32_t tile_x;      /* tile width: 64 or 32 */
     int32_t reserved;    /* must be 0 */
 } lbm_sc_group_launch;
 

@@ -1,6 +1,7 @@
 // Device kernels of the Shan-Chen D3Q19 lattice Boltzmann library (gfx950).
 //
-// Population storage: SoA, population i of node (x, y, z) at i * stride + (z * ny + y) * nx + x.
+// Population storage: SoA, population i of node (x, y, z) at i * stride + (z * ny + y) * px + x,
+// with the row pitch px >= nx a whole number of 128-byte lines (the padding is never read).
 // The stored arrays hold the post-collision populations of the previous step, f*_i(x, t - 1), so
 // the pre-collision state of time t is the pull f_i(x, t) = f*_i(x - xi_i, t - 1) (Eq. lbm of
 // arXiv:2105.08772 read as pull streaming). FP32 storage keeps g_i = f_i - w_i rho_ref.
@@ -9,7 +10,7 @@
 //   pull the 19 populations -> density n and momentum j -> psi(n) -> Shan-Chen force F from the
 //   psi of the 18 neighbours (Eq. SCForce) -> u_eq = (j + F/2)/n -> BGK relaxation to the
 //   second-order equilibrium plus the Guo term -> store. psi at the neighbours is needed at the
-//   same time level, so each workgroup owns a 64 x (4 rows) x-y tile, marches up a chunk of
+//   same time level, so each workgroup owns an x-y tile (64 or 32 nodes wide), marches up a chunk of
 //   z-planes, pulls the densities of its tile plus a one-node x-y halo into an LDS ring of four
 //   psi planes, and collides plane q once the psi of plane q + 1 is in LDS. Only the xy halo
 //   and the two end planes of each chunk are pulled twice; the repeated reads are meant to hit
@@ -22,12 +23,17 @@
 namespace lbm {
 namespace {
 
-constexpr int BX = 64;       // tile width = one wave64 row
 
 __device__ __forceinline__ int wrapi(int v, int L)
 {
     int r = v % L;
     return r < 0 ? r + L : r;
+}
+
+// Stored (pitched) index of node (x, y, z) within one population array.
+__device__ __forceinline__ unsigned stored_index(const BoxDesc& b, int x, int y, int z)
+{
+    return ((unsigned)z * (unsigned)b.ny + (unsigned)y) * b.px + (unsigned)x;
 }
 
 template <typename T, int PSI>
@@ -225,59 +231,81 @@ __device__ __forceinline__ void collide_store(const PopBuf& dst, unsigned off, C
     bstore<T, 0>(dst, off, (T)(dn64 - sum));
 }
 
-// LDS ring of four psi planes of a (64 + 2) x (waves * rows + 2) tile, shared by the single-box and
-// the multi-box kernels.
-template <typename T, int R, int WAVES>
+// Tile of a workgroup of WAVES wave64s: BXT (64 or 32) nodes wide; each wave covers R rows of
+// 64 / BXT sub-rows, so the tile is WAVES * R * 64 / BXT rows high.
+template <int R, int WAVES, int BXT>
+constexpr int tile_rows()
+{
+    static_assert(BXT == 64 || BXT == 32, "tile width is 64 or 32");
+    return WAVES * R * (64 / BXT);
+}
+
+// LDS ring of four psi planes of a (BXT + 2) x (BY + 2) tile, shared by the single-box and the
+// multi-box kernels.
+template <typename T, int BXT, int BY>
 struct Ring {
-    static constexpr int BY = WAVES * R;
-    static constexpr int LX = BX + 2, LY = BY + 2;
+    static constexpr int LX = BXT + 2, LY = BY + 2;
     T v[4][LY][LX];
 };
+template <typename T, int R, int WAVES, int BXT>
+using RingOf = Ring<T, BXT, tile_rows<R, WAVES, BXT>()>;
 
 // One workgroup's share of a step: the tile (tix, tiy) of box b, planes [z0, z1), populations
 // stored as T, arithmetic in C (C = T, or T = float with C = double). The caller provides the LDS
 // ring; the routine ends with every thread past its last read of the ring.
-template <typename T, typename C, int PSI, bool TAU1, int R, bool PF, int WAVES>
+template <typename T, typename C, int PSI, bool TAU1, int R, bool PF, int WAVES, int BXT>
 __device__ __forceinline__ void step_tile(const BoxDesc& bd, const T* __restrict__ src,
                                           T* __restrict__ dst, int tix, int tiy, int z0, int z1,
-                                          Ring<C, R, WAVES>& rg)
+                                          RingOf<C, R, WAVES, BXT>& rg)
 {
     constexpr int NT = 64 * WAVES;
-    constexpr int BY = WAVES * R;
-    constexpr int LX = BX + 2;
+    constexpr int SUB = 64 / BXT;
+    constexpr int BY = tile_rows<R, WAVES, BXT>();
+    constexpr int LX = BXT + 2;
     constexpr int NH = 2 * LX + 2 * BY;
     static_assert(NH <= NT, "halo ring larger than the workgroup");
     auto& ring = rg.v;
 
     const int nx = bd.nx, ny = bd.ny, nz = bd.nz;
-    const unsigned nxy = bd.nxy;
+    const unsigned pxy = bd.pxy;
     const PopBuf sbuf = make_popbuf(src, bd.stride);
     const PopBuf dbuf = make_popbuf(dst, bd.stride);
     const C rho_ref = (C)bd.rho_ref;
     const C G = (C)bd.G;
     const C inv_tau = (C)(1.0 / bd.tau);
     const C guo_pref = (C)(1.0 - 0.5 / bd.tau);
-    const int x0 = tix * BX, y0 = tiy * BY;
+    const int x0 = tix * BXT, y0 = tiy * BY;
 
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
+    // lane -> (column lc, sub-row ls) of the wave's rows; row r of the wave is tile row
+    // (wv * R + r) * SUB + ls
+    const int lc = lane % BXT, ls = lane / BXT;
 
-    // The thread's own column; lanes past the box edge wrap and only feed psi to the LDS ring.
+    // The thread's own column. In the last tile of a row, the lane at x = nx pulls node 0 (the
+    // east neighbour of node nx - 1, wrapped) and only feeds psi to the LDS ring; lanes beyond it
+    // load nothing. Lanes in the row's padding (nx <= x < px) store values nobody reads, so that
+    // the row's last 128-byte line is written whole.
     constexpr unsigned E = sizeof(T);
-    const bool xin = x0 + lane < nx;
-    const int x = wrapi(x0 + lane, nx);
+    const unsigned rowb = bd.px * E;
+    const int xg = x0 + lc;
+    const bool xload = xg <= nx;
+    const bool xstore = xg < (int)bd.px;
+    const int x = wrapi(xg, nx);
     const unsigned xo[3] = {(unsigned)wrapi(x - 1, nx) * E, (unsigned)x * E,
                             (unsigned)wrapi(x + 1, nx) * E};
+    const unsigned xso = (unsigned)xg * E;
     unsigned yo[R][3];
-    bool yin[R];
+    bool yin[R], ld[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        const int yg = y0 + wv * R + r;
+        const int yg = y0 + (wv * R + r) * SUB + ls;
         yin[r] = yg < ny;
+        ld[r] = xload && yg <= ny;   // the row at y = ny is row 0, the north neighbour of ny - 1
         const int y = wrapi(yg, ny);
-        yo[r][0] = (unsigned)wrapi(y - 1, ny) * (unsigned)nx * E;
-        yo[r][1] = (unsigned)y * (unsigned)nx * E;
-        yo[r][2] = (unsigned)wrapi(y + 1, ny) * (unsigned)nx * E;
+        yo[r][0] = (unsigned)wrapi(y - 1, ny) * rowb;
+        yo[r][1] = (unsigned)y * rowb;
+        yo[r][2] = (unsigned)wrapi(y + 1, ny) * rowb;
     }
 
     // Halo node of this thread (ring position hx, hy in LDS coordinates), if any.
@@ -294,20 +322,19 @@ __device__ __forceinline__ void step_tile(const BoxDesc& bd, const T* __restrict
         hx = 0;
         hy = 1 + (t - 2 * LX);
     } else {
-        hx = BX + 1;
+        hx = BXT + 1;
         hy = 1 + (t - 2 * LX - BY);
     }
     const int hxg = wrapi(x0 - 1 + hx, nx), hyg = wrapi(y0 - 1 + hy, ny);
     const unsigned hxo[3] = {(unsigned)wrapi(hxg - 1, nx) * E, (unsigned)hxg * E,
                              (unsigned)wrapi(hxg + 1, nx) * E};
-    const unsigned hyo[3] = {(unsigned)wrapi(hyg - 1, ny) * (unsigned)nx * E,
-                             (unsigned)hyg * (unsigned)nx * E,
-                             (unsigned)wrapi(hyg + 1, ny) * (unsigned)nx * E};
+    const unsigned hyo[3] = {(unsigned)wrapi(hyg - 1, ny) * rowb, (unsigned)hyg * rowb,
+                             (unsigned)wrapi(hyg + 1, ny) * rowb};
 
     auto plane_offsets = [&](int p, unsigned (&zo)[3]) {
-        zo[0] = (unsigned)wrapi(p - 1, nz) * nxy * E;
-        zo[1] = (unsigned)wrapi(p, nz) * nxy * E;
-        zo[2] = (unsigned)wrapi(p + 1, nz) * nxy * E;
+        zo[0] = (unsigned)wrapi(p - 1, nz) * pxy * E;
+        zo[1] = (unsigned)wrapi(p, nz) * pxy * E;
+        zo[2] = (unsigned)wrapi(p + 1, nz) * pxy * E;
     };
 
     // Raw populations of the plane being reduced. With PF the loads of plane k + 1 are issued
@@ -315,6 +342,10 @@ __device__ __forceinline__ void step_tile(const BoxDesc& bd, const T* __restrict
     // collision of plane k - 1.
     T fr[R][Q];
     T fh[Q];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int i = 0; i < Q; ++i) fr[r][i] = T(0);
     double pdn[R];
     C pjx[R], pjy[R], pjz[R];
     unsigned pzo[3] = {0u, 0u, 0u};
@@ -323,7 +354,8 @@ __device__ __forceinline__ void step_tile(const BoxDesc& bd, const T* __restrict
         unsigned zo[3];
         plane_offsets(z0 - 1, zo);
 #pragma unroll
-        for (int r = 0; r < R; ++r) load_node(sbuf, zo, yo[r], xo, fr[r]);
+        for (int r = 0; r < R; ++r)
+            if (ld[r]) load_node(sbuf, zo, yo[r], xo, fr[r]);
         if (has_halo) load_node(sbuf, zo, hyo, hxo, fh);
     }
     for (int k = 0; k < nplanes; ++k) {
@@ -335,9 +367,11 @@ __device__ __forceinline__ void step_tile(const BoxDesc& bd, const T* __restrict
         C cjx[R], cjy[R], cjz[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            if constexpr (!PF) load_node(sbuf, zo, yo[r], xo, fr[r]);
+            if constexpr (!PF) {
+                if (ld[r]) load_node(sbuf, zo, yo[r], xo, fr[r]);
+            }
             moments(fr[r], cdn[r], cjx[r], cjy[r], cjz[r]);
-            slot[wv * R + r + 1][lane + 1] = psi_of<C, PSI>(rho_ref + (C)cdn[r]);
+            slot[(wv * R + r) * SUB + ls + 1][lc + 1] = psi_of<C, PSI>(rho_ref + (C)cdn[r]);
         }
         if (has_halo) {
             double hdn;
@@ -351,7 +385,8 @@ __device__ __forceinline__ void step_tile(const BoxDesc& bd, const T* __restrict
                 unsigned zn[3];
                 plane_offsets(p + 1, zn);
 #pragma unroll
-                for (int r = 0; r < R; ++r) load_node(sbuf, zn, yo[r], xo, fr[r]);
+                for (int r = 0; r < R; ++r)
+                    if (ld[r]) load_node(sbuf, zn, yo[r], xo, fr[r]);
                 if (has_halo) load_node(sbuf, zn, hyo, hxo, fh);
             }
         }
@@ -361,12 +396,12 @@ __device__ __forceinline__ void step_tile(const BoxDesc& bd, const T* __restrict
             const C(*pm)[LX] = ring[(k - 2) & 3];
             const C(*pc)[LX] = ring[(k - 1) & 3];
             const C(*pp)[LX] = ring[k & 3];
-            const unsigned qoff = (unsigned)(p - 1) * nxy * E;
-            const int lx = lane + 1;
+            const unsigned qoff = (unsigned)(p - 1) * pxy * E;
+            const int lx = lc + 1;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                if (!(xin && yin[r])) continue;
-                const int ly = wv * R + r + 1;
+                if (!(xstore && yin[r])) continue;
+                const int ly = (wv * R + r) * SUB + ls + 1;
                 const C c_e = pc[ly][lx + 1], c_w = pc[ly][lx - 1];
                 const C c_n = pc[ly + 1][lx], c_s = pc[ly - 1][lx];
                 const C c_ne = pc[ly + 1][lx + 1], c_nw = pc[ly + 1][lx - 1];
@@ -386,7 +421,7 @@ __device__ __forceinline__ void step_tile(const BoxDesc& bd, const T* __restrict
                 const C Sz = w1 * (p_c - m_c) +
                              w2 * ((p_e - m_e) + (p_w - m_w) + (p_n - m_n) + (p_s - m_s));
                 const C gp = -G * psi0;
-                const unsigned off = qoff + yo[r][1] + xo[1];
+                const unsigned off = qoff + yo[r][1] + xso;
                 if constexpr (TAU1) {
                     collide_store<T, C, true>(dbuf, off, rho_ref, pdn[r], pjx[r], pjy[r], pjz[r],
                                               gp * Sx, gp * Sy, gp * Sz, inv_tau, guo_pref,
@@ -415,11 +450,11 @@ __device__ __forceinline__ void step_tile(const BoxDesc& bd, const T* __restrict
     }
 }
 
-template <typename T, typename C, int PSI, bool TAU1, int R, bool PF, int WAVES>
+template <typename T, typename C, int PSI, bool TAU1, int R, bool PF, int WAVES, int BXT>
 __global__ __launch_bounds__(64 * WAVES) void k_step(StepArgs a, const T* __restrict__ src,
                                                      T* __restrict__ dst)
 {
-    __shared__ Ring<C, R, WAVES> ring;
+    __shared__ RingOf<C, R, WAVES, BXT> ring;
     const unsigned logical = a.remap ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
     const int tix = (int)(logical % (unsigned)a.tiles_x);
     const unsigned t2 = logical / (unsigned)a.tiles_x;
@@ -427,7 +462,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_step(StepArgs a, const T* __rest
     const int ch = (int)(t2 / (unsigned)a.tiles_y);
     const int z0 = ch * a.zc;
     const int z1 = min(z0 + a.zc, a.b.nz);
-    step_tile<T, C, PSI, TAU1, R, PF, WAVES>(a.b, src, dst, tix, tiy, z0, z1, ring);
+    step_tile<T, C, PSI, TAU1, R, PF, WAVES, BXT>(a.b, src, dst, tix, tiy, z0, z1, ring);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -437,9 +472,10 @@ __global__ __launch_bounds__(64 * WAVES) void k_step(StepArgs a, const T* __rest
 // (rows, prefetch) is shared. Box b reads pop[(phase_b + parity) & 1] and writes the other.
 // ------------------------------------------------------------------------------------------
 
-template <typename T, int R, bool PF, int WAVES>
+template <typename T, int R, bool PF, int WAVES, int BXT>
 __device__ __forceinline__ void group_item(const GroupBox* __restrict__ boxes, int nbox,
-                                           unsigned item, int parity, Ring<T, R, WAVES>& ring)
+                                           unsigned item, int parity,
+                                           RingOf<T, R, WAVES, BXT>& ring)
 {
     // box of the item: last box whose first item is <= item
     int lo = 0, hi = nbox - 1;
@@ -461,22 +497,22 @@ __device__ __forceinline__ void group_item(const GroupBox* __restrict__ boxes, i
     T* dst = (T*)g.pop[1 - s];
     const bool tau1 = g.b.tau == 1.0;
     if (g.b.psi == 0) {
-        if (tau1) step_tile<T, T, 0, true, R, PF, WAVES>(g.b, src, dst, tix, tiy, z0, z1, ring);
-        else step_tile<T, T, 0, false, R, PF, WAVES>(g.b, src, dst, tix, tiy, z0, z1, ring);
+        if (tau1) step_tile<T, T, 0, true, R, PF, WAVES, BXT>(g.b, src, dst, tix, tiy, z0, z1, ring);
+        else step_tile<T, T, 0, false, R, PF, WAVES, BXT>(g.b, src, dst, tix, tiy, z0, z1, ring);
     } else {
-        if (tau1) step_tile<T, T, 1, true, R, PF, WAVES>(g.b, src, dst, tix, tiy, z0, z1, ring);
-        else step_tile<T, T, 1, false, R, PF, WAVES>(g.b, src, dst, tix, tiy, z0, z1, ring);
+        if (tau1) step_tile<T, T, 1, true, R, PF, WAVES, BXT>(g.b, src, dst, tix, tiy, z0, z1, ring);
+        else step_tile<T, T, 1, false, R, PF, WAVES, BXT>(g.b, src, dst, tix, tiy, z0, z1, ring);
     }
 }
 
 // One workgroup per work item (the hardware dispatcher balances the uneven items).
-template <typename T, int R, bool PF, int WAVES = 4>
+template <typename T, int R, bool PF, int WAVES, int BXT>
 __global__ __launch_bounds__(64 * WAVES) void k_step_group(const GroupBox* __restrict__ boxes,
                                                            int nbox, int parity, int remap)
 {
-    __shared__ Ring<T, R, WAVES> ring;
+    __shared__ RingOf<T, R, WAVES, BXT> ring;
     const unsigned item = remap ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
-    group_item<T, R, PF, WAVES>(boxes, nbox, item, parity, ring);
+    group_item<T, R, PF, WAVES, BXT>(boxes, nbox, item, parity, ring);
 }
 
 // Persistent variant: a fixed grid whose workgroups take items from eight work queues, one per
@@ -485,11 +521,11 @@ __global__ __launch_bounds__(64 * WAVES) void k_step_group(const GroupBox* __res
 // draws tickets until its queue is exhausted; the last workgroup to finish clears the queues and
 // the finish counter for the next launch, so the kernel needs no host-side reset and can be
 // replayed from a captured graph.
-template <typename T, int R, bool PF, int WAVES = 4>
+template <typename T, int R, bool PF, int WAVES, int BXT>
 __global__ __launch_bounds__(64 * WAVES) void k_step_group_persistent(
     const GroupBox* __restrict__ boxes, int nbox, int parity, QueueState* __restrict__ q)
 {
-    __shared__ Ring<T, R, WAVES> ring;
+    __shared__ RingOf<T, R, WAVES, BXT> ring;
     __shared__ unsigned ticket;
     const unsigned xcd = blockIdx.x % 8u;
     const unsigned begin = q->range[xcd], end = q->range[xcd + 1];
@@ -499,7 +535,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_step_group_persistent(
         const unsigned item = ticket;
         __syncthreads();
         if (item >= end) break;
-        group_item<T, R, PF, WAVES>(boxes, nbox, item, parity, ring);
+        group_item<T, R, PF, WAVES, BXT>(boxes, nbox, item, parity, ring);
         __syncthreads();  // the next item rewrites the LDS ring
     }
     if (threadIdx.x == 0) {
@@ -513,35 +549,43 @@ __global__ __launch_bounds__(64 * WAVES) void k_step_group_persistent(
     }
 }
 
-template <typename T, typename C, int PSI, bool TAU1, int R, bool PF, int WAVES>
+template <typename T, typename C, int PSI, bool TAU1, int R, bool PF, int WAVES, int BXT>
 hipError_t launch_step_t(const StepArgs& a, const void* src, void* dst, hipStream_t st)
 {
     const unsigned grid = (unsigned)(a.tiles_x * a.tiles_y * a.nchunks);
-    hipLaunchKernelGGL((k_step<T, C, PSI, TAU1, R, PF, WAVES>), dim3(grid), dim3(64 * WAVES), 0,
-                       st, a, (const T*)src, (T*)dst);
+    hipLaunchKernelGGL((k_step<T, C, PSI, TAU1, R, PF, WAVES, BXT>), dim3(grid), dim3(64 * WAVES),
+                       0, st, a, (const T*)src, (T*)dst);
     return hipGetLastError();
 }
 
-template <typename T, typename C, int PSI, bool TAU1, bool PF, int WAVES>
-hipError_t dispatch_rows(int rows, const StepArgs& a, const void* src, void* dst, hipStream_t st)
-{
-    switch (rows) {
-        case 1: return launch_step_t<T, C, PSI, TAU1, 1, PF, WAVES>(a, src, dst, st);
-        case 2: return launch_step_t<T, C, PSI, TAU1, 2, PF, WAVES>(a, src, dst, st);
-        case 4: return launch_step_t<T, C, PSI, TAU1, 4, PF, WAVES>(a, src, dst, st);
-        default: return hipErrorInvalidValue;
-    }
-}
-
+// Supported launch shapes (checked by shape_supported): 4 waves with rows 1, 2 or 4 and either
+// prefetch setting; 8 waves with rows 1 or 2 and no prefetch; tile width 32 with rows 1 or 2.
 template <typename T, typename C, int PSI, bool TAU1>
 hipError_t dispatch_pf(const StepShape& s, const StepArgs& a, const void* src, void* dst,
                        hipStream_t st)
 {
-    if (s.waves == 8)
-        return s.prefetch ? dispatch_rows<T, C, PSI, TAU1, true, 8>(s.rows, a, src, dst, st)
-                          : dispatch_rows<T, C, PSI, TAU1, false, 8>(s.rows, a, src, dst, st);
-    return s.prefetch ? dispatch_rows<T, C, PSI, TAU1, true, 4>(s.rows, a, src, dst, st)
-                      : dispatch_rows<T, C, PSI, TAU1, false, 4>(s.rows, a, src, dst, st);
+#define LBM_STEP(R, PF, WV, BXT) launch_step_t<T, C, PSI, TAU1, R, PF, WV, BXT>(a, src, dst, st)
+    if (s.waves == 8) {
+        if (s.tile_x == 32) return s.rows == 1 ? LBM_STEP(1, false, 8, 32) : LBM_STEP(2, false, 8, 32);
+        return s.rows == 1 ? LBM_STEP(1, false, 8, 64) : LBM_STEP(2, false, 8, 64);
+    }
+    if (s.tile_x == 32) {
+        if (s.prefetch) return s.rows == 1 ? LBM_STEP(1, true, 4, 32) : LBM_STEP(2, true, 4, 32);
+        return s.rows == 1 ? LBM_STEP(1, false, 4, 32) : LBM_STEP(2, false, 4, 32);
+    }
+    if (s.prefetch) {
+        switch (s.rows) {
+            case 1: return LBM_STEP(1, true, 4, 64);
+            case 2: return LBM_STEP(2, true, 4, 64);
+            default: return LBM_STEP(4, true, 4, 64);
+        }
+    }
+    switch (s.rows) {
+        case 1: return LBM_STEP(1, false, 4, 64);
+        case 2: return LBM_STEP(2, false, 4, 64);
+        default: return LBM_STEP(4, false, 4, 64);
+    }
+#undef LBM_STEP
 }
 
 template <typename T, typename C>
@@ -645,9 +689,8 @@ __global__ void k_init_pops(BoxDesc b, const double* __restrict__ dn,
         const double c = CX[i] * ux + CY[i] * uy + CZ[i] * uz;
         const double f = weight(i) * n * (1.0 + 3.0 * c + 4.5 * c * c - 1.5 * uu);
         // f_i(x, 0) is the pull of the stored slot at x - xi_i
-        const unsigned s = ((unsigned)wrapi(z - CZ[i], b.nz) * (unsigned)b.ny +
-                            (unsigned)wrapi(y - CY[i], b.ny)) * (unsigned)b.nx +
-                           (unsigned)wrapi(x - CX[i], b.nx);
+        const unsigned s = stored_index(b, wrapi(x - CX[i], b.nx), wrapi(y - CY[i], b.ny),
+                                        wrapi(z - CZ[i], b.nz));
         dst[(unsigned long long)i * b.stride + s] = (T)(f - weight(i) * b.rho_ref);
     }
 }
@@ -665,9 +708,7 @@ __global__ void k_get(BoxDesc b, int cx, int cy, int cz, double w, const T* __re
     const int x = (int)(k % (unsigned)b.nx);
     const int y = (int)((k / (unsigned)b.nx) % (unsigned)b.ny);
     const int z = (int)(k / b.nxy);
-    const unsigned s = ((unsigned)wrapi(z - cz, b.nz) * (unsigned)b.ny +
-                        (unsigned)wrapi(y - cy, b.ny)) * (unsigned)b.nx +
-                       (unsigned)wrapi(x - cx, b.nx);
+    const unsigned s = stored_index(b, wrapi(x - cx, b.nx), wrapi(y - cy, b.ny), wrapi(z - cz, b.nz));
     out[k] = (double)src[s] + w * b.rho_ref;
 }
 
@@ -684,7 +725,7 @@ __global__ void k_set(BoxDesc b, int cx, int cy, int cz, double w, const double*
     const unsigned s = ((unsigned)wrapi(z + cz, b.nz) * (unsigned)b.ny +
                         (unsigned)wrapi(y + cy, b.ny)) * (unsigned)b.nx +
                        (unsigned)wrapi(x + cx, b.nx);
-    dst[k] = (T)(in[s] - w * b.rho_ref);
+    dst[stored_index(b, x, y, z)] = (T)(in[s] - w * b.rho_ref);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -703,9 +744,8 @@ __global__ void k_obs_pull(BoxDesc b, const T* __restrict__ src, double* __restr
         double s = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            const unsigned o = ((unsigned)wrapi(z - CZ[i], b.nz) * (unsigned)b.ny +
-                                (unsigned)wrapi(y - CY[i], b.ny)) * (unsigned)b.nx +
-                               (unsigned)wrapi(x - CX[i], b.nx);
+            const unsigned o = stored_index(b, wrapi(x - CX[i], b.nx), wrapi(y - CY[i], b.ny),
+                                            wrapi(z - CZ[i], b.nz));
             const double f = (double)src[(unsigned long long)i * b.stride + o] + weight(i) * b.rho_ref;
             s += f;
             jx += CX[i] * f;
@@ -955,13 +995,11 @@ __global__ __launch_bounds__(256) void k_stream_copy(const float* __restrict__ s
 hipError_t launch_step(bool fp32, bool math64, const BoxDesc& b, const StepShape& s,
                        const void* src, void* dst, hipStream_t st)
 {
-    if (s.rows != 1 && s.rows != 2 && s.rows != 4) return hipErrorInvalidValue;
-    if (s.waves != 4 && s.waves != 8) return hipErrorInvalidValue;
-    if (s.z_chunk < 1) return hipErrorInvalidValue;
+    if (!shape_supported(s)) return hipErrorInvalidValue;
     StepArgs a;
     a.b = b;
-    a.tiles_x = (b.nx + BX - 1) / BX;
-    const int by = s.waves * s.rows;
+    a.tiles_x = (b.nx + s.tile_x - 1) / s.tile_x;
+    const int by = tile_height(s);
     a.tiles_y = (b.ny + by - 1) / by;
     a.zc = s.z_chunk < b.nz ? s.z_chunk : b.nz;
     a.nchunks = (b.nz + a.zc - 1) / a.zc;
@@ -971,49 +1009,58 @@ hipError_t launch_step(bool fp32, bool math64, const BoxDesc& b, const StepShape
                   : dispatch_step<float, float>(s, a, src, dst, st);
 }
 
-template <typename T, int R, bool PF>
+template <typename T, int R, bool PF, int WAVES, int BXT>
 hipError_t launch_group_t(const GroupBox* boxes, int nbox, unsigned nitems, int parity,
                           int persistent, int remap, unsigned workers, QueueState* q,
                           hipStream_t st)
 {
     if (persistent)
-        hipLaunchKernelGGL((k_step_group_persistent<T, R, PF, 4>), dim3(workers), dim3(256), 0, st,
-                           boxes, nbox, parity, q);
+        hipLaunchKernelGGL((k_step_group_persistent<T, R, PF, WAVES, BXT>), dim3(workers),
+                           dim3(64 * WAVES), 0, st, boxes, nbox, parity, q);
     else
-        hipLaunchKernelGGL((k_step_group<T, R, PF, 4>), dim3(nitems), dim3(256), 0, st, boxes, nbox,
-                           parity, remap);
+        hipLaunchKernelGGL((k_step_group<T, R, PF, WAVES, BXT>), dim3(nitems), dim3(64 * WAVES), 0,
+                           st, boxes, nbox, parity, remap);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_group_rows(const StepShape& s, const GroupBox* boxes, int nbox, unsigned nitems,
-                             int parity, int persistent, unsigned workers, QueueState* q,
-                             hipStream_t st)
+hipError_t launch_group_shape(const StepShape& s, const GroupBox* boxes, int nbox, unsigned nitems,
+                              int parity, int persistent, unsigned workers, QueueState* q,
+                              hipStream_t st)
 {
-    const int r = s.xcd_remap;
+#define LBM_GROUP(R, PF, WV, BXT) \
+    launch_group_t<T, R, PF, WV, BXT>(boxes, nbox, nitems, parity, persistent, s.xcd_remap, workers, q, st)
+    if (s.waves == 8) {
+        if (s.tile_x == 32) return s.rows == 1 ? LBM_GROUP(1, false, 8, 32) : LBM_GROUP(2, false, 8, 32);
+        return s.rows == 1 ? LBM_GROUP(1, false, 8, 64) : LBM_GROUP(2, false, 8, 64);
+    }
+    if (s.tile_x == 32) {
+        if (s.prefetch) return s.rows == 1 ? LBM_GROUP(1, true, 4, 32) : LBM_GROUP(2, true, 4, 32);
+        return s.rows == 1 ? LBM_GROUP(1, false, 4, 32) : LBM_GROUP(2, false, 4, 32);
+    }
     if (s.prefetch) {
         switch (s.rows) {
-            case 1: return launch_group_t<T, 1, true>(boxes, nbox, nitems, parity, persistent, r, workers, q, st);
-            case 2: return launch_group_t<T, 2, true>(boxes, nbox, nitems, parity, persistent, r, workers, q, st);
-            case 4: return launch_group_t<T, 4, true>(boxes, nbox, nitems, parity, persistent, r, workers, q, st);
-        }
-    } else {
-        switch (s.rows) {
-            case 1: return launch_group_t<T, 1, false>(boxes, nbox, nitems, parity, persistent, r, workers, q, st);
-            case 2: return launch_group_t<T, 2, false>(boxes, nbox, nitems, parity, persistent, r, workers, q, st);
-            case 4: return launch_group_t<T, 4, false>(boxes, nbox, nitems, parity, persistent, r, workers, q, st);
+            case 1: return LBM_GROUP(1, true, 4, 64);
+            case 2: return LBM_GROUP(2, true, 4, 64);
+            default: return LBM_GROUP(4, true, 4, 64);
         }
     }
-    return hipErrorInvalidValue;
+    switch (s.rows) {
+        case 1: return LBM_GROUP(1, false, 4, 64);
+        case 2: return LBM_GROUP(2, false, 4, 64);
+        default: return LBM_GROUP(4, false, 4, 64);
+    }
+#undef LBM_GROUP
 }
 
 hipError_t launch_step_group(bool fp32, const StepShape& s, const GroupBox* boxes, int nbox,
                              unsigned nitems, int parity, int persistent, unsigned workers,
                              QueueState* q, hipStream_t st)
 {
+    if (!shape_supported(s)) return hipErrorInvalidValue;
     if (nbox <= 0 || nitems == 0) return hipSuccess;
-    return fp32 ? launch_group_rows<float>(s, boxes, nbox, nitems, parity, persistent, workers, q, st)
-                : launch_group_rows<double>(s, boxes, nbox, nitems, parity, persistent, workers, q, st);
+    return fp32 ? launch_group_shape<float>(s, boxes, nbox, nitems, parity, persistent, workers, q, st)
+                : launch_group_shape<double>(s, boxes, nbox, nitems, parity, persistent, workers, q, st);
 }
 
 hipError_t launch_init(bool fp32, const BoxDesc& b, const InitDesc& d, double* dn, double* dpsi,

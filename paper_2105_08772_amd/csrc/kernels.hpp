@@ -10,8 +10,11 @@ namespace lbm {
 struct BoxDesc {
     int nx, ny, nz;
     unsigned nxy;            // nx * ny
-    unsigned n;              // nx * ny * nz
-    unsigned long long stride;  // elements between consecutive population arrays (>= n)
+    unsigned n;              // nx * ny * nz (nodes; canonical index (z * ny + y) * nx + x)
+    unsigned px;             // row pitch of the stored populations (elements, >= nx, whole
+                             // 128-byte lines)
+    unsigned pxy;            // plane pitch px * ny; stored index (z * ny + y) * px + x
+    unsigned long long stride;  // elements between consecutive population arrays (>= pxy * nz)
     int psi;                 // 0: exp(-1/n), 1: 1 - exp(-n)
     double G;
     double tau;
@@ -19,14 +22,29 @@ struct BoxDesc {
 };
 
 // Launch shape of the fused step kernel. The workgroup is 64 * waves threads (waves wave64s); the
-// tile is 64 x (waves * rows) nodes in x-y and z_chunk planes in z.
+// tile is tile_x nodes wide (64, or 32 with each wave row split into two sub-rows), tile_height()
+// rows high and z_chunk planes deep.
 struct StepShape {
     int rows;        // rows of the tile per wave (1, 2 or 4)
-    int waves;       // wave64s per workgroup (4 or 8); the multi-box kernels use 4
+    int waves;       // wave64s per workgroup (4 or 8)
     int z_chunk;     // planes marched per workgroup
     int xcd_remap;   // 1: map consecutive logical tiles to one XCD
     int prefetch;    // 1: issue the next plane's loads before the barrier (software pipelining)
+    int tile_x;      // tile width: 64 or 32
 };
+
+// The compiled shapes: 4 waves with rows 1, 2 or 4 (rows 1 or 2 at tile width 32), either
+// prefetch setting; 8 waves with rows 1 or 2 and no prefetch.
+inline bool shape_supported(const StepShape& s)
+{
+    if (s.z_chunk < 1 || (s.xcd_remap & ~1) || (s.prefetch & ~1)) return false;
+    if (s.tile_x != 64 && s.tile_x != 32) return false;
+    if (s.waves == 4) return s.rows == 1 || s.rows == 2 || (s.rows == 4 && s.tile_x == 64);
+    if (s.waves == 8) return (s.rows == 1 || s.rows == 2) && s.prefetch == 0;
+    return false;
+}
+
+inline int tile_height(const StepShape& s) { return s.waves * s.rows * (64 / s.tile_x); }
 
 // One box of a multi-box step.
 struct GroupBox {

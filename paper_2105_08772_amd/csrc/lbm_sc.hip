@@ -353,12 +353,22 @@ void default_shape(lbm_sc* h)
     h->shape.waves = 8;
     h->shape.xcd_remap = 1;
     h->shape.prefetch = 0;
-    const int by = h->shape.waves * h->shape.rows;
+    h->shape.tile_x = 64;
+    const int by = lbm::tile_height(h->shape);
     const long tiles = (long)((h->box.nx + 63) / 64) * ((h->box.ny + by - 1) / by);
     long chunks = (256 + tiles - 1) / tiles;
     if (chunks > h->box.nz) chunks = h->box.nz;
     if (chunks < 1) chunks = 1;
     h->shape.z_chunk = (int)((h->box.nz + chunks - 1) / chunks);
+}
+
+// Row pitch of the stored populations: nx rounded up to whole 128-byte lines, so that every row
+// starts on a line and the step kernel writes complete lines (it fills the padding of the last
+// line of each row, which nothing reads).
+unsigned row_pitch(int nx, size_t elem)
+{
+    const unsigned per_line = (unsigned)(128 / elem);
+    return ((unsigned)nx + per_line - 1) / per_line * per_line;
 }
 
 // Elements between population arrays: rounded up to 64 elements and, for arrays of 4 MiB or more,
@@ -380,9 +390,10 @@ Sizes sizes_for(const lbm_sc_config* c)
 {
     const size_t elem = c->prec == LBM_SC_FP64 ? 8 : 4;
     const unsigned long long n = (unsigned long long)c->nx * c->ny * c->nz;
+    const unsigned long long stored = (unsigned long long)row_pitch(c->nx, elem) * c->ny * c->nz;
     const int Lmax = std::max(c->nx, std::max(c->ny, c->nz));
     Sizes s;
-    s.popbytes = (size_t)19 * population_stride(n, elem) * elem;
+    s.popbytes = (size_t)19 * population_stride(stored, elem) * elem;
     s.n8 = (size_t)n * 8;
     s.n24 = 3 * (size_t)n * 8;
     s.parts = (size_t)lbm::OBS_BLOCKS * lbm::OBS_PARTS * 8;
@@ -463,7 +474,10 @@ int lbm_sc_create(const lbm_sc_config* cfg, lbm_sc** out)
     b.nz = cfg->nz;
     b.nxy = (unsigned)cfg->nx * (unsigned)cfg->ny;
     b.n = b.nxy * (unsigned)cfg->nz;
-    b.stride = population_stride(b.n, h->elem);
+    b.px = row_pitch(cfg->nx, h->elem);
+    const unsigned long long pxy = (unsigned long long)b.px * (unsigned)cfg->ny;
+    b.pxy = (unsigned)pxy;   // < 2^32 whenever the 4 GiB check below passes
+    b.stride = population_stride(pxy * (unsigned)cfg->nz, h->elem);
     b.psi = cfg->psi;
     b.G = h->G;
     b.tau = cfg->tau;
@@ -614,8 +628,8 @@ int lbm_sc_get_info(lbm_sc* h, lbm_sc_info* out)
     out->nodes = (int64_t)h->box.n;
     out->device_bytes = h->device_bytes;
     out->bytes_per_step = (int64_t)2 * 19 * (int64_t)h->elem * (int64_t)h->box.n;
-    out->block_x = 64;
-    out->block_y = h->shape.waves * h->shape.rows;
+    out->block_x = h->shape.tile_x;
+    out->block_y = lbm::tile_height(h->shape);
     out->z_chunk = h->shape.z_chunk;
     return LBM_SC_OK;
 }
@@ -623,14 +637,22 @@ int lbm_sc_get_info(lbm_sc* h, lbm_sc_info* out)
 int lbm_sc_set_launch(lbm_sc* h, const lbm_sc_launch* l)
 {
     if (!h || !l) return fail(LBM_SC_EINVAL, "handle or launch is NULL");
-    if (l->rows != 1 && l->rows != 2 && l->rows != 4) return fail(LBM_SC_EINVAL, "rows must be 1, 2 or 4");
     if (l->z_chunk < 1) return fail(LBM_SC_EINVAL, "z_chunk must be >= 1");
     if (l->xcd_remap != 0 && l->xcd_remap != 1) return fail(LBM_SC_EINVAL, "xcd_remap must be 0 or 1");
     if (l->prefetch != 0 && l->prefetch != 1) return fail(LBM_SC_EINVAL, "prefetch must be 0 or 1");
-    if (l->waves != 4 && l->waves != 8) return fail(LBM_SC_EINVAL, "waves must be 4 or 8");
-    if (l->reserved != 0) return fail(LBM_SC_EINVAL, "reserved must be 0");
+    lbm::StepShape s;
+    s.rows = l->rows;
+    s.waves = l->waves;
+    s.z_chunk = l->z_chunk;
+    s.xcd_remap = l->xcd_remap;
+    s.prefetch = l->prefetch;
+    s.tile_x = l->tile_x;
+    if (!lbm::shape_supported(s))
+        return fail(LBM_SC_EINVAL, "unsupported tile shape (waves 4: rows 1, 2, 4, or 1, 2 at tile_x 32; "
+                                   "waves 8: rows 1, 2 without prefetch)");
     h->shape.rows = l->rows;
     h->shape.waves = l->waves;
+    h->shape.tile_x = l->tile_x;
     h->shape.z_chunk = l->z_chunk < h->box.nz ? l->z_chunk : h->box.nz;
     h->shape.xcd_remap = l->xcd_remap;
     h->shape.prefetch = l->prefetch;
@@ -645,7 +667,7 @@ int lbm_sc_get_launch(lbm_sc* h, lbm_sc_launch* out)
     out->xcd_remap = h->shape.xcd_remap;
     out->prefetch = h->shape.prefetch;
     out->waves = h->shape.waves;
-    out->reserved = 0;
+    out->tile_x = h->shape.tile_x;
     return LBM_SC_OK;
 }
 
@@ -696,6 +718,18 @@ void drop_graph(lbm_sc_group* g)
     g->graph_len = 0;
 }
 
+lbm::StepShape group_shape(const lbm_sc_group_launch& L)
+{
+    lbm::StepShape s;
+    s.rows = L.rows;
+    s.waves = L.waves;
+    s.z_chunk = L.z_chunk;
+    s.xcd_remap = L.xcd_remap;
+    s.prefetch = L.prefetch;
+    s.tile_x = L.tile_x;
+    return s;
+}
+
 // Build the work list and queue ranges for the current boxes and launch shape, and upload them.
 // Phases align every box's current buffer with parity 0.
 int group_rebuild(lbm_sc_group* g)
@@ -706,7 +740,8 @@ int group_rebuild(lbm_sc_group* g)
     g->nodes = 0;
     g->bytes_per_step = 0;
     std::vector<double> work;   // nodes per item, box-major
-    const int by = 4 * L.rows;
+    const lbm::StepShape shape = group_shape(L);
+    const int bx = shape.tile_x, by = lbm::tile_height(shape);
     for (lbm_sc* h : g->boxes) {
         lbm::GroupBox d;
         std::memset(&d, 0, sizeof(d));
@@ -714,7 +749,7 @@ int group_rebuild(lbm_sc_group* g)
         d.pop[0] = h->pop[0];
         d.pop[1] = h->pop[1];
         d.phase = h->cur;
-        d.tiles_x = (h->box.nx + 63) / 64;
+        d.tiles_x = (h->box.nx + bx - 1) / bx;
         d.tiles_y = (h->box.ny + by - 1) / by;
         d.zc = L.z_chunk < h->box.nz ? L.z_chunk : h->box.nz;
         const unsigned nch = (unsigned)((h->box.nz + d.zc - 1) / d.zc);
@@ -723,7 +758,7 @@ int group_rebuild(lbm_sc_group* g)
         for (unsigned it = 0; it < d.items; ++it) {
             const unsigned tix = it % d.tiles_x, t2 = it / d.tiles_x;
             const unsigned tiy = t2 % d.tiles_y, ch = t2 / d.tiles_y;
-            const int w = std::min(64, h->box.nx - (int)tix * 64);
+            const int w = std::min(bx, h->box.nx - (int)tix * bx);
             const int hgt = std::min(by, h->box.ny - (int)tiy * by);
             const int dz = std::min(d.zc, h->box.nz - (int)ch * d.zc);
             work.push_back((double)std::max(w, 1) * std::max(hgt, 1) * std::max(dz, 1));
@@ -770,12 +805,7 @@ int group_rebuild(lbm_sc_group* g)
 
 hipError_t group_launch(lbm_sc_group* g, int parity)
 {
-    lbm::StepShape s;
-    s.rows = g->launch.rows;
-    s.waves = 4;
-    s.z_chunk = g->launch.z_chunk;
-    s.xcd_remap = g->launch.xcd_remap;
-    s.prefetch = g->launch.prefetch;
+    const lbm::StepShape s = group_shape(g->launch);
     const unsigned workers = g->launch.workers ? (unsigned)g->launch.workers : 256u;
     return lbm::launch_step_group(g->fp32, s, g->d_desc, (int)g->desc.size(), g->nitems, parity,
                                   g->launch.persistent, workers, g->d_queue, g->stream);
@@ -783,9 +813,11 @@ hipError_t group_launch(lbm_sc_group* g, int parity)
 
 int check_group_launch(const lbm_sc_group_launch* l)
 {
-    if (l->rows != 1 && l->rows != 2 && l->rows != 4) return fail(LBM_SC_EINVAL, "rows must be 1, 2 or 4");
     if (l->z_chunk < 1) return fail(LBM_SC_EINVAL, "z_chunk must be >= 1");
     if ((l->xcd_remap | l->prefetch | l->persistent) & ~1) return fail(LBM_SC_EINVAL, "flags must be 0 or 1");
+    if (!lbm::shape_supported(group_shape(*l)))
+        return fail(LBM_SC_EINVAL, "unsupported tile shape (waves 4: rows 1, 2, 4, or 1, 2 at tile_x 32; "
+                                   "waves 8: rows 1, 2 without prefetch)");
     if (l->workers < 0 || l->workers % 8 || l->workers > 65536)
         return fail(LBM_SC_EINVAL, "workers must be a multiple of 8 in [0, 65536]");
     if (l->graph_steps < 0 || l->graph_steps % 2 || l->graph_steps > 4096)
@@ -806,7 +838,7 @@ int lbm_sc_group_create(void* stream, lbm_sc_group** out)
     lbm_sc_group* g = new (std::nothrow) lbm_sc_group();
     if (!g) return fail(LBM_SC_ENOMEM, "host allocation failed");
     g->stream = (hipStream_t)stream;
-    g->launch = {2, 32, 1, 1, 0, 0, 64, 0};
+    g->launch = {2, 32, 1, 1, 0, 0, 64, 4, 64, 0};
     hipError_t e = hipMalloc((void**)&g->d_queue, sizeof(lbm::QueueState));
     if (e != hipSuccess) {
         delete g;

@@ -13,13 +13,17 @@ def _sync():
     torch.cuda.synchronize()
 
 
+SHAPES = [dict(waves=4, rows=r, prefetch=pf, tile_x=64) for r in (1, 2, 4) for pf in (0, 1)] + \
+         [dict(waves=4, rows=r, prefetch=pf, tile_x=32) for r in (1, 2) for pf in (0, 1)] + \
+         [dict(waves=8, rows=r, prefetch=0, tile_x=bx) for r in (1, 2) for bx in (64, 32)]
+
+
 def group_candidates():
     out = []
-    for rows, zc, pf in itertools.product((1, 2, 4), (16, 32, 64), (0, 1)):
-        out.append(dict(rows=rows, z_chunk=zc, prefetch=pf, xcd_remap=1, persistent=0, workers=0))
+    for shape, zc in itertools.product(SHAPES, (16, 32, 64)):
+        out.append(dict(shape, z_chunk=zc, xcd_remap=1, persistent=0, workers=0))
         for workers in (256, 512):
-            out.append(dict(rows=rows, z_chunk=zc, prefetch=pf, xcd_remap=1, persistent=1,
-                            workers=workers))
+            out.append(dict(shape, z_chunk=zc, xcd_remap=1, persistent=1, workers=workers))
     return out
 
 
@@ -45,10 +49,9 @@ def tune_group(group, steps=8, candidates=None, log=None):
 
 def box_candidates(nz):
     out = []
-    for waves, rows, zc, pf, remap in itertools.product((4, 8), (1, 2, 4), (8, 16, 32, 64, 128),
-                                                        (0, 1), (0, 1)):
+    for shape, zc, remap in itertools.product(SHAPES, (8, 16, 32, 64, 128), (0, 1)):
         if zc <= max(nz, 8):
-            out.append(dict(rows=rows, z_chunk=zc, prefetch=pf, xcd_remap=remap, waves=waves))
+            out.append(dict(shape, z_chunk=zc, xcd_remap=remap))
     return out
 
 
@@ -57,7 +60,7 @@ def tune_box(box, steps=16, candidates=None, log=None):
     best = None
     for cand in candidates or box_candidates(box.dims[2]):
         box.set_launch(cand["rows"], cand["z_chunk"], cand["xcd_remap"], cand["prefetch"],
-                       cand["waves"])
+                       cand["waves"], cand["tile_x"])
         box.step(2)
         _sync()
         t0 = time.perf_counter()
@@ -69,5 +72,6 @@ def tune_box(box, steps=16, candidates=None, log=None):
         if best is None or t < best[0]:
             best = (t, cand)
     c = best[1]
-    box.set_launch(c["rows"], c["z_chunk"], c["xcd_remap"], c["prefetch"], c["waves"])
+    box.set_launch(c["rows"], c["z_chunk"], c["xcd_remap"], c["prefetch"], c["waves"],
+                   c["tile_x"])
     return dict(c, seconds_per_step=best[0])

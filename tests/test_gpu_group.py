@@ -48,6 +48,12 @@ LAUNCHES = [
     dict(rows=1, z_chunk=5, xcd_remap=0, prefetch=0, persistent=0, workers=0, graph_steps=0),
     dict(rows=4, z_chunk=9, xcd_remap=1, prefetch=1, persistent=1, workers=64, graph_steps=6),
     dict(rows=2, z_chunk=64, xcd_remap=1, prefetch=0, persistent=1, workers=8, graph_steps=2),
+    dict(rows=2, z_chunk=7, xcd_remap=1, prefetch=0, persistent=1, workers=24, graph_steps=4,
+         waves=8, tile_x=64),
+    dict(rows=1, z_chunk=16, xcd_remap=1, prefetch=1, persistent=0, workers=0, graph_steps=0,
+         tile_x=32),
+    dict(rows=2, z_chunk=3, xcd_remap=0, prefetch=0, persistent=1, workers=40, graph_steps=2,
+         waves=8, tile_x=32),
 ]
 
 
@@ -118,6 +124,10 @@ def test_group_rejects_mixed_precision_and_foreign_streams():
             assert e.value.code == lbm.LBM_SC_EINVAL
         with pytest.raises(lbm.LbmScError):
             g.set_launch(workers=12)
+        with pytest.raises(lbm.LbmScError):
+            g.set_launch(waves=8, prefetch=1)
+        with pytest.raises(lbm.LbmScError):
+            g.set_launch(rows=4, tile_x=32)
         with pytest.raises(lbm.LbmScError):
             g.set_launch(graph_steps=3)
     for x in (a, b, c, d):

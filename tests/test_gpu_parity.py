@@ -77,7 +77,9 @@ def test_one_step_fp32_shifted(dims, tau, prefetch):
     with make_box(dims, prec=lbm.LBM_SC_FP32_SHIFTED, tau=tau, rho_ref=rho_ref) as b:
         b.set(f)
         lc = b.launch()
-        b.set_launch(lc["rows"], lc["z_chunk"], lc["xcd_remap"], prefetch, lc["waves"])
+        # prefetch is compiled for 4-wave workgroups
+        b.set_launch(lc["rows"], lc["z_chunk"], lc["xcd_remap"], prefetch,
+                     4 if prefetch else lc["waves"], lc["tile_x"])
         b.step(1)
         g = b.get()
     ref = core.step(f, G, tau, 0)
@@ -128,20 +130,24 @@ def test_launch_shapes_are_bitwise_identical(prec):
     rho_ref = 1.5
     f = fp32_representable(inputs.random_populations(dims, 3, W * 1.5, amp=0.3), rho_ref)
     outs = []
-    for rows, zc, remap, pf, waves in ((1, 1, 0, 0, 4), (2, 7, 1, 1, 4), (4, 33, 1, 0, 4),
-                                       (4, 5, 0, 1, 4), (1, 64, 1, 1, 4), (2, 3, 0, 0, 4),
-                                       (2, 9, 1, 0, 8), (4, 33, 0, 1, 8), (1, 2, 1, 1, 8)):
+    shapes = ((1, 1, 0, 0, 4, 64), (2, 7, 1, 1, 4, 64), (4, 33, 1, 0, 4, 64),
+              (4, 5, 0, 1, 4, 64), (1, 64, 1, 1, 4, 64), (2, 3, 0, 0, 4, 64),
+              (2, 9, 1, 0, 8, 64), (1, 33, 0, 0, 8, 64), (1, 2, 1, 1, 4, 32), (2, 5, 0, 1, 4, 32),
+              (2, 11, 1, 0, 4, 32), (1, 4, 1, 0, 8, 32), (2, 33, 0, 0, 8, 32))
+    for rows, zc, remap, pf, waves, tx in shapes:
         with make_box(dims, prec=prec, rho_ref=rho_ref) as b:
             b.set(f)
-            b.set_launch(rows, zc, remap, pf, waves)
+            b.set_launch(rows, zc, remap, pf, waves, tx)
             assert b.launch() == dict(rows=rows, z_chunk=min(zc, 33), xcd_remap=remap, prefetch=pf,
-                                      waves=waves)
+                                      waves=waves, tile_x=tx)
             b.step(3)
             outs.append(b.get())
     for o in outs[1:]:
         assert np.array_equal(o, outs[0])
     with make_box(dims, prec=prec, rho_ref=rho_ref) as b:
-        for bad in ((3, 4, 1, 0, 4), (2, 0, 1, 0, 4), (2, 4, 2, 0, 4), (2, 4, 1, 0, 6)):
+        for bad in ((3, 4, 1, 0, 4, 64), (2, 0, 1, 0, 4, 64), (2, 4, 2, 0, 4, 64),
+                    (2, 4, 1, 0, 6, 64), (4, 4, 1, 0, 8, 64), (2, 4, 1, 1, 8, 64),
+                    (4, 4, 1, 0, 4, 32), (2, 4, 1, 0, 4, 16)):
             with pytest.raises(lbm.LbmScError):
                 b.set_launch(*bad)
 
