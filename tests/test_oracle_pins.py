@@ -305,6 +305,36 @@ def test_guo_collision_moments():
         assert np.abs(np.einsum("i,ia,ib->ab", fs, XI, XI) - want).max() < 1e-14
 
 
+def test_one_step_on_4cubed_without_force_at_tau_one():
+    """Brute-force check of one whole step on a 4^3 grid with G = 0 and tau = 1: the collision
+    relaxes fully, so population i arriving at x is the equilibrium of the source node x - xi_i.
+    Un-streaming every population (rolling it back by -xi_i) must give at each node a set that
+    (a) carries the source node's density and momentum, (b) has the second moment
+    n c_s^2 delta + j j / n, (c) has the third moment sum xi_a^3 f = j_a (xi_a^3 = xi_a on the
+    lattice), and (d) is the same for two nodes with equal (n, j) but different populations.
+    A population streamed the wrong way, a missing 1/2 or a wrong velocity definition fails it."""
+    f = inputs.random_populations((4, 4, 4), 77, weights_scale(1.2), amp=0.3)
+    # two nodes with different populations but the same density and momentum
+    a, b = (1, 2, 3), (3, 0, 1)
+    delta = np.zeros(19)
+    delta[0], delta[7], delta[8] = 0.01, -0.005, -0.005   # (1,1,0) and (-1,-1,0): same n, same j
+    f[:, b[2], b[1], b[0]] = f[:, a[2], a[1], a[0]] + delta
+    g = core.step(f, 0.0, 1.0, core.PSI_EXP)
+    back = np.stack([np.roll(g[i], shift=(-XI[i, 2], -XI[i, 1], -XI[i, 0]), axis=(0, 1, 2))
+                     for i in range(19)])
+    n = f.sum(axis=0)
+    j = np.einsum("ic,izyx->czyx", XI, f)
+    assert np.abs(back.sum(axis=0) - n).max() < 1e-15
+    assert np.abs(np.einsum("ic,izyx->czyx", XI, back) - j).max() < 1e-15
+    Pi = np.einsum("ia,ib,izyx->abzyx", XI, XI, back)
+    want = n * CS2 * np.eye(3)[:, :, None, None, None] + np.einsum("azyx,bzyx->abzyx", j, j) / n
+    assert np.abs(Pi - want).max() < 1e-14
+    for c in range(3):
+        assert np.abs(np.einsum("i,izyx->zyx", XI[:, c] ** 3, back) - j[c]).max() < 1e-15
+    assert np.abs(f[:, b[2], b[1], b[0]] - f[:, a[2], a[1], a[0]]).max() > 1e-3
+    assert np.abs(back[:, b[2], b[1], b[0]] - back[:, a[2], a[1], a[0]]).max() < 1e-15
+
+
 def test_init_is_equilibrium_at_zero_velocity():
     """Initial populations: sum f = n, sum xi f = -F/2 (zero physical velocity), second moment
     n c_s^2 delta + n u u with u = -F/(2n): pins the equilibrium's three moments."""
