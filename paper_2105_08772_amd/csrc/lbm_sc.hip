@@ -345,8 +345,11 @@ int observe(lbm_sc* h, lbm_sc_obs* o, double* prof_out)
     return LBM_SC_OK;
 }
 
-// Default launch shape (measured on MI355X at 256^3): 8-wave workgroups with two rows per wave
-// (64 x 16 tiles), XCD remap on, and z chunks long enough that about one workgroup runs per CU.
+// Default launch shape: 8-wave workgroups with two rows per wave (64 x 16 tiles), XCD remap on,
+// no prefetch, and the z chunk that minimises (rounds of workgroups over the CUs) x (planes per
+// chunk + the two planes each chunk pulls again): one workgroup per CU already draws its share
+// of the bandwidth, so a partly filled last round costs a whole round (measured on MI355X:
+// 288 workgroups of a 192^3 box run 30 % slower than 252).
 void default_shape(lbm_sc* h)
 {
     h->shape.rows = 2;
@@ -354,12 +357,27 @@ void default_shape(lbm_sc* h)
     h->shape.xcd_remap = 1;
     h->shape.prefetch = 0;
     h->shape.tile_x = 64;
+    int cus = 0;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus <= 0)
+        cus = 256;
     const int by = lbm::tile_height(h->shape);
     const long tiles = (long)((h->box.nx + 63) / 64) * ((h->box.ny + by - 1) / by);
-    long chunks = (256 + tiles - 1) / tiles;
-    if (chunks > h->box.nz) chunks = h->box.nz;
-    if (chunks < 1) chunks = 1;
-    h->shape.z_chunk = (int)((h->box.nz + chunks - 1) / chunks);
+    int best = h->box.nz;
+    double best_cost = 0.0;
+    for (int zc = 1; zc <= h->box.nz; ++zc) {
+        const long chunks = (h->box.nz + zc - 1) / zc;
+        if (zc > 1 && (h->box.nz + zc - 2) / (zc - 1) == chunks) continue;   // same split
+        const long wgs = tiles * chunks;
+        const double cost = (double)((wgs + cus - 1) / cus) * (zc + 2);
+        if (zc == 1 || cost < best_cost) {
+            best = zc;
+            best_cost = cost;
+        }
+    }
+    h->shape.z_chunk = best;
 }
 
 // Row pitch of the stored populations: nx rounded up to whole 128-byte lines, so that every row
