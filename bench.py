@@ -405,7 +405,7 @@ def main():
     ap.add_argument("--remap", type=int, default=-1)
     ap.add_argument("--prefetch", type=int, default=-1)
     ap.add_argument("--waves", type=int, default=0)
-    ap.add_argument("--tile-x", type=int, default=0)
+    ap.add_argument("--tile-x", type=int, default=-1, help="64, 32, or 0 for full-row tiles")
     ap.add_argument("--tune", action="store_true", help="sweep launch shapes, keep the fastest")
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
@@ -474,8 +474,11 @@ def main():
         best = None
         from paper_2105_08772_amd import tune
         for c in tune.box_candidates(L):
-            box.set_launch(c["rows"], c["z_chunk"], c["xcd_remap"], c["prefetch"], c["waves"],
-                           c["tile_x"])
+            try:
+                box.set_launch(c["rows"], c["z_chunk"], c["xcd_remap"], c["prefetch"], c["waves"],
+                               c["tile_x"])
+            except lbm.LbmScError:
+                continue
             box.step(8)
             t = time_steps(64)
             print(f"# tune {c} {nodes / t / 1e6:.0f} MLUPS {bytes_per_step / t / 1e9:.0f} GB/s",
@@ -486,12 +489,12 @@ def main():
         box.set_launch(tuned["rows"], tuned["z_chunk"], tuned["xcd_remap"], tuned["prefetch"],
                        tuned["waves"], tuned["tile_x"])
     if (args.rows or args.zchunk or args.remap >= 0 or args.prefetch >= 0 or args.waves
-            or args.tile_x):
+            or args.tile_x >= 0):
         lc = box.launch()
         box.set_launch(args.rows or lc["rows"], args.zchunk or lc["z_chunk"],
                        args.remap if args.remap >= 0 else lc["xcd_remap"],
                        args.prefetch if args.prefetch >= 0 else lc["prefetch"],
-                       args.waves or lc["waves"], args.tile_x or lc["tile_x"])
+                       args.waves or lc["waves"], args.tile_x if args.tile_x >= 0 else lc["tile_x"])
     info = box.info()
     launch = box.launch()
 

@@ -154,14 +154,17 @@ int lbm_sc_set_populations(lbm_sc* h, const double* f, size_t len);
  * owns an x-y tile tile_x nodes wide and waves*rows*(64/tile_x) rows high (at tile_x = 32 each
  * wave row covers two rows of 32 nodes), and a run of z_chunk planes along z. Supported shapes:
  * waves 4 with rows 1, 2 or 4 (rows 1 or 2 at tile_x 32) and either prefetch setting; waves 8
- * with rows 1 or 2 and prefetch 0. */
+ * with rows 1 or 2 and prefetch 0. tile_x = 0 selects full-row tiles for boxes with short rows:
+ * the workgroup (waves 8, prefetch 0) owns whole rows, `rows` (4, or 8 with FP32 arithmetic) is
+ * the number of nodes each thread holds per plane, and a tile has rows*512/px - 2 rows, px being
+ * nx rounded up to whole 128-byte lines (LBM_SC_EINVAL if that is below 1). */
 typedef struct {
-    int32_t rows;       /* tile rows per wave: 1, 2 or 4 */
+    int32_t rows;       /* tile rows per wave: 1, 2 or 4 (full-row tiles: nodes per thread, 4 or 8) */
     int32_t z_chunk;    /* planes per workgroup, >= 1 (clamped to nz) */
     int32_t xcd_remap;  /* 1: hand neighbouring tiles to the same XCD (shared L2); 0: identity */
     int32_t prefetch;   /* 1: issue the next plane's loads before the collision of the current one */
     int32_t waves;      /* wave64s per workgroup: 4 or 8 */
-    int32_t tile_x;     /* tile width: 64 or 32 */
+    int32_t tile_x;     /* tile width: 64 or 32; 0 for full-row tiles */
 } lbm_sc_launch;
 
 /* Set / read the launch shape. The shape changes only the schedule: every node's arithmetic and
@@ -195,7 +198,7 @@ typedef struct {
     int32_t workers;     /* persistent grid size, a multiple of 8 (0 = 256) */
     int32_t graph_steps; /* steps captured per hipGraph and replayed (even, 0 = no graph) */
     int32_t waves;       /* wave64s per workgroup: 4 or 8 */
-    int32_t tile_x;      /* tile width: 64 or 32 */
+    int32_t tile_x;      /* tile width: 64 or 32; 0 for full-row tiles (FP32 boxes for rows 8) */
     int32_t reserved;    /* must be 0 */
 } lbm_sc_group_launch;
 

@@ -138,6 +138,7 @@ __device__ __forceinline__ void static_for(F&& f)
 struct StepArgs {
     BoxDesc b;
     int tiles_x, tiles_y, nchunks, zc, remap;
+    int by;     // full-row tiles: interior rows per tile
 };
 
 // Pull the 19 pre-collision populations of one node and reduce them to (sum g, j). Byte offsets
@@ -247,8 +248,24 @@ struct Ring {
     static constexpr int LX = BXT + 2, LY = BY + 2;
     T v[4][LY][LX];
 };
+// LDS ring of full-row tiles: four planes of up to CAP psi values (rows of nx, flattened).
+template <typename T, int CAP>
+struct RowRing {
+    T v[4][CAP];
+};
+
+// Ring of a launch shape: BXT = 64 or 32 for x-y tiles; BXT = 0 for full-row tiles, where R is
+// the number of nodes each thread holds per plane.
 template <typename T, int R, int WAVES, int BXT>
-using RingOf = Ring<T, BXT, tile_rows<R, WAVES, BXT>()>;
+struct RingSel {
+    using type = Ring<T, BXT, tile_rows<R, WAVES, BXT>()>;
+};
+template <typename T, int R, int WAVES>
+struct RingSel<T, R, WAVES, 0> {
+    using type = RowRing<T, R * 64 * WAVES>;
+};
+template <typename T, int R, int WAVES, int BXT>
+using RingOf = typename RingSel<T, R, WAVES, BXT>::type;
 
 // One workgroup's share of a step: the tile (tix, tiy) of box b, planes [z0, z1), populations
 // stored as T, arithmetic in C (C = T, or T = float with C = double). The caller provides the LDS
@@ -450,6 +467,153 @@ __device__ __forceinline__ void step_tile(const BoxDesc& bd, const T* __restrict
     }
 }
 
+// Full-row tiles (for boxes whose rows are short): the workgroup owns rows [y0, y0 + by) of the
+// whole x extent, z planes [z0, z1). Per plane it pulls by + 2 rows (one halo row on each side,
+// wrapped) flattened over the row pitch: node m of the list is (m % px, m / px), thread t holds
+// nodes t + k NT, k < NPT. There is no x halo (x neighbours wrap inside the LDS row), and only
+// the row padding leaves lanes idle; those lanes store values nobody reads, so that each row's
+// last 128-byte line is written whole. The host chooses by so that px (by + 2) <= NPT NT.
+template <typename T, typename C, int PSI, bool TAU1, int NPT, int WAVES>
+__device__ __forceinline__ void step_rows(const BoxDesc& bd, const T* __restrict__ src,
+                                          T* __restrict__ dst, int by, int tiy, int z0, int z1,
+                                          RowRing<C, NPT * 64 * WAVES>& rg)
+{
+    constexpr int NT = 64 * WAVES;
+    auto& ring = rg.v;
+    const int nx = bd.nx, ny = bd.ny, nz = bd.nz;
+    const int px = (int)bd.px;
+    const unsigned pxy = bd.pxy;
+    const PopBuf sbuf = make_popbuf(src, bd.stride);
+    const PopBuf dbuf = make_popbuf(dst, bd.stride);
+    const C rho_ref = (C)bd.rho_ref;
+    const C G = (C)bd.G;
+    const C inv_tau = (C)(1.0 / bd.tau);
+    const C guo_pref = (C)(1.0 - 0.5 / bd.tau);
+    constexpr unsigned E = sizeof(T);
+    const unsigned rowb = bd.px * E;
+    const int y0 = tiy * by;
+    const int M = px * (by + 2);
+
+    // the thread's nodes: LDS position (lx, ly), box coordinates (x, y), load and store flags
+    int lxk[NPT], lyk[NPT], xk[NPT], yk[NPT];
+    bool ldk[NPT], stk[NPT];
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+        const int m = (int)threadIdx.x + k * NT;
+        const bool valid = m < M;
+        const int lx = valid ? m % px : 0;
+        const int ly = valid ? m / px : 0;
+        const int yg = y0 - 1 + ly;
+        lxk[k] = lx < nx ? lx : nx - 1;     // padding lanes read the last column's neighbourhood
+        lyk[k] = ly;
+        xk[k] = lx;                          // store column (padding included)
+        yk[k] = wrapi(yg, ny);
+        // rows past ny other than the first (row 0 again, the north neighbour of ny - 1) are
+        // not needed
+        ldk[k] = valid && lx < nx && yg <= ny;
+        stk[k] = valid && ly >= 1 && ly <= by && yg < ny;
+    }
+    auto node_offsets = [&](int k, unsigned (&xo)[3], unsigned (&yo)[3]) {
+        const int x = lxk[k], y = yk[k];
+        xo[0] = (unsigned)(x == 0 ? nx - 1 : x - 1) * E;
+        xo[1] = (unsigned)x * E;
+        xo[2] = (unsigned)(x == nx - 1 ? 0 : x + 1) * E;
+        yo[0] = (unsigned)(y == 0 ? ny - 1 : y - 1) * rowb;
+        yo[1] = (unsigned)y * rowb;
+        yo[2] = (unsigned)(y == ny - 1 ? 0 : y + 1) * rowb;
+    };
+    auto plane_offsets = [&](int p, unsigned (&zo)[3]) {
+        zo[0] = (unsigned)wrapi(p - 1, nz) * pxy * E;
+        zo[1] = (unsigned)wrapi(p, nz) * pxy * E;
+        zo[2] = (unsigned)wrapi(p + 1, nz) * pxy * E;
+    };
+
+    double pdn[NPT];
+    C pjx[NPT], pjy[NPT], pjz[NPT];
+    unsigned pzo[3] = {0u, 0u, 0u};
+    const int nplanes = (z1 - z0) + 2;
+    for (int kp = 0; kp < nplanes; ++kp) {
+        const int p = z0 - 1 + kp;
+        unsigned zo[3];
+        plane_offsets(p, zo);
+        C* slot = ring[kp & 3];
+        double cdn[NPT];
+        C cjx[NPT], cjy[NPT], cjz[NPT];
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) {
+            cdn[k] = 0.0;
+            cjx[k] = cjy[k] = cjz[k] = C(0);
+            if (ldk[k]) {
+                unsigned xo[3], yo[3];
+                node_offsets(k, xo, yo);
+                T f[Q];
+                load_node(sbuf, zo, yo, xo, f);
+                moments(f, cdn[k], cjx[k], cjy[k], cjz[k]);
+                slot[lyk[k] * nx + xk[k]] = psi_of<C, PSI>(rho_ref + (C)cdn[k]);
+            }
+        }
+        __syncthreads();
+        if (kp >= 2) {
+            // collide plane q = p - 1 with psi of planes q - 1, q, q + 1
+            const C* pm = ring[(kp - 2) & 3];
+            const C* pc = ring[(kp - 1) & 3];
+            const C* pp = ring[kp & 3];
+            const unsigned qoff = (unsigned)(p - 1) * pxy * E;
+#pragma unroll
+            for (int k = 0; k < NPT; ++k) {
+                if (!stk[k]) continue;
+                const int lx = lxk[k];
+                const int xw = lx == 0 ? nx - 1 : lx - 1, xe = lx == nx - 1 ? 0 : lx + 1;
+                const int r0 = (lyk[k] - 1) * nx, r1 = lyk[k] * nx, r2 = (lyk[k] + 1) * nx;
+                const C c_e = pc[r1 + xe], c_w = pc[r1 + xw];
+                const C c_n = pc[r2 + lx], c_s = pc[r0 + lx];
+                const C c_ne = pc[r2 + xe], c_nw = pc[r2 + xw];
+                const C c_se = pc[r0 + xe], c_sw = pc[r0 + xw];
+                const C p_c = pp[r1 + lx], p_e = pp[r1 + xe], p_w = pp[r1 + xw];
+                const C p_n = pp[r2 + lx], p_s = pp[r0 + lx];
+                const C m_c = pm[r1 + lx], m_e = pm[r1 + xe], m_w = pm[r1 + xw];
+                const C m_n = pm[r2 + lx], m_s = pm[r0 + lx];
+                const C psi0 = pc[r1 + lx];
+                const C w1 = (C)W1, w2 = (C)W2;
+                // S = sum_a w_a psi(x + xi_a) xi_a; F = -G psi(x) S (Eq. SCForce, c_s^2 W_a = w_a)
+                const C Sx = w1 * (c_e - c_w) +
+                             w2 * ((c_ne - c_nw) + (c_se - c_sw) + (p_e - p_w) + (m_e - m_w));
+                const C Sy = w1 * (c_n - c_s) +
+                             w2 * ((c_ne - c_se) + (c_nw - c_sw) + (p_n - p_s) + (m_n - m_s));
+                const C Sz = w1 * (p_c - m_c) +
+                             w2 * ((p_e - m_e) + (p_w - m_w) + (p_n - m_n) + (p_s - m_s));
+                const C gp = -G * psi0;
+                unsigned xo[3], yo[3];
+                node_offsets(k, xo, yo);
+                const unsigned off = qoff + yo[1] + (unsigned)xk[k] * E;
+                if constexpr (TAU1) {
+                    collide_store<T, C, true>(dbuf, off, rho_ref, pdn[k], pjx[k], pjy[k], pjz[k],
+                                              gp * Sx, gp * Sy, gp * Sz, inv_tau, guo_pref,
+                                              (const T*)nullptr);
+                } else {
+                    T fin[Q];
+                    static_for<0, Q>([&](auto I) {
+                        constexpr int i = decltype(I)::value;
+                        fin[i] = bload<T, i>(sbuf, pzo[1 - CZ[i]] + yo[1 - CY[i]] + xo[1 - CX[i]]);
+                    });
+                    collide_store<T, C, false>(dbuf, off, rho_ref, pdn[k], pjx[k], pjy[k], pjz[k],
+                                               gp * Sx, gp * Sy, gp * Sz, inv_tau, guo_pref, fin);
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) {
+            pdn[k] = cdn[k];
+            pjx[k] = cjx[k];
+            pjy[k] = cjy[k];
+            pjz[k] = cjz[k];
+        }
+        pzo[0] = zo[0];
+        pzo[1] = zo[1];
+        pzo[2] = zo[2];
+    }
+}
+
 template <typename T, typename C, int PSI, bool TAU1, int R, bool PF, int WAVES, int BXT>
 __global__ __launch_bounds__(64 * WAVES) void k_step(StepArgs a, const T* __restrict__ src,
                                                      T* __restrict__ dst)
@@ -462,7 +626,8 @@ __global__ __launch_bounds__(64 * WAVES) void k_step(StepArgs a, const T* __rest
     const int ch = (int)(t2 / (unsigned)a.tiles_y);
     const int z0 = ch * a.zc;
     const int z1 = min(z0 + a.zc, a.b.nz);
-    step_tile<T, C, PSI, TAU1, R, PF, WAVES, BXT>(a.b, src, dst, tix, tiy, z0, z1, ring);
+    if constexpr (BXT == 0) step_rows<T, C, PSI, TAU1, R, WAVES>(a.b, src, dst, a.by, tiy, z0, z1, ring);
+    else step_tile<T, C, PSI, TAU1, R, PF, WAVES, BXT>(a.b, src, dst, tix, tiy, z0, z1, ring);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -496,12 +661,22 @@ __device__ __forceinline__ void group_item(const GroupBox* __restrict__ boxes, i
     const T* src = (const T*)g.pop[s];
     T* dst = (T*)g.pop[1 - s];
     const bool tau1 = g.b.tau == 1.0;
-    if (g.b.psi == 0) {
-        if (tau1) step_tile<T, T, 0, true, R, PF, WAVES, BXT>(g.b, src, dst, tix, tiy, z0, z1, ring);
-        else step_tile<T, T, 0, false, R, PF, WAVES, BXT>(g.b, src, dst, tix, tiy, z0, z1, ring);
+    if constexpr (BXT == 0) {
+        if (g.b.psi == 0) {
+            if (tau1) step_rows<T, T, 0, true, R, WAVES>(g.b, src, dst, g.by, tiy, z0, z1, ring);
+            else step_rows<T, T, 0, false, R, WAVES>(g.b, src, dst, g.by, tiy, z0, z1, ring);
+        } else {
+            if (tau1) step_rows<T, T, 1, true, R, WAVES>(g.b, src, dst, g.by, tiy, z0, z1, ring);
+            else step_rows<T, T, 1, false, R, WAVES>(g.b, src, dst, g.by, tiy, z0, z1, ring);
+        }
     } else {
-        if (tau1) step_tile<T, T, 1, true, R, PF, WAVES, BXT>(g.b, src, dst, tix, tiy, z0, z1, ring);
-        else step_tile<T, T, 1, false, R, PF, WAVES, BXT>(g.b, src, dst, tix, tiy, z0, z1, ring);
+        if (g.b.psi == 0) {
+            if (tau1) step_tile<T, T, 0, true, R, PF, WAVES, BXT>(g.b, src, dst, tix, tiy, z0, z1, ring);
+            else step_tile<T, T, 0, false, R, PF, WAVES, BXT>(g.b, src, dst, tix, tiy, z0, z1, ring);
+        } else {
+            if (tau1) step_tile<T, T, 1, true, R, PF, WAVES, BXT>(g.b, src, dst, tix, tiy, z0, z1, ring);
+            else step_tile<T, T, 1, false, R, PF, WAVES, BXT>(g.b, src, dst, tix, tiy, z0, z1, ring);
+        }
     }
 }
 
@@ -559,12 +734,18 @@ hipError_t launch_step_t(const StepArgs& a, const void* src, void* dst, hipStrea
 }
 
 // Supported launch shapes (checked by shape_supported): 4 waves with rows 1, 2 or 4 and either
-// prefetch setting; 8 waves with rows 1 or 2 and no prefetch; tile width 32 with rows 1 or 2.
+// prefetch setting; 8 waves with rows 1 or 2 and no prefetch; tile width 32 with rows 1 or 2;
+// full-row tiles (tile width 0) with 8 waves, 4 or 8 nodes per thread and no prefetch.
 template <typename T, typename C, int PSI, bool TAU1>
 hipError_t dispatch_pf(const StepShape& s, const StepArgs& a, const void* src, void* dst,
                        hipStream_t st)
 {
 #define LBM_STEP(R, PF, WV, BXT) launch_step_t<T, C, PSI, TAU1, R, PF, WV, BXT>(a, src, dst, st)
+    if (s.tile_x == 0) {
+        // 8 nodes per thread only with single-precision arithmetic (in double it spills)
+        if constexpr (sizeof(C) == 8) return s.rows == 4 ? LBM_STEP(4, false, 8, 0) : hipErrorInvalidValue;
+        else return s.rows == 4 ? LBM_STEP(4, false, 8, 0) : LBM_STEP(8, false, 8, 0);
+    }
     if (s.waves == 8) {
         if (s.tile_x == 32) return s.rows == 1 ? LBM_STEP(1, false, 8, 32) : LBM_STEP(2, false, 8, 32);
         return s.rows == 1 ? LBM_STEP(1, false, 8, 64) : LBM_STEP(2, false, 8, 64);
@@ -998,9 +1179,17 @@ hipError_t launch_step(bool fp32, bool math64, const BoxDesc& b, const StepShape
     if (!shape_supported(s)) return hipErrorInvalidValue;
     StepArgs a;
     a.b = b;
-    a.tiles_x = (b.nx + s.tile_x - 1) / s.tile_x;
-    const int by = tile_height(s);
-    a.tiles_y = (b.ny + by - 1) / by;
+    a.by = 0;
+    if (s.tile_x == 0) {
+        a.by = row_tile_rows(s, b.px);
+        if (a.by < 1) return hipErrorInvalidValue;
+        a.tiles_x = 1;
+        a.tiles_y = (b.ny + a.by - 1) / a.by;
+    } else {
+        a.tiles_x = (b.nx + s.tile_x - 1) / s.tile_x;
+        const int by = tile_height(s);
+        a.tiles_y = (b.ny + by - 1) / by;
+    }
     a.zc = s.z_chunk < b.nz ? s.z_chunk : b.nz;
     a.nchunks = (b.nz + a.zc - 1) / a.zc;
     a.remap = s.xcd_remap;
@@ -1030,6 +1219,10 @@ hipError_t launch_group_shape(const StepShape& s, const GroupBox* boxes, int nbo
 {
 #define LBM_GROUP(R, PF, WV, BXT) \
     launch_group_t<T, R, PF, WV, BXT>(boxes, nbox, nitems, parity, persistent, s.xcd_remap, workers, q, st)
+    if (s.tile_x == 0) {
+        if constexpr (sizeof(T) == 8) return s.rows == 4 ? LBM_GROUP(4, false, 8, 0) : hipErrorInvalidValue;
+        else return s.rows == 4 ? LBM_GROUP(4, false, 8, 0) : LBM_GROUP(8, false, 8, 0);
+    }
     if (s.waves == 8) {
         if (s.tile_x == 32) return s.rows == 1 ? LBM_GROUP(1, false, 8, 32) : LBM_GROUP(2, false, 8, 32);
         return s.rows == 1 ? LBM_GROUP(1, false, 8, 64) : LBM_GROUP(2, false, 8, 64);

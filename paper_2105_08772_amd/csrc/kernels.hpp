@@ -23,14 +23,15 @@ struct BoxDesc {
 
 // Launch shape of the fused step kernel. The workgroup is 64 * waves threads (waves wave64s); the
 // tile is tile_x nodes wide (64, or 32 with each wave row split into two sub-rows), tile_height()
-// rows high and z_chunk planes deep.
+// rows high and z_chunk planes deep. tile_x = 0 selects full-row tiles: the whole x extent and
+// row_tile_rows() rows, with `rows` nodes per thread and plane.
 struct StepShape {
-    int rows;        // rows of the tile per wave (1, 2 or 4)
+    int rows;        // rows of the tile per wave (1, 2 or 4); full-row tiles: nodes per thread (4, 8)
     int waves;       // wave64s per workgroup (4 or 8)
     int z_chunk;     // planes marched per workgroup
     int xcd_remap;   // 1: map consecutive logical tiles to one XCD
     int prefetch;    // 1: issue the next plane's loads before the barrier (software pipelining)
-    int tile_x;      // tile width: 64 or 32
+    int tile_x;      // tile width: 64, 32, or 0 for full-row tiles
 };
 
 // The compiled shapes: 4 waves with rows 1, 2 or 4 (rows 1 or 2 at tile width 32), either
@@ -38,6 +39,7 @@ struct StepShape {
 inline bool shape_supported(const StepShape& s)
 {
     if (s.z_chunk < 1 || (s.xcd_remap & ~1) || (s.prefetch & ~1)) return false;
+    if (s.tile_x == 0) return s.waves == 8 && s.prefetch == 0 && (s.rows == 4 || s.rows == 8);
     if (s.tile_x != 64 && s.tile_x != 32) return false;
     if (s.waves == 4) return s.rows == 1 || s.rows == 2 || (s.rows == 4 && s.tile_x == 64);
     if (s.waves == 8) return (s.rows == 1 || s.rows == 2) && s.prefetch == 0;
@@ -46,6 +48,13 @@ inline bool shape_supported(const StepShape& s)
 
 inline int tile_height(const StepShape& s) { return s.waves * s.rows * (64 / s.tile_x); }
 
+// Interior rows of a full-row tile for row pitch px: the tile pulls by + 2 rows of px nodes into
+// rows * 64 * waves thread slots (< 1: the rows are too long for full-row tiles).
+inline int row_tile_rows(const StepShape& s, unsigned px)
+{
+    return (int)((unsigned)(s.rows * 64 * s.waves) / px) - 2;
+}
+
 // One box of a multi-box step.
 struct GroupBox {
     BoxDesc b;
@@ -53,6 +62,7 @@ struct GroupBox {
     int phase;              // pop[phase] holds the box's current state when the group's step
                             // counter is even
     int tiles_x, tiles_y, zc;
+    int by;                 // full-row tiles: interior rows per tile
     unsigned item_begin;    // first work item of the box
     unsigned items;         // tiles_x * tiles_y * ceil(nz / zc)
 };

@@ -18,6 +18,10 @@ namespace {
 
 thread_local std::string g_err = "no error";
 
+const char* const SHAPE_MSG =
+    "unsupported launch shape (tile_x 64: waves 4 with rows 1, 2, 4, or waves 8 with rows 1, 2 and no "
+    "prefetch; tile_x 32: rows 1, 2 (waves 8: no prefetch); tile_x 0: waves 8, rows 4 or 8, no prefetch)";
+
 int fail(int code, const std::string& msg)
 {
     g_err = msg;
@@ -345,6 +349,26 @@ int observe(lbm_sc* h, lbm_sc_obs* o, double* prof_out)
     return LBM_SC_OK;
 }
 
+// Tile width and height of a launch shape on a box (full-row tiles: the box's nx and the rows
+// that fit; by < 1 means the box's rows are too long for them).
+void tile_dims(const lbm::StepShape& s, const lbm::BoxDesc& b, int& bx, int& by)
+{
+    if (s.tile_x == 0) {
+        bx = b.nx;
+        by = lbm::row_tile_rows(s, b.px);
+    } else {
+        bx = s.tile_x;
+        by = lbm::tile_height(s);
+    }
+}
+
+bool shape_fits(const lbm::StepShape& s, const lbm::BoxDesc& b)
+{
+    int bx, by;
+    tile_dims(s, b, bx, by);
+    return bx >= 1 && by >= 1;
+}
+
 // Default launch shape: 8-wave workgroups with two rows per wave (64 x 16 tiles), XCD remap on,
 // no prefetch, and the z chunk that minimises (rounds of workgroups over the CUs) x (planes per
 // chunk + the two planes each chunk pulls again): one workgroup per CU already draws its share
@@ -646,8 +670,10 @@ int lbm_sc_get_info(lbm_sc* h, lbm_sc_info* out)
     out->nodes = (int64_t)h->box.n;
     out->device_bytes = h->device_bytes;
     out->bytes_per_step = (int64_t)2 * 19 * (int64_t)h->elem * (int64_t)h->box.n;
-    out->block_x = h->shape.tile_x;
-    out->block_y = lbm::tile_height(h->shape);
+    int bx, by;
+    tile_dims(h->shape, h->box, bx, by);
+    out->block_x = bx;
+    out->block_y = by;
     out->z_chunk = h->shape.z_chunk;
     return LBM_SC_OK;
 }
@@ -666,8 +692,12 @@ int lbm_sc_set_launch(lbm_sc* h, const lbm_sc_launch* l)
     s.prefetch = l->prefetch;
     s.tile_x = l->tile_x;
     if (!lbm::shape_supported(s))
-        return fail(LBM_SC_EINVAL, "unsupported tile shape (waves 4: rows 1, 2, 4, or 1, 2 at tile_x 32; "
-                                   "waves 8: rows 1, 2 without prefetch)");
+        return fail(LBM_SC_EINVAL, SHAPE_MSG);
+    if (!shape_fits(s, h->box))
+        return fail(LBM_SC_EINVAL, "rows too long for full-row tiles of this size (use more nodes per "
+                                   "thread or tile_x 64)");
+    if (s.tile_x == 0 && s.rows == 8 && (!h->fp32 || h->math64))
+        return fail(LBM_SC_EINVAL, "full-row tiles with 8 nodes per thread need FP32 arithmetic");
     h->shape.rows = l->rows;
     h->shape.waves = l->waves;
     h->shape.tile_x = l->tile_x;
@@ -759,14 +789,16 @@ int group_rebuild(lbm_sc_group* g)
     g->bytes_per_step = 0;
     std::vector<double> work;   // nodes per item, box-major
     const lbm::StepShape shape = group_shape(L);
-    const int bx = shape.tile_x, by = lbm::tile_height(shape);
     for (lbm_sc* h : g->boxes) {
+        int bx, by;
+        tile_dims(shape, h->box, bx, by);
         lbm::GroupBox d;
         std::memset(&d, 0, sizeof(d));
         d.b = h->box;
         d.pop[0] = h->pop[0];
         d.pop[1] = h->pop[1];
         d.phase = h->cur;
+        d.by = shape.tile_x == 0 ? by : 0;
         d.tiles_x = (h->box.nx + bx - 1) / bx;
         d.tiles_y = (h->box.ny + by - 1) / by;
         d.zc = L.z_chunk < h->box.nz ? L.z_chunk : h->box.nz;
@@ -833,9 +865,7 @@ int check_group_launch(const lbm_sc_group_launch* l)
 {
     if (l->z_chunk < 1) return fail(LBM_SC_EINVAL, "z_chunk must be >= 1");
     if ((l->xcd_remap | l->prefetch | l->persistent) & ~1) return fail(LBM_SC_EINVAL, "flags must be 0 or 1");
-    if (!lbm::shape_supported(group_shape(*l)))
-        return fail(LBM_SC_EINVAL, "unsupported tile shape (waves 4: rows 1, 2, 4, or 1, 2 at tile_x 32; "
-                                   "waves 8: rows 1, 2 without prefetch)");
+    if (!lbm::shape_supported(group_shape(*l))) return fail(LBM_SC_EINVAL, SHAPE_MSG);
     if (l->workers < 0 || l->workers % 8 || l->workers > 65536)
         return fail(LBM_SC_EINVAL, "workers must be a multiple of 8 in [0, 65536]");
     if (l->graph_steps < 0 || l->graph_steps % 2 || l->graph_steps > 4096)
@@ -888,6 +918,11 @@ int lbm_sc_group_set(lbm_sc_group* g, lbm_sc* const* boxes, int32_t nbox)
             return fail(LBM_SC_EINVAL, "all boxes of a group must share one precision");
         for (int j = 0; j < i; ++j)
             if (boxes[j] == boxes[i]) return fail(LBM_SC_EINVAL, "a box appears twice");
+        if (!shape_fits(group_shape(g->launch), boxes[i]->box))
+            return fail(LBM_SC_EINVAL, "box " + std::to_string(i) +
+                                           ": rows too long for the group's full-row tiles");
+        if (g->launch.tile_x == 0 && g->launch.rows == 8 && !boxes[i]->fp32)
+            return fail(LBM_SC_EINVAL, "full-row tiles with 8 nodes per thread need FP32 boxes");
     }
     g->boxes.assign(boxes, boxes + nbox);
     g->fp32 = nbox > 0 && boxes[0]->fp32;
@@ -952,6 +987,13 @@ int lbm_sc_group_set_launch(lbm_sc_group* g, const lbm_sc_group_launch* l)
     if (!g || !l) return fail(LBM_SC_EINVAL, "group or launch is NULL");
     int rc = check_group_launch(l);
     if (rc) return rc;
+    for (size_t i = 0; i < g->boxes.size(); ++i) {
+        if (!shape_fits(group_shape(*l), g->boxes[i]->box))
+            return fail(LBM_SC_EINVAL, "box " + std::to_string(i) +
+                                           ": rows too long for full-row tiles of this launch");
+        if (l->tile_x == 0 && l->rows == 8 && !g->boxes[i]->fp32)
+            return fail(LBM_SC_EINVAL, "full-row tiles with 8 nodes per thread need FP32 boxes");
+    }
     g->launch = *l;
     return group_rebuild(g);
 }

@@ -15,7 +15,8 @@ def _sync():
 
 SHAPES = [dict(waves=4, rows=r, prefetch=pf, tile_x=64) for r in (1, 2, 4) for pf in (0, 1)] + \
          [dict(waves=4, rows=r, prefetch=pf, tile_x=32) for r in (1, 2) for pf in (0, 1)] + \
-         [dict(waves=8, rows=r, prefetch=0, tile_x=bx) for r in (1, 2) for bx in (64, 32)]
+         [dict(waves=8, rows=r, prefetch=0, tile_x=bx) for r in (1, 2) for bx in (64, 32)] + \
+         [dict(waves=8, rows=r, prefetch=0, tile_x=0) for r in (4, 8)]   # full-row tiles
 
 
 def group_candidates():
@@ -30,9 +31,13 @@ def group_candidates():
 def tune_group(group, steps=8, candidates=None, log=None):
     """Try each candidate on `group` (a paper_2105_08772_amd.Group) for `steps` steps; set and
     return the fastest as a dict with its seconds per step."""
+    from . import LbmScError
     best = None
     for cand in candidates or group_candidates():
-        group.set_launch(graph_steps=steps, **cand)
+        try:
+            group.set_launch(graph_steps=steps, **cand)
+        except LbmScError:
+            continue               # shape not available for these boxes (e.g. rows too long)
         group.step(steps)          # warm-up: first capture and replay
         _sync()
         t0 = time.perf_counter()
@@ -57,10 +62,14 @@ def box_candidates(nz):
 
 def tune_box(box, steps=16, candidates=None, log=None):
     """Same for one box (a paper_2105_08772_amd.Box)."""
+    from . import LbmScError
     best = None
     for cand in candidates or box_candidates(box.dims[2]):
-        box.set_launch(cand["rows"], cand["z_chunk"], cand["xcd_remap"], cand["prefetch"],
-                       cand["waves"], cand["tile_x"])
+        try:
+            box.set_launch(cand["rows"], cand["z_chunk"], cand["xcd_remap"], cand["prefetch"],
+                           cand["waves"], cand["tile_x"])
+        except LbmScError:
+            continue
         box.step(2)
         _sync()
         t0 = time.perf_counter()

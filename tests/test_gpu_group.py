@@ -54,6 +54,10 @@ LAUNCHES = [
          tile_x=32),
     dict(rows=2, z_chunk=3, xcd_remap=0, prefetch=0, persistent=1, workers=40, graph_steps=2,
          waves=8, tile_x=32),
+    dict(rows=4, z_chunk=6, xcd_remap=1, prefetch=0, persistent=0, workers=0, graph_steps=4,
+         waves=8, tile_x=0),
+    dict(rows=4, z_chunk=16, xcd_remap=1, prefetch=0, persistent=1, workers=16, graph_steps=0,
+         waves=8, tile_x=0),
 ]
 
 
@@ -80,6 +84,37 @@ def test_group_equals_boxes_alone(prec, li):
         assert np.array_equal(a, b), f"box {k} differs from the same box stepped alone"
     for b in boxes:
         b.close()
+
+
+def test_group_full_row_tiles_8_nodes_per_thread():
+    """8 nodes per thread (FP32 only): bitwise equal to the boxes stepped alone; FP64 groups
+    reject the shape."""
+    import torch
+    s = torch.cuda.Stream()
+    launch = dict(rows=8, z_chunk=8, xcd_remap=1, prefetch=0, persistent=1, workers=64,
+                  graph_steps=4, waves=8, tile_x=0)
+    cfgs = box_configs(lbm.LBM_SC_FP32_SHIFTED, s.cuda_stream)
+    want = alone(cfgs, 9)
+    boxes = [lbm.Box(c) for c in cfgs]
+    with lbm.Group(s.cuda_stream) as g:
+        g.set_launch(**launch)
+        g.set(boxes)
+        g.step(9)
+        got = [b.get() for b in boxes]
+    for k, (a, b) in enumerate(zip(got, want)):
+        assert np.array_equal(a, b), f"box {k} differs from the same box stepped alone"
+    for b in boxes:
+        b.close()
+    b64 = lbm.Box(box_configs(lbm.LBM_SC_FP64, s.cuda_stream)[0])
+    with lbm.Group(s.cuda_stream) as g:
+        g.set([b64])
+        with pytest.raises(lbm.LbmScError):
+            g.set_launch(**launch)
+        g.set([])
+        g.set_launch(**launch)
+        with pytest.raises(lbm.LbmScError):
+            g.set([b64])
+    b64.close()
 
 
 def test_group_resyncs_after_a_box_steps_alone_and_after_resets():

@@ -133,7 +133,10 @@ def test_launch_shapes_are_bitwise_identical(prec):
     shapes = ((1, 1, 0, 0, 4, 64), (2, 7, 1, 1, 4, 64), (4, 33, 1, 0, 4, 64),
               (4, 5, 0, 1, 4, 64), (1, 64, 1, 1, 4, 64), (2, 3, 0, 0, 4, 64),
               (2, 9, 1, 0, 8, 64), (1, 33, 0, 0, 8, 64), (1, 2, 1, 1, 4, 32), (2, 5, 0, 1, 4, 32),
-              (2, 11, 1, 0, 4, 32), (1, 4, 1, 0, 8, 32), (2, 33, 0, 0, 8, 32))
+              (2, 11, 1, 0, 4, 32), (1, 4, 1, 0, 8, 32), (2, 33, 0, 0, 8, 32),
+              (4, 7, 1, 0, 8, 0), (4, 33, 0, 0, 8, 0))
+    if prec == lbm.LBM_SC_FP32_SHIFTED:
+        shapes += ((8, 5, 1, 0, 8, 0), (8, 33, 0, 0, 8, 0))
     for rows, zc, remap, pf, waves, tx in shapes:
         with make_box(dims, prec=prec, rho_ref=rho_ref) as b:
             b.set(f)
@@ -145,11 +148,46 @@ def test_launch_shapes_are_bitwise_identical(prec):
     for o in outs[1:]:
         assert np.array_equal(o, outs[0])
     with make_box(dims, prec=prec, rho_ref=rho_ref) as b:
-        for bad in ((3, 4, 1, 0, 4, 64), (2, 0, 1, 0, 4, 64), (2, 4, 2, 0, 4, 64),
-                    (2, 4, 1, 0, 6, 64), (4, 4, 1, 0, 8, 64), (2, 4, 1, 1, 8, 64),
-                    (4, 4, 1, 0, 4, 32), (2, 4, 1, 0, 4, 16)):
+        bad_shapes = [(3, 4, 1, 0, 4, 64), (2, 0, 1, 0, 4, 64), (2, 4, 2, 0, 4, 64),
+                      (2, 4, 1, 0, 6, 64), (4, 4, 1, 0, 8, 64), (2, 4, 1, 1, 8, 64),
+                      (4, 4, 1, 0, 4, 32), (2, 4, 1, 0, 4, 16), (4, 4, 1, 0, 4, 0),
+                      (2, 4, 1, 0, 8, 0), (4, 4, 1, 1, 8, 0)]
+        if prec != lbm.LBM_SC_FP32_SHIFTED:
+            bad_shapes.append((8, 4, 1, 0, 8, 0))   # 8 nodes per thread: FP32 arithmetic only
+        for bad in bad_shapes:
             with pytest.raises(lbm.LbmScError):
                 b.set_launch(*bad)
+    # full-row tiles need rows that fit: px = 704 leaves no room for 4 nodes per thread
+    with make_box((700, 3, 2), prec=prec, rho_ref=rho_ref) as b:
+        with pytest.raises(lbm.LbmScError):
+            b.set_launch(4, 2, 1, 0, 8, 0)
+
+
+@pytest.mark.parametrize("dims", SHAPES + [(100, 37, 9), (129, 5, 4)])
+@pytest.mark.parametrize("prec", [lbm.LBM_SC_FP64, lbm.LBM_SC_FP32_SHIFTED])
+def test_full_row_tiles_one_step(dims, prec):
+    """Full-row tiles (tile_x 0) against the oracle (FP64, 1e-11) and bitwise against the default
+    x-y tiles (FP32) after one and three steps, on tiny, ragged and multi-tile boxes."""
+    say(f"full-row tiles dims={dims} prec={prec}")
+    rho_ref = 1.5
+    f = fp32_representable(inputs.random_populations(dims, 5 + sum(dims), W * 1.5, amp=0.3), rho_ref)
+    G = 1.3 * lbm.lbm_sc_gc(0)
+    outs = []
+    for launch in (None, (4, 3, 1, 0, 8, 0)) + (((8, 2, 0, 0, 8, 0),)
+                                                 if prec == lbm.LBM_SC_FP32_SHIFTED else ()):
+        with make_box(dims, prec=prec, rho_ref=rho_ref) as b:
+            b.set(f)
+            if launch:
+                b.set_launch(*launch)
+            b.step(1)
+            g1 = b.get()
+            b.step(2)
+            outs.append((g1, b.get()))
+    if prec == lbm.LBM_SC_FP64:
+        ref = core.step(f, G, 1.0, 0)
+        assert rel_err(outs[1][0], ref) <= TOL64
+    for g1, g3 in outs[1:]:
+        assert np.array_equal(g1, outs[0][0]) and np.array_equal(g3, outs[0][1])
 
 
 def droplet_cfg(prec=lbm.LBM_SC_FP64, n=32, R=8.0, seed=1, noise=1e-6, geom=lbm.LBM_SC_DROPLET,
