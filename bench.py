@@ -145,6 +145,8 @@ def run_batched(args, torch, lbm, stream, steps, log):
             fp64.append(b64.observables(profile=False, raise_unstable=False)[0])
     dP_err = [abs(obs32[k]["dP"] - o["dP"]) / abs(o["dP"]) for k, o in zip(subset, fp64)
               if o["finite"] and obs32[k]["finite"] and o["dP"] != 0]
+    per_box = [dict(L=spec[k]["L"], bubble=spec[k]["bubble"], g_over_gc=round(spec[k]["g_over_gc"], 4),
+                    dP_fp32=obs32[k]["dP"], dP_fp64=o["dP"]) for k, o in zip(subset, fp64)]
     group.close()
     for b in boxes:
         b.close()
@@ -170,7 +172,9 @@ def run_batched(args, torch, lbm, stream, steps, log):
                                                                   (mlups64 * 1e6)) * len(boxes), 1),
                              "dP_rel_err_fp32_vs_fp64_max": max(dP_err) if dP_err else None,
                              "dP_rel_err_fp32_vs_fp64_median": float(sorted(dP_err)[len(dP_err) // 2])
-                             if dP_err else None},
+                             if dP_err else None,
+                             "steps_compared": steps_done,
+                             "per_box": per_box},
         "speedup_vs_fp64_single": round(mlups / mlups64, 2),
     }
 
@@ -190,7 +194,10 @@ def run_served(args, torch, lbm, log):
     rate = args.served_rate
     spec = inputs.served_requests(seed=8772, count=args.served_count, rate=rate)
     be = serve.GpuBackend()
-    be.set_launch(rows=2, z_chunk=16, prefetch=0, persistent=0, workers=0, graph_steps=64)
+    # full-row tiles (the fastest shape of the batched mix; the backend falls back to x-y tiles
+    # for a box whose rows are too long)
+    be.set_launch(rows=4, waves=8, tile_x=0, z_chunk=8, prefetch=0, persistent=0, workers=0,
+                  graph_steps=64)
     budget = be.free_bytes() - (8 << 30)
     srv = serve.Server(be, budget, chunk=512, observe_every=2048, max_steps=100000,
                        dp_tol=1e-5, du_tol=1e-9, log=log)
@@ -281,7 +288,8 @@ def run_tolman(args, torch, lbm, log):
 
     def sweep(prec):
         be = serve.GpuBackend(prec=prec, width=1.0)
-        be.set_launch(rows=2, z_chunk=16, prefetch=0, persistent=0, workers=0, graph_steps=64)
+        be.set_launch(rows=4, waves=8, tile_x=0, z_chunk=8, prefetch=0, persistent=0, workers=0,
+                      graph_steps=64)
         srv = serve.Server(be, be.free_bytes() - (8 << 30), chunk=512, observe_every=2048,
                            max_steps=100000, dp_tol=1e-5, du_tol=0.0, log=log)
         for k, v in spec.items():

@@ -73,12 +73,13 @@ class GpuBackend:
     def __init__(self, prec=None, stream=None, tau=1.0, width=2.0, noise_amp=1e-6):
         import torch
 
-        from . import (LBM_SC_BUBBLE, LBM_SC_DROPLET, LBM_SC_FP32_SHIFTED, Box, Group, config,
-                       lbm_sc_device_bytes)
+        from . import (LBM_SC_BUBBLE, LBM_SC_DROPLET, LBM_SC_FP32_SHIFTED, Box, Group, LbmScError,
+                       config, lbm_sc_device_bytes)
         self._torch = torch
         self.stream = stream or torch.cuda.Stream()
         self.prec = LBM_SC_FP32_SHIFTED if prec is None else prec
         self._Box, self._Group, self._config = Box, Group, config
+        self._error = LbmScError
         self._bubble, self._droplet = LBM_SC_BUBBLE, LBM_SC_DROPLET
         self._bytes = lbm_sc_device_bytes
         self.tau, self.width, self.noise_amp = tau, width, noise_amp
@@ -101,8 +102,20 @@ class GpuBackend:
     def create(self, r):
         return self._Box(self.config(r))
 
+    # x-y tiles: every box size fits them (full-row tiles need rows short enough for the workgroup)
+    FALLBACK = dict(rows=2, waves=4, tile_x=64, prefetch=0)
+
     def set_active(self, boxes):
-        self.group.set(boxes)
+        try:
+            self.group.set(boxes)
+        except self._error:
+            launch = self.group.launch()
+            if launch["tile_x"] != 0:
+                raise
+            # a box's rows are too long for the full-row tiles: switch the group to x-y tiles
+            self.group.set([])
+            self.group.set_launch(**self.FALLBACK)
+            self.group.set(boxes)
 
     def set_launch(self, **kw):
         self.group.set_launch(**kw)

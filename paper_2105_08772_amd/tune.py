@@ -21,7 +21,7 @@ SHAPES = [dict(waves=4, rows=r, prefetch=pf, tile_x=64) for r in (1, 2, 4) for p
 
 def group_candidates():
     out = []
-    for shape, zc in itertools.product(SHAPES, (16, 32, 64)):
+    for shape, zc in itertools.product(SHAPES, (8, 16, 32, 64)):
         out.append(dict(shape, z_chunk=zc, xcd_remap=1, persistent=0, workers=0))
         for workers in (256, 512):
             out.append(dict(shape, z_chunk=zc, xcd_remap=1, persistent=1, workers=workers))

@@ -102,3 +102,32 @@ def test_memory_limited_admission_gives_the_same_results(mixed):
     for rid, r in limited.items():
         assert (r.status, r.steps) == (recs[rid].status, recs[rid].steps)
         assert np.array_equal(r.final, recs[rid].final)
+
+
+def test_backend_falls_back_to_xy_tiles_for_long_rows():
+    """A group on full-row tiles cannot take a box whose rows are too long for the workgroup;
+    the backend then switches the group to x-y tiles, and stepping still equals the boxes alone."""
+    import paper_2105_08772_amd as lbm
+    be = serve.GpuBackend()
+    be.set_launch(rows=4, waves=8, tile_x=0, z_chunk=8, prefetch=0, persistent=0, workers=0,
+                  graph_steps=0)
+    small = be.create(serve.Request(rid=0, L=16, radius=4.0, g_over_gc=1.3, bubble=False, seed=1))
+    cfg = lbm.config(700, 3, 2, psi=0, geom=lbm.LBM_SC_SLAB, prec=lbm.LBM_SC_FP32_SHIFTED,
+                     g_over_gc=1.3, slab_thickness=350.0, width=2.0, slab_axis=0,
+                     stream=be.stream.cuda_stream)
+    wide = lbm.Box(cfg)
+    be.set_active([small])
+    assert be.group.launch()["tile_x"] == 0
+    be.set_active([small, wide])
+    assert be.group.launch()["tile_x"] == 64
+    f_small, f_wide = small.get(), wide.get()
+    be.step(4)
+    got = [small.get(), wide.get()]
+    for b, f in ((small, f_small), (wide, f_wide)):
+        b.set(f)
+        b.step(4)
+    assert np.array_equal(got[0], small.get()) and np.array_equal(got[1], wide.get())
+    be.group.set([])
+    small.close()
+    wide.close()
+    be.close()
