@@ -267,17 +267,35 @@ def run_served(args, torch, lbm, log):
 
 
 def run_tolman(args, torch, lbm, log):
-    """A scaled version of the paper's droplet/bubble sweep (Sec. 4): couplings G/G_c - 1 in
-    {0.159, 0.215, 0.293}, odd box sizes L in {41, ..., 123}, R = L/4, droplets and
-    bubbles, exp psi, the paper's tanh profile (width 1), all boxes served together until the
-    paper's criterion (relative dP change < 1e-5 over 2048 steps), once with FP32-shifted and
-    once with FP64 populations. The Tolman fit per coupling gives sigma_0 and delta; sigma_0 is
-    compared with the flat value from a converged FP64 slab (the paper reports that the two
-    agree), and every FP32 result (dP, sigma_s, R_s, and the fitted sigma_0 and delta) is stated
-    against its FP64 counterpart."""
+    """A scaled version of the paper's droplet/bubble sweep (Sec. 4) for both pseudopotentials:
+    couplings G/G_c - 1 in {0.159, 0.215, 0.293}, odd box sizes L in {41, ..., 157}, R = L/4,
+    droplets and bubbles, the paper's tanh profile (width 1), all boxes served together until
+    the paper's criterion (relative dP change < 1e-5 over 2048 steps), once with FP32-shifted
+    and once with FP64 populations. The Tolman fit per coupling gives sigma_0 and delta; sigma_0
+    is compared with the flat value from a converged FP64 slab (the paper reports that the two
+    agree), every FP32 result (dP, sigma_s, R_s, and the fitted sigma_0 and delta) is stated
+    against its FP64 counterpart, and the two pseudopotentials are compared through the
+    mean-field prefactor sigma_0 / (G/G_c - 1)^(3/2)."""
+    out = {"workload": "psi in {exp, 1-exp} x G/G_c-1 in {0.159,0.215,0.293} x L in "
+                       "{41,47,55,61,67,77,87,103,123,157} x {droplet,bubble}, R=L/4, tanh width "
+                       "1, served together until |dP change|/dP < 1e-5 per 2048 steps; "
+                       "FP32-shifted and FP64 sweeps"}
+    for name, psi in (("exp", lbm.LBM_SC_PSI_EXP), ("oneminus", lbm.LBM_SC_PSI_ONEMINUS)):
+        out[name] = tolman_sweep(torch, lbm, log, psi)
+    pref = {}
+    for name in ("exp", "oneminus"):
+        pref[name] = {g: c["flat_sigma0"] / (float(g) - 1) ** 1.5
+                      for g, c in out[name]["couplings"].items()}
+    out["flat_sigma0_prefactor"] = pref
+    out["flat_sigma0_prefactor_ratio_exp_over_oneminus"] = {
+        g: pref["exp"][g] / pref["oneminus"][g] for g in pref["exp"] if g in pref["oneminus"]}
+    return out
+
+
+def tolman_sweep(torch, lbm, log, psi):
     from paper_2105_08772_amd import analysis, serve
     ratios = (1.159, 1.215, 1.293)
-    sizes = (41, 47, 55, 61, 67, 77, 87, 103, 123)
+    sizes = (41, 47, 55, 61, 67, 77, 87, 103, 123, 157)
     spec = {}
     rid = 0
     for g in ratios:
@@ -295,7 +313,7 @@ def run_tolman(args, torch, lbm, log):
         for k, v in spec.items():
             srv.submit(serve.Request(rid=k, L=v["L"], radius=v["L"] / 4.0,
                                      g_over_gc=v["g_over_gc"], bubble=v["bubble"],
-                                     seed=1000 + k, arrival=0.0))
+                                     seed=1000 + k, arrival=0.0, psi=psi))
         recs = srv.run()
         be.close()
         torch.cuda.empty_cache()
@@ -305,24 +323,22 @@ def run_tolman(args, torch, lbm, log):
 
     res = {}
     for name, prec in (("fp32", lbm.LBM_SC_FP32_SHIFTED), ("fp64", lbm.LBM_SC_FP64)):
-        log(f"tolman sweep {name}")
+        log(f"tolman sweep psi={psi} {name}")
         res[name] = sweep(prec)
     # flat sigma_0: FP64 slab 4 x 4 x 64, liquid thickness 32, width 1, 40000 steps
     stream = torch.cuda.Stream()
     flat = {}
     for g in ratios:
-        cfg = lbm.config(4, 4, 64, psi=0, geom=lbm.LBM_SC_SLAB, prec=lbm.LBM_SC_FP64, g_over_gc=g,
-                         slab_thickness=32.0, width=1.0, slab_axis=2, stream=stream.cuda_stream)
+        cfg = lbm.config(4, 4, 64, psi=psi, geom=lbm.LBM_SC_SLAB, prec=lbm.LBM_SC_FP64,
+                         g_over_gc=g, slab_thickness=32.0, width=1.0, slab_axis=2,
+                         stream=stream.cuda_stream)
         with lbm.Box(cfg) as b:
             b.step(40000)
             o, _ = b.observables()
         flat[g] = dict(sigma0=o["sigma0_flat"], pn_spread_rel=o["pn_spread"] / o["P_out"])
     srv32, conv32, fits32 = res["fp32"]
     srv64, conv64, fits64 = res["fp64"]
-    out = {"workload": "G/G_c-1 in {0.159,0.215,0.293} x L in {41,47,55,61,67,77,87,103,123} x "
-                       "{droplet,bubble}, R=L/4, tanh width 1, exp psi, served together until "
-                       "|dP change|/dP < 1e-5 per 2048 steps; FP32-shifted and FP64 sweeps",
-           "wall_s": {"fp32": round(srv32.wall, 2), "fp64": round(srv64.wall, 2)},
+    out = {"wall_s": {"fp32": round(srv32.wall, 2), "fp64": round(srv64.wall, 2)},
            "statuses": {"fp32": srv32.summary()["statuses"], "fp64": srv64.summary()["statuses"]},
            "couplings": {}}
     for g in ratios:

@@ -415,3 +415,51 @@ def test_full_size_bench_workload_sampled():
     say("worst sampled error / max|f| =", worst)
     assert worst <= 1e-6
     assert abs(o1["mass"] - o0["mass"]) <= 1e-7 * o0["mass"]
+
+
+def test_full_size_batched_workload_sampled():
+    """The 64-box batched workload (seed 2105, L ~ U{48..160}, FP32-shifted) in one group with
+    the full-row tiles the benchmark's tuner picks (4 nodes per thread, z chunks of 8, hipGraph
+    chunks of 64 steps): one group step checked on sampled nodes of every 8th box against the
+    oracle's single-node collision, then 64 graph-replayed steps conserving every box's mass."""
+    import torch
+    say("batched 64-box workload, sampled one-step parity")
+    st = torch.cuda.Stream()
+    spec = inputs.batched_boxes()
+    boxes = [lbm.Box(lbm.config(b["L"], psi=0,
+                                geom=lbm.LBM_SC_BUBBLE if b["bubble"] else lbm.LBM_SC_DROPLET,
+                                prec=lbm.LBM_SC_FP32_SHIFTED, tau=1.0, g_over_gc=b["g_over_gc"],
+                                radius=b["radius"], width=2.0, noise_amp=1e-6, seed=b["seed"],
+                                stream=st.cuda_stream)) for b in spec]
+    rng = np.random.default_rng(77)
+    sub = list(range(0, len(boxes), 8))
+    worst = 0.0
+    with lbm.Group(st.cuda_stream) as g:
+        g.set_launch(rows=4, waves=8, tile_x=0, z_chunk=8, prefetch=0, xcd_remap=1, persistent=0,
+                     workers=0, graph_steps=64)
+        g.set(boxes)
+        f0 = {k: boxes[k].get() for k in sub}
+        o0 = [b.observables(profile=False, raise_unstable=False)[0] for b in boxes]
+        g.step(1)
+        for k in sub:
+            L = spec[k]["L"]
+            f1 = boxes[k].get()
+            G = boxes[k].info()["G"]
+            scale = np.abs(f0[k]).max()
+            pts = [tuple(int(v) for v in rng.integers(0, L, 3)) for _ in range(12)]
+            pts += [(L - 1, L - 1, L - 1), (0, L - 1, L // 2), (L - 1, 0, 0)]
+            for (x, y, z) in pts:
+                fs = core.collide_at(f0[k], G, 1.0, 0, x, y, z)
+                for i in range(19):
+                    d = ((x + XI[i, 0]) % L, (y + XI[i, 1]) % L, (z + XI[i, 2]) % L)
+                    worst = max(worst, abs(f1[i, d[2], d[1], d[0]] - fs[i]) / scale)
+            del f0[k]
+        g.step(64)
+        o1 = [b.observables(profile=False, raise_unstable=False)[0] for b in boxes]
+    for b in boxes:
+        b.close()
+    say("worst sampled error / max|f| =", worst)
+    assert worst <= 1e-6
+    for a, b in zip(o0, o1):
+        assert b["finite"]
+        assert abs(b["mass"] - a["mass"]) <= 1e-7 * a["mass"]
