@@ -369,18 +369,27 @@ bool shape_fits(const lbm::StepShape& s, const lbm::BoxDesc& b)
     return bx >= 1 && by >= 1;
 }
 
-// Default launch shape: 8-wave workgroups with two rows per wave (64 x 16 tiles), XCD remap on,
-// no prefetch, and the z chunk that minimises (rounds of workgroups over the CUs) x (planes per
-// chunk + the two planes each chunk pulls again): one workgroup per CU already draws its share
-// of the bandwidth, so a partly filled last round costs a whole round (measured on MI355X:
-// 288 workgroups of a 192^3 box run 30 % slower than 252).
+// Default launch shape (measured on MI355X at 256^3). Single-precision arithmetic: 8-wave
+// workgroups with two rows per wave (64 x 16 tiles), no prefetch (114 VGPRs: two workgroups per
+// CU hide the latency). Double-precision arithmetic needs about twice the registers, so 4-wave
+// workgroups with the next plane prefetched win: 64 x 16 tiles for FP64 storage, 64 x 8 for FP32
+// storage with FP64 arithmetic. XCD remap on. The z chunk minimises (rounds of workgroups over
+// the CUs) x (planes per chunk + the two planes each chunk pulls again): one workgroup per CU
+// already draws its share of the bandwidth, so a partly filled last round costs a whole round
+// (288 workgroups of a 192^3 box run 30 % slower than 252).
 void default_shape(lbm_sc* h)
 {
-    h->shape.rows = 2;
-    h->shape.waves = 8;
     h->shape.xcd_remap = 1;
-    h->shape.prefetch = 0;
     h->shape.tile_x = 64;
+    if (h->fp32 && !h->math64) {
+        h->shape.rows = 2;
+        h->shape.waves = 8;
+        h->shape.prefetch = 0;
+    } else {
+        h->shape.rows = h->fp32 ? 2 : 4;
+        h->shape.waves = 4;
+        h->shape.prefetch = 1;
+    }
     int cus = 0;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
