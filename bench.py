@@ -384,10 +384,21 @@ def tolman_sweep(torch, lbm, log, psi):
     return out
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(args, nodes_gpu):
     """The FP64 oracle on the host cores: its own initial state of the same droplet, then
-    `cpu_steps` plain steps of the whole box."""
-    import numpy as np  # noqa: F401
+    `cpu_steps` plain steps of the whole box on all threads; plus one step of a 128^3 box of the
+    same droplet (radius scaled) on one thread for the single-core rate."""
     import oracle
     from oracle import core, eos
     oracle.build(force=False)
@@ -398,14 +409,28 @@ def cpu_baseline(args, nodes_gpu):
     n0 = core.init_density(L, L, L, core.DROPLET, args.radius, 2.0, nl, ng, 1e-6, 3)
     f = core.init_populations(n0, G, kind)
     del n0
+    threads = core.threads()
     t0 = time.perf_counter()
     f = core.run(f, G, 1.0, kind, args.cpu_steps)
     dt = time.perf_counter() - t0
+    del f
     nodes = L ** 3
+    # single core, smaller box
+    Ls = 128
+    n0 = core.init_density(Ls, Ls, Ls, core.DROPLET, args.radius * Ls / L, 2.0, nl, ng, 1e-6, 3)
+    f = core.init_populations(n0, G, kind)
+    core.set_threads(1)
+    t1 = time.perf_counter()
+    core.run(f, G, 1.0, kind, 1)
+    dt1 = time.perf_counter() - t1
+    core.set_threads(threads)
     return {"value": round(nodes * args.cpu_steps / dt / 1e6, 3), "unit": "MLUPS",
-            "cores": core.threads(), "kind": "oracle",
+            "cores": threads, "kind": "oracle",
             "sample": f"{args.cpu_steps} steps of the whole {L}^3 droplet (FP64 oracle, "
-                      f"{dt:.1f} s)"}
+                      f"{dt:.1f} s on {threads} threads)",
+            "cpu_model": cpu_model(),
+            "one_core_MLUPS": round(Ls ** 3 / dt1 / 1e6, 3),
+            "one_core_sample": f"1 step of a {Ls}^3 droplet on 1 thread ({dt1:.1f} s)"}
 
 
 PREC_NAMES = {"fp32": "FP32-shifted", "fp32m64": "FP32-shifted (FP64 arithmetic)",
@@ -431,7 +456,7 @@ def main():
     ap.add_argument("--waves", type=int, default=0)
     ap.add_argument("--tile-x", type=int, default=-1, help="64, 32, or 0 for full-row tiles")
     ap.add_argument("--tune", action="store_true", help="sweep launch shapes, keep the fastest")
-    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--cpu-steps", type=int, default=15)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-copy", action="store_true")
     ap.add_argument("--mode", choices=["step", "copy"], default="step",

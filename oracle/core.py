@@ -62,6 +62,8 @@ def lib():
         L.ora_run.argtypes = [_D, i, i, i, d, d, i, ll]
         L.ora_threads.argtypes = []
         L.ora_threads.restype = i
+        L.ora_set_threads.argtypes = [i]
+        L.ora_set_threads.restype = None
         _lib = L
     return _lib
 
@@ -90,6 +92,11 @@ def tables():
 def threads():
     """OpenMP threads the oracle's loops use."""
     return lib().ora_threads()
+
+
+def set_threads(n):
+    """Set the OpenMP threads of the oracle's loops."""
+    lib().ora_set_threads(int(n))
 
 
 def psi(n, kind):

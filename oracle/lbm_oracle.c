@@ -85,6 +85,12 @@ double ora_psi(double n, int kind)
 /* Threads an OpenMP loop of the oracle uses. */
 int ora_threads(void) { return omp_get_max_threads(); }
 
+/* Set the number of threads of the oracle's loops (for timing it on a given core count). */
+void ora_set_threads(int n)
+{
+    if (n > 0) omp_set_num_threads(n);
+}
+
 /* Exposed constants so that tests can check the tables themselves. */
 void ora_tables(int* xi_out, double* w_out, double* W_out)
 {
