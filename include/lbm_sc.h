@@ -126,7 +126,9 @@ int lbm_sc_create(const lbm_sc_config* cfg, lbm_sc** out);
 
 /* Enqueue nsteps (>= 0) time steps of Eq. (lbm) on the handle's stream: fused pull streaming,
  * density and psi, Shan-Chen force, Guo equilibrium velocity, BGK collision with the Guo term.
- * Returns after enqueueing (asynchronous); LBM_SC_EDEVICE if a launch fails. */
+ * Runs of graph_steps steps (lbm_sc_launch) are replayed from a hipGraph the handle captures on
+ * first use (plain launches while the caller is capturing the stream). Returns after enqueueing
+ * (asynchronous); LBM_SC_EDEVICE if a launch fails. */
 int lbm_sc_step(lbm_sc* h, int64_t nsteps);
 
 /* Wait until all work enqueued on the handle's stream has finished. */
@@ -165,6 +167,9 @@ typedef struct {
     int32_t prefetch;   /* 1: issue the next plane's loads before the collision of the current one */
     int32_t waves;      /* wave64s per workgroup: 4 or 8 */
     int32_t tile_x;     /* tile width: 64 or 32; 0 for full-row tiles */
+    int32_t graph_steps;/* lbm_sc_step replays a hipGraph of this many launches (even, <= 4096;
+                           0: plain launches; default 64; plain launches inside a caller's
+                           stream capture) */
 } lbm_sc_launch;
 
 /* Set / read the launch shape. The shape changes only the schedule: every node's arithmetic and

@@ -59,7 +59,7 @@ class LbmScInfo(ctypes.Structure):
 
 class LbmScLaunch(ctypes.Structure):
     _fields_ = [("rows", _i32), ("z_chunk", _i32), ("xcd_remap", _i32), ("prefetch", _i32),
-                ("waves", _i32), ("tile_x", _i32)]
+                ("waves", _i32), ("tile_x", _i32), ("graph_steps", _i32)]
 
     def to_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -218,8 +218,9 @@ def lbm_sc_set_populations(h, f):
     _check(load().lbm_sc_set_populations(h, f.ctypes.data_as(ctypes.POINTER(_f64)), f.size))
 
 
-def lbm_sc_set_launch(h, rows, z_chunk, xcd_remap=1, prefetch=0, waves=4, tile_x=64):
-    l = LbmScLaunch(rows, z_chunk, xcd_remap, prefetch, waves, tile_x)
+def lbm_sc_set_launch(h, rows, z_chunk, xcd_remap=1, prefetch=0, waves=4, tile_x=64,
+                      graph_steps=64):
+    l = LbmScLaunch(rows, z_chunk, xcd_remap, prefetch, waves, tile_x, graph_steps)
     _check(load().lbm_sc_set_launch(h, ctypes.byref(l)))
 
 
@@ -273,8 +274,9 @@ class Box:
     def set(self, f):
         lbm_sc_set_populations(self.h, f)
 
-    def set_launch(self, rows, z_chunk, xcd_remap=1, prefetch=0, waves=4, tile_x=64):
-        lbm_sc_set_launch(self.h, rows, z_chunk, xcd_remap, prefetch, waves, tile_x)
+    def set_launch(self, rows, z_chunk, xcd_remap=1, prefetch=0, waves=4, tile_x=64,
+                   graph_steps=64):
+        lbm_sc_set_launch(self.h, rows, z_chunk, xcd_remap, prefetch, waves, tile_x, graph_steps)
 
     def launch(self):
         return lbm_sc_get_launch(self.h)

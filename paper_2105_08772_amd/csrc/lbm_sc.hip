@@ -194,6 +194,10 @@ struct lbm_sc {
     double mass0 = 0.0;
     double G = 0.0, Gc = 0.0;
     int64_t device_bytes = 0;
+    int graph_steps = 64;              // steps per captured chunk (even; 0: no graph)
+    hipGraphExec_t graph = nullptr;    // graph_len launches captured from buffer graph_cur
+    int graph_len = 0;
+    int graph_cur = 0;
 };
 
 namespace {
@@ -233,10 +237,18 @@ int validate(const lbm_sc_config* c)
     return LBM_SC_OK;
 }
 
+void drop_box_graph(lbm_sc* h)
+{
+    if (h->graph) (void)hipGraphExecDestroy(h->graph);
+    h->graph = nullptr;
+    h->graph_len = 0;
+}
+
 void release(lbm_sc* h)
 {
     if (!h) return;
     if (h->stream) (void)hipStreamSynchronize(h->stream);
+    drop_box_graph(h);
     void* bufs[] = {h->pop[0], h->pop[1], h->d_n, h->d_psi, h->d_u, h->d_uprev,
                     h->d_parts, h->d_small, h->d_prof};
     for (void* p : bufs)
@@ -607,13 +619,54 @@ int lbm_sc_step(lbm_sc* h, int64_t nsteps)
 {
     if (!h) return fail(LBM_SC_EINVAL, "handle is NULL");
     if (nsteps < 0) return fail(LBM_SC_EINVAL, "nsteps must be >= 0");
-    for (int64_t s = 0; s < nsteps; ++s) {
+    auto single = [&]() -> hipError_t {
         hipError_t e = lbm::launch_step(h->fp32, h->math64, h->box, h->shape, h->pop[h->cur],
                                         h->pop[1 - h->cur], h->stream);
-        if (e != hipSuccess) return fail_hip("launch_step", e);
-        h->cur = 1 - h->cur;
-        ++h->step;
+        if (e == hipSuccess) h->cur = 1 - h->cur;
+        return e;
+    };
+    const int K = h->graph_steps;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    HIP_TRY(hipStreamIsCapturing(h->stream, &cs));
+    // inside a caller's capture the launches are recorded into the caller's graph instead
+    const bool use_graph = K > 0 && nsteps >= K && cs == hipStreamCaptureStatusNone;
+    if (use_graph && (!h->graph || h->graph_len != K)) {
+        // K (even) launches alternating the two buffers, starting from the current one
+        drop_box_graph(h);
+        hipGraph_t graph = nullptr;
+        HIP_TRY(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+        const int c = h->cur;
+        hipError_t le = hipSuccess;
+        for (int k = 0; k < K && le == hipSuccess; ++k)
+            le = lbm::launch_step(h->fp32, h->math64, h->box, h->shape, h->pop[(c + k) & 1],
+                                  h->pop[(c + k + 1) & 1], h->stream);
+        hipError_t ce = hipStreamEndCapture(h->stream, &graph);
+        if (le != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return fail_hip("launch_step during capture", le);
+        }
+        if (ce != hipSuccess) return fail_hip("hipStreamEndCapture", ce);
+        hipError_t ie = hipGraphInstantiate(&h->graph, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ie != hipSuccess) {
+            h->graph = nullptr;
+            return fail_hip("hipGraphInstantiate", ie);
+        }
+        h->graph_len = K;
+        h->graph_cur = c;
     }
+    int64_t done = 0;
+    while (done < nsteps) {
+        if (use_graph && h->graph && h->cur == h->graph_cur && nsteps - done >= h->graph_len) {
+            HIP_TRY(hipGraphLaunch(h->graph, h->stream));
+            done += h->graph_len;          // even: the current buffer is unchanged
+        } else {
+            hipError_t e = single();
+            if (e != hipSuccess) return fail_hip("launch_step", e);
+            ++done;
+        }
+    }
+    h->step += nsteps;
     return LBM_SC_OK;
 }
 
@@ -707,6 +760,10 @@ int lbm_sc_set_launch(lbm_sc* h, const lbm_sc_launch* l)
                                    "thread or tile_x 64)");
     if (s.tile_x == 0 && s.rows == 8 && (!h->fp32 || h->math64))
         return fail(LBM_SC_EINVAL, "full-row tiles with 8 nodes per thread need FP32 arithmetic");
+    if (l->graph_steps < 0 || l->graph_steps % 2 || l->graph_steps > 4096)
+        return fail(LBM_SC_EINVAL, "graph_steps must be even, in [0, 4096]");
+    drop_box_graph(h);
+    h->graph_steps = l->graph_steps;
     h->shape.rows = l->rows;
     h->shape.waves = l->waves;
     h->shape.tile_x = l->tile_x;
@@ -725,6 +782,7 @@ int lbm_sc_get_launch(lbm_sc* h, lbm_sc_launch* out)
     out->prefetch = h->shape.prefetch;
     out->waves = h->shape.waves;
     out->tile_x = h->shape.tile_x;
+    out->graph_steps = h->graph_steps;
     return LBM_SC_OK;
 }
 

@@ -142,7 +142,7 @@ def test_launch_shapes_are_bitwise_identical(prec):
             b.set(f)
             b.set_launch(rows, zc, remap, pf, waves, tx)
             assert b.launch() == dict(rows=rows, z_chunk=min(zc, 33), xcd_remap=remap, prefetch=pf,
-                                      waves=waves, tile_x=tx)
+                                      waves=waves, tile_x=tx, graph_steps=64)
             b.step(3)
             outs.append(b.get())
     for o in outs[1:]:
@@ -161,6 +161,67 @@ def test_launch_shapes_are_bitwise_identical(prec):
     with make_box((700, 3, 2), prec=prec, rho_ref=rho_ref) as b:
         with pytest.raises(lbm.LbmScError):
             b.set_launch(4, 2, 1, 0, 8, 0)
+
+
+def test_graph_replay_equals_plain_launches():
+    """lbm_sc_step replays captured chunks of graph_steps launches: bitwise the same as plain
+    launches for step counts below, at and above the chunk, after an odd number of steps (the
+    chunk was captured from the other buffer), after a change of launch shape and after
+    set_populations; odd or too long chunks are rejected."""
+    say("graph replay vs plain launches")
+    dims = (37, 29, 11)
+    rho_ref = 1.5
+    f = fp32_representable(inputs.random_populations(dims, 21, W * 1.5, amp=0.3), rho_ref)
+    runs = {}
+    for K in (0, 2, 6):
+        with make_box(dims, prec=lbm.LBM_SC_FP32_SHIFTED, rho_ref=rho_ref) as b:
+            lc = b.launch()
+            b.set(f)
+            b.set_launch(lc["rows"], lc["z_chunk"], lc["xcd_remap"], lc["prefetch"], lc["waves"],
+                         lc["tile_x"], K)
+            out = []
+            for n in (1, 6, 7, 13, 2):
+                b.step(n)
+                out.append(b.get())
+            b.set_launch(1, 5, 0, 1, 4, 64, K)     # new shape: the chunk is captured again
+            b.step(9)
+            out.append(b.get())
+            b.set(f)                                # same buffers, new state
+            b.step(8)
+            out.append(b.get())
+            for bad in (3, -2, 4098):
+                with pytest.raises(lbm.LbmScError):
+                    b.set_launch(2, 4, 1, 0, 8, 64, bad)
+        runs[K] = out
+    for K in (2, 6):
+        for a, c in zip(runs[K], runs[0]):
+            assert np.array_equal(a, c)
+
+
+def test_steps_recorded_into_a_caller_graph():
+    """lbm_sc_step inside a caller's stream capture records plain launches into the caller's
+    graph; replaying it (several times, with eager work and synchronisation between the
+    replays) matches a box stepped eagerly from the same state after every replay."""
+    import torch
+    say("steps inside a caller's graph capture")
+    s = torch.cuda.Stream()
+    dims = (24, 20, 16)
+    rho_ref = 1.5
+    f = fp32_representable(inputs.random_populations(dims, 31, W * 1.5, amp=0.3), rho_ref)
+    cfg = lbm.config(*dims, psi=0, geom=lbm.LBM_SC_FROM_HOST, prec=lbm.LBM_SC_FP32_SHIFTED,
+                     g_over_gc=1.3, rho_ref=rho_ref, stream=s.cuda_stream)
+    with lbm.Box(cfg) as b, lbm.Box(cfg) as ref:
+        b.set(f)
+        ref.set(f)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            b.step(4)
+        for _ in range(3):
+            g.replay()
+            torch.cuda.synchronize()
+            ref.step(4)
+            assert np.array_equal(b.get(), ref.get())
 
 
 @pytest.mark.parametrize("dims", SHAPES + [(100, 37, 9), (129, 5, 4)])
