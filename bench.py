@@ -117,6 +117,8 @@ def run_batched(args, torch, lbm, stream, steps, log):
         if done % 2048 == 0:
             for b in boxes:
                 b.observables(profile=False, raise_unstable=False)
+            if done % 8192 == 0:
+                log(f"# batched: {done} of {steps} steps, {time.perf_counter() - t0:.1f} s")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     # kernel time of one group step (graph replays, no observations)
@@ -441,7 +443,8 @@ PREC_NAMES = {"fp32": "FP32-shifted", "fp32m64": "FP32-shifted (FP64 arithmetic)
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=4096)
+    ap.add_argument("--steps", type=int, default=50000,
+                    help="timed steps of the 256^3 droplet (default: the configuration's 50000)")
     ap.add_argument("--warmup", type=int, default=128)
     ap.add_argument("--size", type=int, default=256)
     ap.add_argument("--radius", type=float, default=60.0)
@@ -469,9 +472,9 @@ def main():
     ap.add_argument("--served-rate", type=float, default=1.2, help="request arrival rate (1/s)")
     ap.add_argument("--tolman", action="store_true",
                     help="run the scaled droplet/bubble sweep and the Tolman analysis")
-    ap.add_argument("--batched-steps", type=int, default=2048,
+    ap.add_argument("--batched-steps", type=int, default=20000,
                     help="steps of the batched 64-box workload measured after the main timing "
-                         "(0 = skip; 20000 = the full batched configuration)")
+                         "(0 = skip; default: the configuration's 20000)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1",
@@ -565,6 +568,8 @@ def main():
         done += n
         if done % args.observe_every == 0:
             last, _ = box.observables(profile=False)
+            if done % (8 * args.observe_every) == 0:
+                print(f"# {done} of {K} steps", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     wall = t1 - t0
