@@ -195,7 +195,8 @@ typedef struct lbm_sc_group lbm_sc_group;
 
 typedef struct {
     int32_t rows;        /* tile rows per wave (supported tile shapes as for lbm_sc_launch) */
-    int32_t z_chunk;     /* planes per work item, >= 1 (clamped to each box's nz) */
+    int32_t z_chunk;     /* planes per work item, >= 1 (clamped to each box's nz); 0: each box is
+                            cut into z chunks of about equal work, items_per_cu items per CU */
     int32_t xcd_remap;   /* non-persistent launch: hand neighbouring items to the same XCD */
     int32_t prefetch;    /* issue the next plane's loads before the current collision */
     int32_t persistent;  /* 1: fixed grid of `workers` workgroups drawing items from 8 per-XCD
@@ -204,7 +205,7 @@ typedef struct {
     int32_t graph_steps; /* steps captured per hipGraph and replayed (even, 0 = no graph) */
     int32_t waves;       /* wave64s per workgroup: 4 or 8 */
     int32_t tile_x;      /* tile width: 64 or 32; 0 for full-row tiles (FP32 boxes for rows 8) */
-    int32_t reserved;    /* must be 0 */
+    int32_t items_per_cu;/* z_chunk 0: work items per CU in total (0 = 8, at most 4096) */
 } lbm_sc_group_launch;
 
 /* Create an empty group that enqueues on `stream` (a hipStream_t, required: the boxes of the

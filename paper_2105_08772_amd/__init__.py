@@ -68,10 +68,10 @@ class LbmScLaunch(ctypes.Structure):
 class LbmScGroupLaunch(ctypes.Structure):
     _fields_ = [("rows", _i32), ("z_chunk", _i32), ("xcd_remap", _i32), ("prefetch", _i32),
                 ("persistent", _i32), ("workers", _i32), ("graph_steps", _i32), ("waves", _i32),
-                ("tile_x", _i32), ("reserved", _i32)]
+                ("tile_x", _i32), ("items_per_cu", _i32)]
 
     def to_dict(self):
-        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 class LbmScError(RuntimeError):

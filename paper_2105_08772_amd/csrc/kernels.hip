@@ -10,11 +10,11 @@
 //   pull the 19 populations -> density n and momentum j -> psi(n) -> Shan-Chen force F from the
 //   psi of the 18 neighbours (Eq. SCForce) -> u_eq = (j + F/2)/n -> BGK relaxation to the
 //   second-order equilibrium plus the Guo term -> store. psi at the neighbours is needed at the
-//   same time level, so each workgroup owns an x-y tile (64 or 32 nodes wide), marches up a chunk of
-//   z-planes, pulls the densities of its tile plus a one-node x-y halo into an LDS ring of four
-//   psi planes, and collides plane q once the psi of plane q + 1 is in LDS. Only the xy halo
-//   and the two end planes of each chunk are pulled twice; the repeated reads are meant to hit
-//   L2 because neighbouring tiles run together on the same XCD.
+//   same time level, so each workgroup owns an x-y tile (64 or 32 nodes wide, or whole rows),
+//   marches up a chunk of z-planes, pulls the densities of its tile plus a one-node halo into an
+//   LDS ring of four psi planes, and collides plane q once the psi of plane q + 1 is in LDS. Only
+//   the halo and the two end planes of each chunk are pulled twice; the repeated reads are meant
+//   to hit L2 because neighbouring tiles run together on the same XCD.
 #include <type_traits>
 
 #include "kernels.hpp"

@@ -838,7 +838,7 @@ lbm::StepShape group_shape(const lbm_sc_group_launch& L)
     lbm::StepShape s;
     s.rows = L.rows;
     s.waves = L.waves;
-    s.z_chunk = L.z_chunk;
+    s.z_chunk = L.z_chunk > 0 ? L.z_chunk : 1;   // 0: per-box chunks (in the work list)
     s.xcd_remap = L.xcd_remap;
     s.prefetch = L.prefetch;
     s.tile_x = L.tile_x;
@@ -856,6 +856,21 @@ int group_rebuild(lbm_sc_group* g)
     g->bytes_per_step = 0;
     std::vector<double> work;   // nodes per item, box-major
     const lbm::StepShape shape = group_shape(L);
+    // z_chunk 0: each box is cut into z chunks of about the same work, items_per_cu items per CU
+    // in total, so that small boxes march their whole height (no chunk ends pulled twice) and
+    // large ones are split for balance
+    double item_work = 0.0;
+    if (L.z_chunk == 0) {
+        double total = 0.0;
+        for (lbm_sc* h : g->boxes) total += (double)h->box.n;
+        int cus = 0, dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            cus <= 0)
+            cus = 256;
+        const int per_cu = L.items_per_cu > 0 ? L.items_per_cu : 8;
+        item_work = total / ((double)per_cu * cus);
+    }
     for (lbm_sc* h : g->boxes) {
         int bx, by;
         tile_dims(shape, h->box, bx, by);
@@ -868,7 +883,14 @@ int group_rebuild(lbm_sc_group* g)
         d.by = shape.tile_x == 0 ? by : 0;
         d.tiles_x = (h->box.nx + bx - 1) / bx;
         d.tiles_y = (h->box.ny + by - 1) / by;
-        d.zc = L.z_chunk < h->box.nz ? L.z_chunk : h->box.nz;
+        if (L.z_chunk == 0) {
+            const double tiles = (double)d.tiles_x * d.tiles_y;
+            long chunks = item_work > 0.0 ? std::lround((double)h->box.n / item_work / tiles) : 1;
+            chunks = std::max(1L, std::min(chunks, (long)h->box.nz));
+            d.zc = (int)((h->box.nz + chunks - 1) / chunks);
+        } else {
+            d.zc = L.z_chunk < h->box.nz ? L.z_chunk : h->box.nz;
+        }
         const unsigned nch = (unsigned)((h->box.nz + d.zc - 1) / d.zc);
         d.item_begin = g->nitems;
         d.items = (unsigned)d.tiles_x * (unsigned)d.tiles_y * nch;
@@ -930,14 +952,15 @@ hipError_t group_launch(lbm_sc_group* g, int parity)
 
 int check_group_launch(const lbm_sc_group_launch* l)
 {
-    if (l->z_chunk < 1) return fail(LBM_SC_EINVAL, "z_chunk must be >= 1");
+    if (l->z_chunk < 0) return fail(LBM_SC_EINVAL, "z_chunk must be >= 0 (0: per-box chunks)");
+    if (l->items_per_cu < 0 || l->items_per_cu > 4096)
+        return fail(LBM_SC_EINVAL, "items_per_cu must be in [0, 4096]");
     if ((l->xcd_remap | l->prefetch | l->persistent) & ~1) return fail(LBM_SC_EINVAL, "flags must be 0 or 1");
     if (!lbm::shape_supported(group_shape(*l))) return fail(LBM_SC_EINVAL, SHAPE_MSG);
     if (l->workers < 0 || l->workers % 8 || l->workers > 65536)
         return fail(LBM_SC_EINVAL, "workers must be a multiple of 8 in [0, 65536]");
     if (l->graph_steps < 0 || l->graph_steps % 2 || l->graph_steps > 4096)
         return fail(LBM_SC_EINVAL, "graph_steps must be even, in [0, 4096]");
-    if (l->reserved != 0) return fail(LBM_SC_EINVAL, "reserved must be 0");
     return LBM_SC_OK;
 }
 
@@ -953,7 +976,7 @@ int lbm_sc_group_create(void* stream, lbm_sc_group** out)
     lbm_sc_group* g = new (std::nothrow) lbm_sc_group();
     if (!g) return fail(LBM_SC_ENOMEM, "host allocation failed");
     g->stream = (hipStream_t)stream;
-    g->launch = {2, 32, 1, 1, 0, 0, 64, 4, 64, 0};
+    g->launch = {2, 32, 1, 1, 0, 0, 64, 4, 64, 0};   // rows 2, z chunk 32, 4 waves, 64-wide
     hipError_t e = hipMalloc((void**)&g->d_queue, sizeof(lbm::QueueState));
     if (e != hipSuccess) {
         delete g;

@@ -20,11 +20,15 @@ SHAPES = [dict(waves=4, rows=r, prefetch=pf, tile_x=64) for r in (1, 2, 4) for p
 
 
 def group_candidates():
+    """Every compiled shape with z chunks of 8..64 planes or per-box chunks (z_chunk 0) of
+    4, 8 or 16 items per CU, one workgroup per item or persistent workers."""
     out = []
-    for shape, zc in itertools.product(SHAPES, (8, 16, 32, 64)):
-        out.append(dict(shape, z_chunk=zc, xcd_remap=1, persistent=0, workers=0))
+    chunks = [dict(z_chunk=zc, items_per_cu=0) for zc in (8, 16, 32, 64)]
+    chunks += [dict(z_chunk=0, items_per_cu=k) for k in (4, 8, 16)]
+    for shape, ch in itertools.product(SHAPES, chunks):
+        out.append(dict(shape, **ch, xcd_remap=1, persistent=0, workers=0))
         for workers in (256, 512):
-            out.append(dict(shape, z_chunk=zc, xcd_remap=1, persistent=1, workers=workers))
+            out.append(dict(shape, **ch, xcd_remap=1, persistent=1, workers=workers))
     return out
 
 

@@ -58,6 +58,10 @@ LAUNCHES = [
          waves=8, tile_x=0),
     dict(rows=4, z_chunk=16, xcd_remap=1, prefetch=0, persistent=1, workers=16, graph_steps=0,
          waves=8, tile_x=0),
+    dict(rows=4, z_chunk=0, items_per_cu=1, xcd_remap=1, prefetch=0, persistent=0, workers=0,
+         graph_steps=4, waves=8, tile_x=0),
+    dict(rows=2, z_chunk=0, items_per_cu=0, xcd_remap=1, prefetch=1, persistent=1, workers=24,
+         graph_steps=2, waves=4, tile_x=64),
 ]
 
 
@@ -159,6 +163,10 @@ def test_group_rejects_mixed_precision_and_foreign_streams():
             assert e.value.code == lbm.LBM_SC_EINVAL
         with pytest.raises(lbm.LbmScError):
             g.set_launch(workers=12)
+        with pytest.raises(lbm.LbmScError):
+            g.set_launch(z_chunk=-1)
+        with pytest.raises(lbm.LbmScError):
+            g.set_launch(z_chunk=0, items_per_cu=-1)
         with pytest.raises(lbm.LbmScError):
             g.set_launch(waves=8, prefetch=1)
         with pytest.raises(lbm.LbmScError):
