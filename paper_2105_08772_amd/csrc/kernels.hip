@@ -186,9 +186,10 @@ __device__ __forceinline__ void moments(const T (&f)[Q], double& dn, C& jx, C& j
 // it is stored as computed. In single precision round-to-nearest is biased wherever many nodes
 // hold the same value - the bulk of each phase - and the bias adds up coherently once the state
 // is quasi-static (measured: mass drift growing by about 3e-10 per step at 256^3). The value is
-// therefore rounded after adding a dither uniform in [-1/2, 1/2) ulp, drawn from a hash of the
-// node's stored index (MurmurHash3's 32-bit finaliser): the stored value is then unbiased, the
-// result stays deterministic and does not depend on the launch shape or on grouping.
+// therefore rounded after adding a dither in [-1/2, 1/2) ulp taken from the node's stored index
+// by a multiplicative (golden-ratio, Weyl) sequence, whose values over consecutive nodes are
+// spread evenly: the stored value is unbiased over a region, the result stays deterministic and
+// does not depend on the launch shape or on grouping.
 template <typename T>
 __device__ __forceinline__ T round_rest(double v, unsigned key)
 {
@@ -197,14 +198,8 @@ __device__ __forceinline__ T round_rest(double v, unsigned key)
     } else {
         const float fv = (float)v;
         const float ulp = __uint_as_float(__float_as_uint(fv) & 0x7F800000u) * 0x1p-23f;
-        unsigned h = key * 0x9E3779B1u;
-        h ^= h >> 16;
-        h *= 0x85EBCA6Bu;
-        h ^= h >> 13;
-        h *= 0xC2B2AE35u;
-        h ^= h >> 16;
-        const double u = (double)(h >> 8) * 0x1p-24 - 0.5;
-        return (float)(v + u * (double)ulp);
+        const float u = (float)(key * 0x9E3779B9u) * 0x1p-32f - 0.5f;
+        return (float)(v + (double)(u * ulp));
     }
 }
 
