@@ -443,6 +443,34 @@ def cpu_baseline(args, nodes_gpu):
             "one_core_sample": f"1 step of a {Ls}^3 droplet on 1 thread ({dt1:.1f} s)"}
 
 
+def plain_method_full_run(torch, lbm):
+    """The plain-method configuration run in full on both sides: a 32^3 FP64 droplet (exp psi,
+    G/G_c = 1.3, R = 8, tanh width 2, noise 1e-6 seed 1), 2000 steps, by the oracle on all host
+    threads and by the library on the GPU (from the same initial state), with the largest
+    difference of the final populations."""
+    import numpy as np
+    from oracle import core
+    cfg = lbm.config(32, psi=lbm.LBM_SC_PSI_EXP, geom=lbm.LBM_SC_DROPLET, prec=lbm.LBM_SC_FP64,
+                     g_over_gc=1.3, radius=8.0, width=2.0, noise_amp=1e-6, seed=1)
+    with lbm.Box(cfg) as b:
+        G = b.info()["G"]
+        f0 = b.get()
+        b.step(64)                       # capture the step chunk outside the timing
+        b.set(f0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.step(2000)
+        b.sync()
+        gpu_s = time.perf_counter() - t0
+        f_gpu = b.get()
+    t0 = time.perf_counter()
+    f_cpu = core.run(f0, G, 1.0, core.PSI_EXP, 2000)
+    cpu_s = time.perf_counter() - t0
+    return {"oracle_s": round(cpu_s, 3), "gpu_fp64_s": round(gpu_s, 4),
+            "oracle_threads": core.threads(),
+            "max_rel_diff": float(np.abs(f_gpu - f_cpu).max() / np.abs(f_cpu).max())}
+
+
 PREC_NAMES = {"fp32": "FP32-shifted", "fp32m64": "FP32-shifted (FP64 arithmetic)",
               "fp64": "FP64"}
 
@@ -642,6 +670,7 @@ def main():
     if not args.no_cpu:
         print("# timing the oracle on the host cores", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args, nodes)
+        out["cpu_baseline"]["plain_method_32cubed"] = plain_method_full_run(torch, lbm)
     print(json.dumps(out), flush=True)
 
 
