@@ -68,9 +68,11 @@ class Record:
 
 
 class GpuBackend:
-    """Boxes and one group on a dedicated stream of the current GPU."""
+    """Boxes and one group on a dedicated stream of the current GPU. With single=True the active
+    boxes are stepped one by one through the plain single-box path (lbm_sc_step) instead of one
+    multi-box launch: the baseline the batched server is compared with."""
 
-    def __init__(self, prec=None, stream=None, tau=1.0, width=2.0, noise_amp=1e-6):
+    def __init__(self, prec=None, stream=None, tau=1.0, width=2.0, noise_amp=1e-6, single=False):
         import torch
 
         from . import (LBM_SC_BUBBLE, LBM_SC_DROPLET, LBM_SC_FP32_SHIFTED, Box, Group, LbmScError,
@@ -85,6 +87,8 @@ class GpuBackend:
         self.tau, self.width, self.noise_amp = tau, width, noise_amp
         self.group = Group(self.stream.cuda_stream)
         self.launch = None
+        self.single = single
+        self.active = []
 
     def config(self, r):
         return self._config(r.L, psi=r.psi, geom=self._bubble if r.bubble else self._droplet,
@@ -106,6 +110,9 @@ class GpuBackend:
     FALLBACK = dict(rows=2, waves=4, tile_x=64, prefetch=0)
 
     def set_active(self, boxes):
+        if self.single:
+            self.active = list(boxes)
+            return
         try:
             self.group.set(boxes)
         except self._error:
@@ -121,7 +128,11 @@ class GpuBackend:
         self.group.set_launch(**kw)
 
     def step(self, n):
-        self.group.step(n)
+        if self.single:
+            for b in self.active:
+                b.step(n)
+        else:
+            self.group.step(n)
 
     def observe(self, box):
         obs, _ = box.observables(profile=False, raise_unstable=False)
@@ -147,7 +158,7 @@ def percentile(values, q):
 class Server:
     def __init__(self, backend, budget_bytes, chunk=512, observe_every=2048, max_steps=200000,
                  dp_tol=1e-5, du_tol=1e-9, mass_tol=None, clock=None, sleep=None, log=None,
-                 keep_final=False, com_tol=1e-3):
+                 keep_final=False, com_tol=1e-3, max_active=None):
         if observe_every % chunk:
             raise ValueError("observe_every must be a multiple of chunk")
         if observe_every % 2:
@@ -163,6 +174,7 @@ class Server:
         self.log = log
         self.keep_final = keep_final
         self.com_tol = com_tol
+        self.max_active_allowed = max_active   # None: limited by memory only
         self.queue = []            # requests not yet admitted, arrival order
         self.active = {}           # rid -> (request, box, record, last_obs)
         self.records = {}
@@ -219,6 +231,8 @@ class Server:
                 continue
             if self.used + need > self.budget:
                 break                  # first in, first admitted: wait for memory
+            if self.max_active_allowed is not None and len(self.active) >= self.max_active_allowed:
+                break
             self.queue.pop(0)
             box = self.b.create(req)
             rec.bytes = need

@@ -104,6 +104,19 @@ def test_admission_by_memory_in_arrival_order():
         assert r.time_to_equilibrium == r.finished - r.arrival
 
 
+def test_one_at_a_time_serving():
+    """max_active = 1 (the single-box baseline): requests run strictly one after another in
+    arrival order even when memory would admit more, and each waits for the previous one."""
+    reqs = [req(k, 10, 0.1 * k) for k in range(4)]
+    srv, be, _ = make(reqs, budget=10 ** 6, max_active=1)
+    recs = sorted(srv.run(), key=lambda r: r.rid)
+    assert srv.max_active == 1
+    assert all(r.status == "converged" for r in recs)
+    for a, b in zip(recs, recs[1:]):
+        assert b.admitted >= a.finished
+    assert recs[-1].time_to_equilibrium > recs[0].time_to_equilibrium
+
+
 def test_unstable_request_is_retired_and_others_continue():
     reqs = [req(k, 10, 0.0) for k in range(3)]
     srv, be, _ = make(reqs, budget=10 ** 6, fail_at={1: 4096})
