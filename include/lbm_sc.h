@@ -117,7 +117,9 @@ typedef struct {
 
 /* Create a box. Validates cfg (LBM_SC_EINVAL on any out-of-range field: sizes < 1, tau <= 0.5,
  * unknown enums, radius/width <= 0 for DROPLET/BUBBLE/SLAB, g_over_gc <= 1 when the densities must
- * come from lbm_sc_coexistence), allocates two population buffers and the observation scratch on
+ * come from lbm_sc_coexistence; also for boxes of more than 2^31 nodes or whose z-planes are so
+ * large that the 19 populations of one plane exceed 4 GiB, i.e. beyond about 56 M (FP32 storage)
+ * or 28 M (FP64) nodes per plane), allocates two population buffers and the observation scratch on
  * the current HIP device (LBM_SC_ENOMEM), and builds the initial state on the device: the tanh
  * profile plus noise, psi, the force of Eq. (SCForce), and f = f_eq(n, u = -F/(2n)) so that the
  * physical velocity (sum xi f + F/2)/n is zero. Returns after the work is enqueued and *out set.

@@ -1,7 +1,9 @@
 // Device kernels of the Shan-Chen D3Q19 lattice Boltzmann library (gfx950).
 //
-// Population storage: SoA, population i of node (x, y, z) at i * stride + (z * ny + y) * px + x,
-// with the row pitch px >= nx a whole number of 128-byte lines (the padding is never read).
+// Population storage: plane-major, population i of node (x, y, z) at element
+// (z * 19 + i) * pp + y * px + x, with the row pitch px >= nx a whole number of 128-byte lines
+// (the padding is never read) and the population pitch pp >= px * ny. Each z-plane is one
+// contiguous block of 19 population planes, so a box is not limited by 32-bit offsets.
 // The stored arrays hold the post-collision populations of the previous step, f*_i(x, t - 1), so
 // the pre-collision state of time t is the pull f_i(x, t) = f*_i(x - xi_i, t - 1) (Eq. lbm of
 // arXiv:2105.08772 read as pull streaming). FP32 storage keeps g_i = f_i - w_i rho_ref.
@@ -30,10 +32,11 @@ __device__ __forceinline__ int wrapi(int v, int L)
     return r < 0 ? r + L : r;
 }
 
-// Stored (pitched) index of node (x, y, z) within one population array.
-__device__ __forceinline__ unsigned stored_index(const BoxDesc& b, int x, int y, int z)
+// Stored element index of population i of node (x, y, z).
+__device__ __forceinline__ unsigned long long pop_index(const BoxDesc& b, int i, int x, int y, int z)
 {
-    return ((unsigned)z * (unsigned)b.ny + (unsigned)y) * b.px + (unsigned)x;
+    return (unsigned long long)((unsigned)z * (unsigned)Q + (unsigned)i) * b.pp +
+           (unsigned)y * b.px + (unsigned)x;
 }
 
 template <typename T, int PSI>
@@ -62,12 +65,12 @@ __device__ __forceinline__ unsigned xcd_remap(unsigned b, unsigned nb)
     return xcd * per + (xcd < rem ? xcd : rem) + k;
 }
 
-// Population arrays are addressed through two buffer resources: populations 0..9 and 10..18, each
-// group under 4 GiB (checked by the host). A load or store of population i is one buffer
-// instruction with the node's byte offset in a vector register and the population's byte offset
-// (a multiple of the array stride) as the scalar offset; out-of-range offsets read 0 and write
-// nothing instead of faulting.
-constexpr int SPLIT = 10;
+// Populations are addressed plane by plane: the 19 population planes of one z-plane (19 pp
+// elements, under 4 GiB, checked by the host) form one buffer resource whose base is the plane's
+// first byte. A load or store of population i is one buffer instruction with the node's in-plane
+// byte offset in a vector register and i * pp * sizeof(T) as the scalar offset; out-of-range
+// offsets read 0 and write nothing instead of faulting. Rebasing a resource per plane is scalar
+// work, so the box size is limited by memory, not by 32-bit offsets.
 constexpr unsigned RSRC_FLAGS = 0x00020000u;  // raw buffer, 32-bit dword format (gfx9 family)
 // Population stores carry the non-temporal cache policy: a stored population is read again
 // only in the next step, after the whole box has streamed through the caches.
@@ -76,52 +79,63 @@ constexpr int STORE_CPOL_NT = 2;
 // reused across workgroups in L2, not within one CU (measured: about 1.5 % faster than default).
 constexpr int LOAD_CPOL_SC0 = 1;
 
+typedef __amdgpu_buffer_rsrc_t Rsrc;
+
 struct PopBuf {
-    __amdgpu_buffer_rsrc_t lo, hi;
-    unsigned pop_bytes;  // stride * sizeof(T)
+    char* base;
+    unsigned pop_bytes;  // pp * sizeof(T): bytes between the population planes of one z-plane
 };
 
 template <typename T>
-__device__ __forceinline__ PopBuf make_popbuf(const T* p, unsigned long long stride)
+__device__ __forceinline__ PopBuf make_popbuf(const T* p, unsigned pp)
 {
-    PopBuf b;
-    const unsigned long long pb = stride * sizeof(T);
-    char* base = reinterpret_cast<char*>(const_cast<T*>(p));
-    const unsigned long long lo_bytes = pb * SPLIT, hi_bytes = pb * (Q - SPLIT);
-    b.lo = __builtin_amdgcn_make_buffer_rsrc(base, (short)0, (int)(unsigned)lo_bytes, (int)RSRC_FLAGS);
-    b.hi = __builtin_amdgcn_make_buffer_rsrc(base + lo_bytes, (short)0, (int)(unsigned)hi_bytes,
-                                             (int)RSRC_FLAGS);
-    b.pop_bytes = (unsigned)pb;
-    return b;
+    return PopBuf{reinterpret_cast<char*>(const_cast<T*>(p)), pp * (unsigned)sizeof(T)};
+}
+
+// Resource of z-plane z (0 <= z < nz).
+__device__ __forceinline__ Rsrc plane_rsrc(const PopBuf& b, int z)
+{
+    const unsigned plane_bytes = (unsigned)Q * b.pop_bytes;
+    return __builtin_amdgcn_make_buffer_rsrc(b.base + (unsigned long long)(unsigned)z * plane_bytes,
+                                             (short)0, (int)plane_bytes, (int)RSRC_FLAGS);
+}
+
+// Resources of the planes p - 1, p, p + 1 (periodic in z), indexed by dz + 1.
+struct Planes {
+    Rsrc m, c, p;
+};
+
+template <int D>
+__device__ __forceinline__ Rsrc plane_at(const Planes& z)
+{
+    if constexpr (D == 0) return z.m;
+    else if constexpr (D == 1) return z.c;
+    else return z.p;
 }
 
 template <typename T, int I>
-__device__ __forceinline__ T bload(const PopBuf& b, unsigned voff)
+__device__ __forceinline__ T bload(Rsrc r, unsigned pop_bytes, unsigned voff)
 {
-    constexpr int J = I < SPLIT ? I : I - SPLIT;
-    const __amdgpu_buffer_rsrc_t r = I < SPLIT ? b.lo : b.hi;
     if constexpr (sizeof(T) == 4) {
         return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff,
-                                                                              (int)(J * b.pop_bytes), LOAD_CPOL_SC0));
+                                                                              (int)(I * pop_bytes), LOAD_CPOL_SC0));
     } else {
         typedef int v2i __attribute__((ext_vector_type(2)));
-        const v2i v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)(J * b.pop_bytes), LOAD_CPOL_SC0);
+        const v2i v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)(I * pop_bytes), LOAD_CPOL_SC0);
         return __builtin_bit_cast(double, v);
     }
 }
 
 template <typename T, int I>
-__device__ __forceinline__ void bstore(const PopBuf& b, unsigned voff, T v)
+__device__ __forceinline__ void bstore(Rsrc r, unsigned pop_bytes, unsigned voff, T v)
 {
-    constexpr int J = I < SPLIT ? I : I - SPLIT;
-    const __amdgpu_buffer_rsrc_t r = I < SPLIT ? b.lo : b.hi;
     if constexpr (sizeof(T) == 4) {
         __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(int, v), r, (int)voff,
-                                              (int)(J * b.pop_bytes), STORE_CPOL_NT);
+                                              (int)(I * pop_bytes), STORE_CPOL_NT);
     } else {
         typedef int v2i __attribute__((ext_vector_type(2)));
         __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2i, v), r, (int)voff,
-                                              (int)(J * b.pop_bytes), STORE_CPOL_NT);
+                                              (int)(I * pop_bytes), STORE_CPOL_NT);
     }
 }
 
@@ -141,19 +155,17 @@ struct StepArgs {
     int by;     // full-row tiles: interior rows per tile
 };
 
-// Pull the 19 pre-collision populations of one node and reduce them to (sum g, j). Byte offsets
-// zo/yo/xo[d] address the plane/row/column at coordinate + d - 1; the source of velocity xi is the
-// node - xi.
-// Load the 19 pre-collision populations of one node. Byte offsets zo/yo/xo[d] address the
-// plane/row/column at coordinate + d - 1; the source of velocity xi is the node - xi.
+// Load the 19 pre-collision populations of one node. The plane resources zr and the in-plane byte
+// offsets yo/xo[d] address the plane/row/column at coordinate + d - 1; the source of velocity xi
+// is the node - xi.
 template <typename T>
-__device__ __forceinline__ void load_node(const PopBuf& src, const unsigned (&zo)[3],
+__device__ __forceinline__ void load_node(const Planes& zr, unsigned pop_bytes,
                                           const unsigned (&yo)[3], const unsigned (&xo)[3],
                                           T (&f)[Q])
 {
     static_for<0, Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
-        f[i] = bload<T, i>(src, zo[1 - CZ[i]] + yo[1 - CY[i]] + xo[1 - CX[i]]);
+        f[i] = bload<T, i>(plane_at<1 - CZ[i]>(zr), pop_bytes, yo[1 - CY[i]] + xo[1 - CX[i]]);
     });
 }
 
@@ -204,13 +216,15 @@ __device__ __forceinline__ T round_rest(double v, unsigned key)
 }
 
 // Collide one node in the arithmetic type C and store its 19 post-collision (shifted) populations,
-// rounded to the storage type T, at byte offset off.
+// rounded to the storage type T, at in-plane byte offset off of plane resource dst; key is the
+// node's plane-by-plane index (z * ny + y) * px + x, which seeds the rest population's dither.
 // dn64 = sum g (n - rho_ref, exact), j = sum xi g = sum xi f. Rest population: mass-exact
 // closure g*_0 = dn - sum_{i>0} g*_i (the stored values summed in double precision), equal to
 // the BGK value in exact arithmetic; the node's stored mass then changes only by the final
 // rounding of g*_0.
 template <typename T, typename C, bool TAU1>
-__device__ __forceinline__ void collide_store(const PopBuf& dst, unsigned off, C rho_ref,
+__device__ __forceinline__ void collide_store(Rsrc dst, unsigned pop_bytes, unsigned off,
+                                              unsigned key, C rho_ref,
                                               double dn64, C jx, C jy, C jz, C Fx, C Fy, C Fz,
                                               C inv_tau, C guo_pref, const T* fin)
 {
@@ -246,11 +260,11 @@ __device__ __forceinline__ void collide_store(const PopBuf& dst, unsigned off, C
         }
         // the closure sums the values as stored (rounded to T)
         const T sp = (T)gp, sm = (T)gm;
-        bstore<T, i>(dst, off, sp);
-        bstore<T, i + 1>(dst, off, sm);
+        bstore<T, i>(dst, pop_bytes, off, sp);
+        bstore<T, i + 1>(dst, pop_bytes, off, sm);
         sum += (double)sp + (double)sm;
     });
-    bstore<T, 0>(dst, off, round_rest<T>(dn64 - sum, off / (unsigned)sizeof(T)));
+    bstore<T, 0>(dst, pop_bytes, off, round_rest<T>(dn64 - sum, key));
 }
 
 // Tile of a workgroup of WAVES wave64s: BXT (64 or 32) nodes wide; each wave covers R rows of
@@ -306,8 +320,9 @@ __device__ __forceinline__ void step_tile(const BoxDesc& bd, const T* __restrict
 
     const int nx = bd.nx, ny = bd.ny, nz = bd.nz;
     const unsigned pxy = bd.pxy;
-    const PopBuf sbuf = make_popbuf(src, bd.stride);
-    const PopBuf dbuf = make_popbuf(dst, bd.stride);
+    const PopBuf sbuf = make_popbuf(src, bd.pp);
+    const PopBuf dbuf = make_popbuf(dst, bd.pp);
+    const unsigned popb = sbuf.pop_bytes;
     const C rho_ref = (C)bd.rho_ref;
     const C G = (C)bd.G;
     const C inv_tau = (C)(1.0 / bd.tau);
@@ -369,10 +384,9 @@ __device__ __forceinline__ void step_tile(const BoxDesc& bd, const T* __restrict
     const unsigned hyo[3] = {(unsigned)wrapi(hyg - 1, ny) * rowb, (unsigned)hyg * rowb,
                              (unsigned)wrapi(hyg + 1, ny) * rowb};
 
-    auto plane_offsets = [&](int p, unsigned (&zo)[3]) {
-        zo[0] = (unsigned)wrapi(p - 1, nz) * pxy * E;
-        zo[1] = (unsigned)wrapi(p, nz) * pxy * E;
-        zo[2] = (unsigned)wrapi(p + 1, nz) * pxy * E;
+    auto planes = [&](int p) {
+        return Planes{plane_rsrc(sbuf, wrapi(p - 1, nz)), plane_rsrc(sbuf, wrapi(p, nz)),
+                      plane_rsrc(sbuf, wrapi(p + 1, nz))};
     };
 
     // Raw populations of the plane being reduced. With PF the loads of plane k + 1 are issued
@@ -386,27 +400,23 @@ __device__ __forceinline__ void step_tile(const BoxDesc& bd, const T* __restrict
         for (int i = 0; i < Q; ++i) fr[r][i] = T(0);
     double pdn[R];
     C pjx[R], pjy[R], pjz[R];
-    unsigned pzo[3] = {0u, 0u, 0u};
     const int nplanes = (z1 - z0) + 2;
     if constexpr (PF) {
-        unsigned zo[3];
-        plane_offsets(z0 - 1, zo);
+        const Planes zr = planes(z0 - 1);
 #pragma unroll
         for (int r = 0; r < R; ++r)
-            if (ld[r]) load_node(sbuf, zo, yo[r], xo, fr[r]);
-        if (has_halo) load_node(sbuf, zo, hyo, hxo, fh);
+            if (ld[r]) load_node(zr, popb, yo[r], xo, fr[r]);
+        if (has_halo) load_node(zr, popb, hyo, hxo, fh);
     }
     for (int k = 0; k < nplanes; ++k) {
         const int p = z0 - 1 + k;
-        unsigned zo[3];
-        plane_offsets(p, zo);
         C(*slot)[LX] = ring[k & 3];
         double cdn[R];
         C cjx[R], cjy[R], cjz[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             if constexpr (!PF) {
-                if (ld[r]) load_node(sbuf, zo, yo[r], xo, fr[r]);
+                if (ld[r]) load_node(planes(p), popb, yo[r], xo, fr[r]);
             }
             moments(fr[r], cdn[r], cjx[r], cjy[r], cjz[r]);
             slot[(wv * R + r) * SUB + ls + 1][lc + 1] = psi_of<C, PSI>(rho_ref + (C)cdn[r]);
@@ -414,18 +424,17 @@ __device__ __forceinline__ void step_tile(const BoxDesc& bd, const T* __restrict
         if (has_halo) {
             double hdn;
             C hjx, hjy, hjz;
-            if constexpr (!PF) load_node(sbuf, zo, hyo, hxo, fh);
+            if constexpr (!PF) load_node(planes(p), popb, hyo, hxo, fh);
             moments(fh, hdn, hjx, hjy, hjz);
             slot[hy][hx] = psi_of<C, PSI>(rho_ref + (C)hdn);
         }
         if constexpr (PF) {
             if (k + 1 < nplanes) {
-                unsigned zn[3];
-                plane_offsets(p + 1, zn);
+                const Planes zn = planes(p + 1);
 #pragma unroll
                 for (int r = 0; r < R; ++r)
-                    if (ld[r]) load_node(sbuf, zn, yo[r], xo, fr[r]);
-                if (has_halo) load_node(sbuf, zn, hyo, hxo, fh);
+                    if (ld[r]) load_node(zn, popb, yo[r], xo, fr[r]);
+                if (has_halo) load_node(zn, popb, hyo, hxo, fh);
             }
         }
         __syncthreads();
@@ -434,7 +443,9 @@ __device__ __forceinline__ void step_tile(const BoxDesc& bd, const T* __restrict
             const C(*pm)[LX] = ring[(k - 2) & 3];
             const C(*pc)[LX] = ring[(k - 1) & 3];
             const C(*pp)[LX] = ring[k & 3];
-            const unsigned qoff = (unsigned)(p - 1) * pxy * E;
+            // plane q = p - 1 lies in [z0, z1): its resource needs no wrap
+            const Rsrc qr = plane_rsrc(dbuf, p - 1);
+            const unsigned qkey = (unsigned)(p - 1) * pxy;
             const int lx = lc + 1;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
@@ -459,19 +470,19 @@ __device__ __forceinline__ void step_tile(const BoxDesc& bd, const T* __restrict
                 const C Sz = w1 * (p_c - m_c) +
                              w2 * ((p_e - m_e) + (p_w - m_w) + (p_n - m_n) + (p_s - m_s));
                 const C gp = -G * psi0;
-                const unsigned off = qoff + yo[r][1] + xso;
+                const unsigned off = yo[r][1] + xso;
+                const unsigned key = qkey + off / E;
                 if constexpr (TAU1) {
-                    collide_store<T, C, true>(dbuf, off, rho_ref, pdn[r], pjx[r], pjy[r], pjz[r],
-                                              gp * Sx, gp * Sy, gp * Sz, inv_tau, guo_pref,
+                    collide_store<T, C, true>(qr, popb, off, key, rho_ref, pdn[r], pjx[r], pjy[r],
+                                              pjz[r], gp * Sx, gp * Sy, gp * Sz, inv_tau, guo_pref,
                                               (const T*)nullptr);
                 } else {
+                    // the pre-collision populations of plane q, pulled again
                     T fin[Q];
-                    static_for<0, Q>([&](auto I) {
-                        constexpr int i = decltype(I)::value;
-                        fin[i] = bload<T, i>(sbuf, pzo[1 - CZ[i]] + yo[r][1 - CY[i]] + xo[1 - CX[i]]);
-                    });
-                    collide_store<T, C, false>(dbuf, off, rho_ref, pdn[r], pjx[r], pjy[r], pjz[r],
-                                               gp * Sx, gp * Sy, gp * Sz, inv_tau, guo_pref, fin);
+                    load_node(planes(p - 1), popb, yo[r], xo, fin);
+                    collide_store<T, C, false>(qr, popb, off, key, rho_ref, pdn[r], pjx[r], pjy[r],
+                                               pjz[r], gp * Sx, gp * Sy, gp * Sz, inv_tau, guo_pref,
+                                               fin);
                 }
             }
         }
@@ -482,9 +493,6 @@ __device__ __forceinline__ void step_tile(const BoxDesc& bd, const T* __restrict
             pjy[r] = cjy[r];
             pjz[r] = cjz[r];
         }
-        pzo[0] = zo[0];
-        pzo[1] = zo[1];
-        pzo[2] = zo[2];
     }
 }
 
@@ -504,8 +512,9 @@ __device__ __forceinline__ void step_rows(const BoxDesc& bd, const T* __restrict
     const int nx = bd.nx, ny = bd.ny, nz = bd.nz;
     const int px = (int)bd.px;
     const unsigned pxy = bd.pxy;
-    const PopBuf sbuf = make_popbuf(src, bd.stride);
-    const PopBuf dbuf = make_popbuf(dst, bd.stride);
+    const PopBuf sbuf = make_popbuf(src, bd.pp);
+    const PopBuf dbuf = make_popbuf(dst, bd.pp);
+    const unsigned popb = sbuf.pop_bytes;
     const C rho_ref = (C)bd.rho_ref;
     const C G = (C)bd.G;
     const C inv_tau = (C)(1.0 / bd.tau);
@@ -543,20 +552,17 @@ __device__ __forceinline__ void step_rows(const BoxDesc& bd, const T* __restrict
         yo[1] = (unsigned)y * rowb;
         yo[2] = (unsigned)(y == ny - 1 ? 0 : y + 1) * rowb;
     };
-    auto plane_offsets = [&](int p, unsigned (&zo)[3]) {
-        zo[0] = (unsigned)wrapi(p - 1, nz) * pxy * E;
-        zo[1] = (unsigned)wrapi(p, nz) * pxy * E;
-        zo[2] = (unsigned)wrapi(p + 1, nz) * pxy * E;
+    auto planes = [&](int p) {
+        return Planes{plane_rsrc(sbuf, wrapi(p - 1, nz)), plane_rsrc(sbuf, wrapi(p, nz)),
+                      plane_rsrc(sbuf, wrapi(p + 1, nz))};
     };
 
     double pdn[NPT];
     C pjx[NPT], pjy[NPT], pjz[NPT];
-    unsigned pzo[3] = {0u, 0u, 0u};
     const int nplanes = (z1 - z0) + 2;
     for (int kp = 0; kp < nplanes; ++kp) {
         const int p = z0 - 1 + kp;
-        unsigned zo[3];
-        plane_offsets(p, zo);
+        const Planes zr = planes(p);
         C* slot = ring[kp & 3];
         double cdn[NPT];
         C cjx[NPT], cjy[NPT], cjz[NPT];
@@ -568,7 +574,7 @@ __device__ __forceinline__ void step_rows(const BoxDesc& bd, const T* __restrict
                 unsigned xo[3], yo[3];
                 node_offsets(k, xo, yo);
                 T f[Q];
-                load_node(sbuf, zo, yo, xo, f);
+                load_node(zr, popb, yo, xo, f);
                 moments(f, cdn[k], cjx[k], cjy[k], cjz[k]);
                 slot[lyk[k] * nx + xk[k]] = psi_of<C, PSI>(rho_ref + (C)cdn[k]);
             }
@@ -579,7 +585,9 @@ __device__ __forceinline__ void step_rows(const BoxDesc& bd, const T* __restrict
             const C* pm = ring[(kp - 2) & 3];
             const C* pc = ring[(kp - 1) & 3];
             const C* pp = ring[kp & 3];
-            const unsigned qoff = (unsigned)(p - 1) * pxy * E;
+            // plane q = p - 1 lies in [z0, z1): its resource needs no wrap
+            const Rsrc qr = plane_rsrc(dbuf, p - 1);
+            const unsigned qkey = (unsigned)(p - 1) * pxy;
 #pragma unroll
             for (int k = 0; k < NPT; ++k) {
                 if (!stk[k]) continue;
@@ -606,19 +614,19 @@ __device__ __forceinline__ void step_rows(const BoxDesc& bd, const T* __restrict
                 const C gp = -G * psi0;
                 unsigned xo[3], yo[3];
                 node_offsets(k, xo, yo);
-                const unsigned off = qoff + yo[1] + (unsigned)xk[k] * E;
+                const unsigned off = yo[1] + (unsigned)xk[k] * E;
+                const unsigned key = qkey + off / E;
                 if constexpr (TAU1) {
-                    collide_store<T, C, true>(dbuf, off, rho_ref, pdn[k], pjx[k], pjy[k], pjz[k],
-                                              gp * Sx, gp * Sy, gp * Sz, inv_tau, guo_pref,
+                    collide_store<T, C, true>(qr, popb, off, key, rho_ref, pdn[k], pjx[k], pjy[k],
+                                              pjz[k], gp * Sx, gp * Sy, gp * Sz, inv_tau, guo_pref,
                                               (const T*)nullptr);
                 } else {
+                    // the pre-collision populations of plane q, pulled again
                     T fin[Q];
-                    static_for<0, Q>([&](auto I) {
-                        constexpr int i = decltype(I)::value;
-                        fin[i] = bload<T, i>(sbuf, pzo[1 - CZ[i]] + yo[1 - CY[i]] + xo[1 - CX[i]]);
-                    });
-                    collide_store<T, C, false>(dbuf, off, rho_ref, pdn[k], pjx[k], pjy[k], pjz[k],
-                                               gp * Sx, gp * Sy, gp * Sz, inv_tau, guo_pref, fin);
+                    load_node(planes(p - 1), popb, yo, xo, fin);
+                    collide_store<T, C, false>(qr, popb, off, key, rho_ref, pdn[k], pjx[k], pjy[k],
+                                               pjz[k], gp * Sx, gp * Sy, gp * Sz, inv_tau, guo_pref,
+                                               fin);
                 }
             }
         }
@@ -629,9 +637,6 @@ __device__ __forceinline__ void step_rows(const BoxDesc& bd, const T* __restrict
             pjy[k] = cjy[k];
             pjz[k] = cjz[k];
         }
-        pzo[0] = zo[0];
-        pzo[1] = zo[1];
-        pzo[2] = zo[2];
     }
 }
 
@@ -891,9 +896,8 @@ __global__ void k_init_pops(BoxDesc b, const double* __restrict__ dn,
         const double c = CX[i] * ux + CY[i] * uy + CZ[i] * uz;
         const double f = weight(i) * n * (1.0 + 3.0 * c + 4.5 * c * c - 1.5 * uu);
         // f_i(x, 0) is the pull of the stored slot at x - xi_i
-        const unsigned s = stored_index(b, wrapi(x - CX[i], b.nx), wrapi(y - CY[i], b.ny),
-                                        wrapi(z - CZ[i], b.nz));
-        dst[(unsigned long long)i * b.stride + s] = (T)(f - weight(i) * b.rho_ref);
+        dst[pop_index(b, i, wrapi(x - CX[i], b.nx), wrapi(y - CY[i], b.ny), wrapi(z - CZ[i], b.nz))] =
+            (T)(f - weight(i) * b.rho_ref);
     }
 }
 
@@ -902,7 +906,7 @@ __global__ void k_init_pops(BoxDesc b, const double* __restrict__ dn,
 // ------------------------------------------------------------------------------------------
 
 template <typename T>
-__global__ void k_get(BoxDesc b, int cx, int cy, int cz, double w, const T* __restrict__ src,
+__global__ void k_get(BoxDesc b, int i, int cx, int cy, int cz, double w, const T* __restrict__ src,
                       double* __restrict__ out)
 {
     const unsigned k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -910,12 +914,12 @@ __global__ void k_get(BoxDesc b, int cx, int cy, int cz, double w, const T* __re
     const int x = (int)(k % (unsigned)b.nx);
     const int y = (int)((k / (unsigned)b.nx) % (unsigned)b.ny);
     const int z = (int)(k / b.nxy);
-    const unsigned s = stored_index(b, wrapi(x - cx, b.nx), wrapi(y - cy, b.ny), wrapi(z - cz, b.nz));
-    out[k] = (double)src[s] + w * b.rho_ref;
+    out[k] = (double)src[pop_index(b, i, wrapi(x - cx, b.nx), wrapi(y - cy, b.ny), wrapi(z - cz, b.nz))] +
+             w * b.rho_ref;
 }
 
 template <typename T>
-__global__ void k_set(BoxDesc b, int cx, int cy, int cz, double w, const double* __restrict__ in,
+__global__ void k_set(BoxDesc b, int i, int cx, int cy, int cz, double w, const double* __restrict__ in,
                       T* __restrict__ dst)
 {
     const unsigned k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -927,7 +931,7 @@ __global__ void k_set(BoxDesc b, int cx, int cy, int cz, double w, const double*
     const unsigned s = ((unsigned)wrapi(z + cz, b.nz) * (unsigned)b.ny +
                         (unsigned)wrapi(y + cy, b.ny)) * (unsigned)b.nx +
                        (unsigned)wrapi(x + cx, b.nx);
-    dst[stored_index(b, x, y, z)] = (T)(in[s] - w * b.rho_ref);
+    dst[pop_index(b, i, x, y, z)] = (T)(in[s] - w * b.rho_ref);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -946,9 +950,9 @@ __global__ void k_obs_pull(BoxDesc b, const T* __restrict__ src, double* __restr
         double s = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            const unsigned o = stored_index(b, wrapi(x - CX[i], b.nx), wrapi(y - CY[i], b.ny),
-                                            wrapi(z - CZ[i], b.nz));
-            const double f = (double)src[(unsigned long long)i * b.stride + o] + weight(i) * b.rho_ref;
+            const unsigned long long o = pop_index(b, i, wrapi(x - CX[i], b.nx), wrapi(y - CY[i], b.ny),
+                                                   wrapi(z - CZ[i], b.nz));
+            const double f = (double)src[o] + weight(i) * b.rho_ref;
             s += f;
             jx += CX[i] * f;
             jy += CY[i] * f;
@@ -1298,11 +1302,11 @@ hipError_t launch_get(bool fp32, const BoxDesc& b, int i, const void* src, doubl
 {
     const unsigned g = blocks_for(b.n, 256);
     if (fp32)
-        hipLaunchKernelGGL(k_get<float>, dim3(g), dim3(256), 0, st, b, CX[i], CY[i], CZ[i],
-                           weight(i), (const float*)src + (unsigned long long)i * b.stride, out);
+        hipLaunchKernelGGL(k_get<float>, dim3(g), dim3(256), 0, st, b, i, CX[i], CY[i], CZ[i],
+                           weight(i), (const float*)src, out);
     else
-        hipLaunchKernelGGL(k_get<double>, dim3(g), dim3(256), 0, st, b, CX[i], CY[i], CZ[i],
-                           weight(i), (const double*)src + (unsigned long long)i * b.stride, out);
+        hipLaunchKernelGGL(k_get<double>, dim3(g), dim3(256), 0, st, b, i, CX[i], CY[i], CZ[i],
+                           weight(i), (const double*)src, out);
     return hipGetLastError();
 }
 
@@ -1311,11 +1315,11 @@ hipError_t launch_set(bool fp32, const BoxDesc& b, int i, const double* in, void
 {
     const unsigned g = blocks_for(b.n, 256);
     if (fp32)
-        hipLaunchKernelGGL(k_set<float>, dim3(g), dim3(256), 0, st, b, CX[i], CY[i], CZ[i],
-                           weight(i), in, (float*)dst + (unsigned long long)i * b.stride);
+        hipLaunchKernelGGL(k_set<float>, dim3(g), dim3(256), 0, st, b, i, CX[i], CY[i], CZ[i],
+                           weight(i), in, (float*)dst);
     else
-        hipLaunchKernelGGL(k_set<double>, dim3(g), dim3(256), 0, st, b, CX[i], CY[i], CZ[i],
-                           weight(i), in, (double*)dst + (unsigned long long)i * b.stride);
+        hipLaunchKernelGGL(k_set<double>, dim3(g), dim3(256), 0, st, b, i, CX[i], CY[i], CZ[i],
+                           weight(i), in, (double*)dst);
     return hipGetLastError();
 }
 

@@ -13,8 +13,10 @@ struct BoxDesc {
     unsigned n;              // nx * ny * nz (nodes; canonical index (z * ny + y) * nx + x)
     unsigned px;             // row pitch of the stored populations (elements, >= nx, whole
                              // 128-byte lines)
-    unsigned pxy;            // plane pitch px * ny; stored index (z * ny + y) * px + x
-    unsigned long long stride;  // elements between consecutive population arrays (>= pxy * nz)
+    unsigned pxy;            // px * ny
+    unsigned pp;             // population pitch: elements between the population planes of one
+                             // z-plane (>= pxy); population i of node (x, y, z) is stored at
+                             // element (z * 19 + i) * pp + y * px + x
     int psi;                 // 0: exp(-1/n), 1: 1 - exp(-n)
     double G;
     double tau;

@@ -207,7 +207,7 @@ int validate(const lbm_sc_config* c)
     if (!c) return fail(LBM_SC_EINVAL, "cfg is NULL");
     if (c->nx < 1 || c->ny < 1 || c->nz < 1) return fail(LBM_SC_EINVAL, "box sizes must be >= 1");
     const double nodes = (double)c->nx * c->ny * c->nz;
-    if (nodes > 4.0e9) return fail(LBM_SC_EINVAL, "box has more than 4e9 nodes");
+    if (nodes > 2147483648.0) return fail(LBM_SC_EINVAL, "box has more than 2^31 nodes");
     if (c->psi != LBM_SC_PSI_EXP && c->psi != LBM_SC_PSI_ONEMINUS)
         return fail(LBM_SC_EINVAL, "psi must be LBM_SC_PSI_EXP or LBM_SC_PSI_ONEMINUS");
     if (c->geom < LBM_SC_DROPLET || c->geom > LBM_SC_FROM_HOST)
@@ -434,13 +434,13 @@ unsigned row_pitch(int nx, size_t elem)
     return ((unsigned)nx + per_line - 1) / per_line * per_line;
 }
 
-// Elements between population arrays: rounded up to 64 elements and, for arrays of 4 MiB or more,
-// padded by 256 KiB + 256 B so that the 19 arrays do not start at the same offset modulo a large
-// power of two (measured: about 2-3 % more bandwidth at 256^3).
-unsigned long long population_stride(unsigned long long n, size_t elem)
+// Population pitch: elements between the 19 population planes of one z-plane, the plane px * ny
+// rounded up to 64 elements and, for planes of 64 KiB or more, padded by 256 B so that the 19
+// planes do not start at the same offset modulo a large power of two.
+unsigned long long population_pitch(unsigned long long pxy, size_t elem)
 {
-    unsigned long long s = (n + 63ull) / 64ull * 64ull;
-    if (s * elem >= (4ull << 20)) s += (262144ull + 256ull) / elem;
+    unsigned long long s = (pxy + 63ull) / 64ull * 64ull;
+    if (s * elem >= (64ull << 10)) s += 256ull / elem;
     return s;
 }
 
@@ -453,10 +453,10 @@ Sizes sizes_for(const lbm_sc_config* c)
 {
     const size_t elem = c->prec == LBM_SC_FP64 ? 8 : 4;
     const unsigned long long n = (unsigned long long)c->nx * c->ny * c->nz;
-    const unsigned long long stored = (unsigned long long)row_pitch(c->nx, elem) * c->ny * c->nz;
+    const unsigned long long pxy = (unsigned long long)row_pitch(c->nx, elem) * c->ny;
     const int Lmax = std::max(c->nx, std::max(c->ny, c->nz));
     Sizes s;
-    s.popbytes = (size_t)19 * population_stride(stored, elem) * elem;
+    s.popbytes = (size_t)c->nz * 19 * population_pitch(pxy, elem) * elem;
     s.n8 = (size_t)n * 8;
     s.n24 = 3 * (size_t)n * 8;
     s.parts = (size_t)lbm::OBS_BLOCKS * lbm::OBS_PARTS * 8;
@@ -539,19 +539,20 @@ int lbm_sc_create(const lbm_sc_config* cfg, lbm_sc** out)
     b.n = b.nxy * (unsigned)cfg->nz;
     b.px = row_pitch(cfg->nx, h->elem);
     const unsigned long long pxy = (unsigned long long)b.px * (unsigned)cfg->ny;
-    b.pxy = (unsigned)pxy;   // < 2^32 whenever the 4 GiB check below passes
-    b.stride = population_stride(pxy * (unsigned)cfg->nz, h->elem);
+    b.pxy = (unsigned)pxy;   // < 2^32 whenever the plane check below passes
+    const unsigned long long pp = population_pitch(pxy, h->elem);
+    b.pp = (unsigned)pp;
+    // the step kernel addresses the 19 populations of one z-plane through one buffer resource of
+    // at most 4 GiB
+    if ((unsigned long long)19 * pp * h->elem >= (1ull << 32)) {
+        release(h);
+        return fail(LBM_SC_EINVAL, "box too large: the 19 populations of one z-plane must fit in 4 GiB");
+    }
     b.psi = cfg->psi;
     b.G = h->G;
     b.tau = cfg->tau;
     b.rho_ref = rho_ref;
     default_shape(h);
-    // the step kernel addresses populations 0..9 and 10..18 through two buffer resources of at
-    // most 4 GiB each
-    if ((unsigned long long)10 * b.stride * h->elem >= (1ull << 32)) {
-        release(h);
-        return fail(LBM_SC_EINVAL, "box too large: 10 population arrays must fit in 4 GiB");
-    }
 
     if (cfg->stream) {
         h->stream = (hipStream_t)cfg->stream;

@@ -504,6 +504,44 @@ def test_full_size_bench_workload_sampled():
     assert abs(o1["mass"] - o0["mass"]) <= 1e-7 * o0["mass"]
 
 
+@pytest.mark.parametrize("L,prec,tol", [(400, lbm.LBM_SC_FP64, TOL64),
+                                         (480, lbm.LBM_SC_FP32_SHIFTED, 1e-6)])
+def test_box_beyond_32bit_offsets_sampled(L, prec, tol):
+    """Boxes whose population buffers span well over 4 GiB (9.7 GB at 400^3 FP64, 8.4 GB at
+    480^3 FP32): one step of a noisy droplet checked on sampled nodes - many of them in the top
+    planes, at the largest offsets - against the oracle's single-node collision, then mass
+    conservation over 8 steps."""
+    say(f"{L}^3 prec {prec}: sampled one-step parity beyond 32-bit offsets")
+    cfg = lbm.config(L, L, L, psi=0, geom=lbm.LBM_SC_DROPLET, prec=prec, g_over_gc=1.3,
+                     radius=0.3 * L, width=2.0, noise_amp=1e-6, seed=11)
+    rng = np.random.default_rng(L)
+    with lbm.Box(cfg) as b:
+        G = b.info()["G"]
+        f0 = b.get()
+        b.step(1)
+        f1 = b.get()
+        o0 = b.observables(profile=False)[0]
+        b.step(8)
+        o1 = b.observables(profile=False)[0]
+    pts = [tuple(int(v) for v in rng.integers(0, L, 3)) for _ in range(40)]
+    pts += [(int(rng.integers(0, L)), int(rng.integers(0, L)), L - 1 - int(rng.integers(0, 4)))
+            for _ in range(40)]
+    pts += [(L - 1, L - 1, L - 1), (0, L - 1, L - 1), (L - 1, 0, 0), (L // 2 + int(0.3 * L), L // 2, L // 2)]
+    scale = np.abs(f0).max()
+    worst = 0.0
+    for (x, y, z) in pts:
+        fs = core.collide_at(f0, G, 1.0, 0, x, y, z)
+        for i in range(19):
+            d = ((x + XI[i, 0]) % L, (y + XI[i, 1]) % L, (z + XI[i, 2]) % L)
+            worst = max(worst, abs(f1[i, d[2], d[1], d[0]] - fs[i]) / scale)
+    del f0, f1
+    say("worst sampled error / max|f| =", worst)
+    assert worst <= tol
+    assert o1["finite"]
+    mtol = 1e-12 if prec == lbm.LBM_SC_FP64 else 1e-7
+    assert abs(o1["mass"] - o0["mass"]) <= mtol * o0["mass"]
+
+
 def test_full_size_batched_workload_sampled():
     """The 64-box batched workload (seed 2105, L ~ U{48..160}, FP32-shifted) in one group with
     the full-row tiles the benchmark's tuner picks (4 nodes per thread, z chunks of 8, hipGraph

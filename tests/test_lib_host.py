@@ -69,6 +69,18 @@ def test_invalid_configurations_are_rejected_before_any_device_work(bad):
     assert lbm.lbm_sc_last_error()
 
 
+@pytest.mark.parametrize("dims,prec", [((1291, 1291, 1291), lbm.LBM_SC_FP32_SHIFTED),
+                                       ((7600, 7600, 1), lbm.LBM_SC_FP32_SHIFTED),
+                                       ((5400, 5400, 1), lbm.LBM_SC_FP64)])
+def test_oversized_boxes_are_rejected_before_any_device_work(dims, prec):
+    # more than 2^31 nodes; a z-plane whose 19 populations exceed 4 GiB (one buffer resource)
+    cfg = lbm.config(*dims, prec=prec, radius=3.0, width=2.0)
+    with pytest.raises(lbm.LbmScError) as e:
+        lbm.lbm_sc_create(cfg)
+    assert e.value.code == lbm.LBM_SC_EINVAL
+    assert "2^31" in lbm.lbm_sc_last_error() or "4 GiB" in lbm.lbm_sc_last_error()
+
+
 def test_ctypes_structs_match_the_c_layout(tmp_path):
     """Compile a probe against include/lbm_sc.h and compare every field offset and struct size
     with the ctypes mirrors of the Python binding."""
