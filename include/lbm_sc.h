@@ -118,8 +118,8 @@ typedef struct {
 /* Create a box. Validates cfg (LBM_SC_EINVAL on any out-of-range field: sizes < 1, tau <= 0.5,
  * unknown enums, radius/width <= 0 for DROPLET/BUBBLE/SLAB, g_over_gc <= 1 when the densities must
  * come from lbm_sc_coexistence; also for boxes of more than 2^31 nodes or whose z-planes are so
- * large that the 19 populations of one plane exceed 4 GiB, i.e. beyond about 56 M (FP32 storage)
- * or 28 M (FP64) nodes per plane), allocates two population buffers and the observation scratch on
+ * large that the 19 populations of one plane exceed 4 GiB, i.e. beyond about 53 M (FP32 storage)
+ * or 26 M (FP64) nodes per plane), allocates two population buffers and the observation scratch on
  * the current HIP device (LBM_SC_ENOMEM), and builds the initial state on the device: the tanh
  * profile plus noise, psi, the force of Eq. (SCForce), and f = f_eq(n, u = -F/(2n)) so that the
  * physical velocity (sum xi f + F/2)/n is zero. Returns after the work is enqueued and *out set.
@@ -151,7 +151,9 @@ int lbm_sc_get_populations(lbm_sc* h, double* f, size_t len);
 
 /* Replace the state by the host array f (canonical layout, pre-collision populations at the
  * current time, len 19*nx*ny*nz). Shifted FP32 storage holds them rounded after subtracting w_i rho_ref.
- * Resets the step counter, mass0 and the du reference. Synchronises. */
+ * Resets the step counter (which also seeds the rounding dither of the FP32 rest population, so
+ * the same state stepped the same number of times gives the same result), mass0 and the du
+ * reference. Synchronises. Not for use inside a stream capture. */
 int lbm_sc_set_populations(lbm_sc* h, const double* f, size_t len);
 
 /* Launch shape of the fused step kernel. The workgroup is 64*waves threads (waves wave64s) and

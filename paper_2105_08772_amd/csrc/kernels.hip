@@ -151,6 +151,7 @@ __device__ __forceinline__ void static_for(F&& f)
 
 struct StepArgs {
     BoxDesc b;
+    int s;      // source buffer (0 or 1): selects the step count b.tick[s] behind the dither
     int tiles_x, tiles_y, nchunks, zc, remap;
     int by;     // full-row tiles: interior rows per tile
 };
@@ -198,10 +199,15 @@ __device__ __forceinline__ void moments(const T (&f)[Q], double& dn, C& jx, C& j
 // it is stored as computed. In single precision round-to-nearest is biased wherever many nodes
 // hold the same value - the bulk of each phase - and the bias adds up coherently once the state
 // is quasi-static (measured: mass drift growing by about 3e-10 per step at 256^3). The value is
-// therefore rounded after adding a dither in [-1/2, 1/2) ulp taken from the node's stored index
-// by a multiplicative (golden-ratio, Weyl) sequence, whose values over consecutive nodes are
-// spread evenly: the stored value is unbiased over a region, the result stays deterministic and
-// does not depend on the launch shape or on grouping.
+// therefore rounded after adding a dither in [-1/2, 1/2) ulp, u = frac((k + s) phi) - 1/2, k the
+// node's stored index and phi the golden-ratio fraction (a Weyl sequence over the nodes): over
+// the nodes of one step the dither is spread evenly, so the stored value is unbiased over a
+// region. The offset s is a hash of the box's step count, so the pattern moves to an unrelated
+// position every step: the rounding errors of a quasi-static state neither repeat (which makes
+// the mass drift linearly) nor follow the previous step's pattern (a regular shift, e.g. a second
+// Weyl sequence in time, correlates the dither with the state it produced and biases the
+// rounding; measured 10x more drift than a fixed pattern). The caller passes key = k + s. The
+// result is deterministic and depends neither on the launch shape nor on grouping.
 template <typename T>
 __device__ __forceinline__ T round_rest(double v, unsigned key)
 {
@@ -215,9 +221,22 @@ __device__ __forceinline__ T round_rest(double v, unsigned key)
     }
 }
 
+// Dither offset of step count t: the 32-bit finaliser of MurmurHash3 (A. Appleby), a bijection
+// whose outputs for consecutive inputs look independent.
+__device__ __forceinline__ unsigned dither_shift(unsigned t)
+{
+    t ^= t >> 16;
+    t *= 0x85EBCA6Bu;
+    t ^= t >> 13;
+    t *= 0xC2B2AE35u;
+    t ^= t >> 16;
+    return t;
+}
+
 // Collide one node in the arithmetic type C and store its 19 post-collision (shifted) populations,
-// rounded to the storage type T, at in-plane byte offset off of plane resource dst; key is the
-// node's plane-by-plane index (z * ny + y) * px + x, which seeds the rest population's dither.
+// rounded to the storage type T, at in-plane byte offset off of plane resource dst; key, the
+// node's plane-by-plane index (z * ny + y) * px + x plus the dither offset of the box's step,
+// sets the rest population's dither.
 // dn64 = sum g (n - rho_ref, exact), j = sum xi g = sum xi f. Rest population: mass-exact
 // closure g*_0 = dn - sum_{i>0} g*_i (the stored values summed in double precision), equal to
 // the BGK value in exact arithmetic; the node's stored mass then changes only by the final
@@ -308,6 +327,7 @@ using RingOf = typename RingSel<T, R, WAVES, BXT>::type;
 template <typename T, typename C, int PSI, bool TAU1, int R, bool PF, int WAVES, int BXT>
 __device__ __forceinline__ void step_tile(const BoxDesc& bd, const T* __restrict__ src,
                                           T* __restrict__ dst, int tix, int tiy, int z0, int z1,
+                                          const unsigned* tick_in, unsigned* tick_out,
                                           RingOf<C, R, WAVES, BXT>& rg)
 {
     constexpr int NT = 64 * WAVES;
@@ -401,11 +421,17 @@ __device__ __forceinline__ void step_tile(const BoxDesc& bd, const T* __restrict
     double pdn[R];
     C pjx[R], pjy[R], pjz[R];
     const int nplanes = (z1 - z0) + 2;
+    // the step count behind the dither: a vector load (a relaxed atomic, so that it is not
+    // turned into a scalar load, whose wait would also hold up the LDS traffic) issued behind the
+    // first plane's row loads, so that it delays none of them, and moved to a scalar register once
+    // the plane is reduced (waiting for the halo loads issued after it has covered its latency)
+    unsigned tkv = 0u, tk = 0u, seed = 0u;
     if constexpr (PF) {
         const Planes zr = planes(z0 - 1);
 #pragma unroll
         for (int r = 0; r < R; ++r)
             if (ld[r]) load_node(zr, popb, yo[r], xo, fr[r]);
+        tkv = __hip_atomic_load(tick_in, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
         if (has_halo) load_node(zr, popb, hyo, hxo, fh);
     }
     for (int k = 0; k < nplanes; ++k) {
@@ -417,6 +443,8 @@ __device__ __forceinline__ void step_tile(const BoxDesc& bd, const T* __restrict
         for (int r = 0; r < R; ++r) {
             if constexpr (!PF) {
                 if (ld[r]) load_node(planes(p), popb, yo[r], xo, fr[r]);
+                if (k == 0 && r == R - 1)
+                    tkv = __hip_atomic_load(tick_in, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
             }
             moments(fr[r], cdn[r], cjx[r], cjy[r], cjz[r]);
             slot[(wv * R + r) * SUB + ls + 1][lc + 1] = psi_of<C, PSI>(rho_ref + (C)cdn[r]);
@@ -438,6 +466,10 @@ __device__ __forceinline__ void step_tile(const BoxDesc& bd, const T* __restrict
             }
         }
         __syncthreads();
+        if (k == 0) {
+            tk = __builtin_amdgcn_readfirstlane(tkv);
+            seed = dither_shift(tk);
+        }
         if (k >= 2) {
             // collide plane q = p - 1 with psi of planes q - 1, q, q + 1
             const C(*pm)[LX] = ring[(k - 2) & 3];
@@ -445,7 +477,7 @@ __device__ __forceinline__ void step_tile(const BoxDesc& bd, const T* __restrict
             const C(*pp)[LX] = ring[k & 3];
             // plane q = p - 1 lies in [z0, z1): its resource needs no wrap
             const Rsrc qr = plane_rsrc(dbuf, p - 1);
-            const unsigned qkey = (unsigned)(p - 1) * pxy;
+            const unsigned qkey = (unsigned)(p - 1) * pxy + seed;   // scalar: plane index + offset
             const int lx = lc + 1;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
@@ -494,6 +526,7 @@ __device__ __forceinline__ void step_tile(const BoxDesc& bd, const T* __restrict
             pjz[r] = cjz[r];
         }
     }
+    if (tick_out && threadIdx.x == 0) *tick_out = tk + 1u;
 }
 
 // Full-row tiles (for boxes whose rows are short): the workgroup owns rows [y0, y0 + by) of the
@@ -505,6 +538,7 @@ __device__ __forceinline__ void step_tile(const BoxDesc& bd, const T* __restrict
 template <typename T, typename C, int PSI, bool TAU1, int NPT, int WAVES>
 __device__ __forceinline__ void step_rows(const BoxDesc& bd, const T* __restrict__ src,
                                           T* __restrict__ dst, int by, int tiy, int z0, int z1,
+                                          const unsigned* tick_in, unsigned* tick_out,
                                           RowRing<C, NPT * 64 * WAVES>& rg)
 {
     constexpr int NT = 64 * WAVES;
@@ -560,6 +594,9 @@ __device__ __forceinline__ void step_rows(const BoxDesc& bd, const T* __restrict
     double pdn[NPT];
     C pjx[NPT], pjy[NPT], pjz[NPT];
     const int nplanes = (z1 - z0) + 2;
+    // step count behind the dither, loaded as in step_tile once the first plane is reduced and
+    // moved to a scalar register after the second (whose loads cover its latency)
+    unsigned tkv = 0u, tk = 0u, seed = 0u;
     for (int kp = 0; kp < nplanes; ++kp) {
         const int p = z0 - 1 + kp;
         const Planes zr = planes(p);
@@ -579,7 +616,12 @@ __device__ __forceinline__ void step_rows(const BoxDesc& bd, const T* __restrict
                 slot[lyk[k] * nx + xk[k]] = psi_of<C, PSI>(rho_ref + (C)cdn[k]);
             }
         }
+        if (kp == 0) tkv = __hip_atomic_load(tick_in, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
         __syncthreads();
+        if (kp == 1) {
+            tk = __builtin_amdgcn_readfirstlane(tkv);
+            seed = dither_shift(tk);
+        }
         if (kp >= 2) {
             // collide plane q = p - 1 with psi of planes q - 1, q, q + 1
             const C* pm = ring[(kp - 2) & 3];
@@ -587,7 +629,7 @@ __device__ __forceinline__ void step_rows(const BoxDesc& bd, const T* __restrict
             const C* pp = ring[kp & 3];
             // plane q = p - 1 lies in [z0, z1): its resource needs no wrap
             const Rsrc qr = plane_rsrc(dbuf, p - 1);
-            const unsigned qkey = (unsigned)(p - 1) * pxy;
+            const unsigned qkey = (unsigned)(p - 1) * pxy + seed;   // scalar: plane index + offset
 #pragma unroll
             for (int k = 0; k < NPT; ++k) {
                 if (!stk[k]) continue;
@@ -638,6 +680,7 @@ __device__ __forceinline__ void step_rows(const BoxDesc& bd, const T* __restrict
             pjz[k] = cjz[k];
         }
     }
+    if (tick_out && threadIdx.x == 0) *tick_out = tk + 1u;
 }
 
 template <typename T, typename C, int PSI, bool TAU1, int R, bool PF, int WAVES, int BXT>
@@ -652,8 +695,13 @@ __global__ __launch_bounds__(64 * WAVES) void k_step(StepArgs a, const T* __rest
     const int ch = (int)(t2 / (unsigned)a.tiles_y);
     const int z0 = ch * a.zc;
     const int z1 = min(z0 + a.zc, a.b.nz);
-    if constexpr (BXT == 0) step_rows<T, C, PSI, TAU1, R, WAVES>(a.b, src, dst, a.by, tiy, z0, z1, ring);
-    else step_tile<T, C, PSI, TAU1, R, PF, WAVES, BXT>(a.b, src, dst, tix, tiy, z0, z1, ring);
+    // the dither comes from the box's step count, kept per buffer (tick[s] counts the steps up to
+    // the state in buffer s); one workgroup hands the next count to the step that reads the other
+    // buffer
+    const unsigned* tin = a.b.tick + a.s;
+    unsigned* tout = logical == 0 ? a.b.tick + (1 - a.s) : nullptr;
+    if constexpr (BXT == 0) step_rows<T, C, PSI, TAU1, R, WAVES>(a.b, src, dst, a.by, tiy, z0, z1, tin, tout, ring);
+    else step_tile<T, C, PSI, TAU1, R, PF, WAVES, BXT>(a.b, src, dst, tix, tiy, z0, z1, tin, tout, ring);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -686,22 +734,25 @@ __device__ __forceinline__ void group_item(const GroupBox* __restrict__ boxes, i
     const int s = (g.phase + parity) & 1;
     const T* src = (const T*)g.pop[s];
     T* dst = (T*)g.pop[1 - s];
+    // step count behind the dither and its successor, as in the single-box kernel
+    const unsigned* tin = g.b.tick + s;
+    unsigned* tout = local == 0 ? g.b.tick + (1 - s) : nullptr;
     const bool tau1 = g.b.tau == 1.0;
     if constexpr (BXT == 0) {
         if (g.b.psi == 0) {
-            if (tau1) step_rows<T, T, 0, true, R, WAVES>(g.b, src, dst, g.by, tiy, z0, z1, ring);
-            else step_rows<T, T, 0, false, R, WAVES>(g.b, src, dst, g.by, tiy, z0, z1, ring);
+            if (tau1) step_rows<T, T, 0, true, R, WAVES>(g.b, src, dst, g.by, tiy, z0, z1, tin, tout, ring);
+            else step_rows<T, T, 0, false, R, WAVES>(g.b, src, dst, g.by, tiy, z0, z1, tin, tout, ring);
         } else {
-            if (tau1) step_rows<T, T, 1, true, R, WAVES>(g.b, src, dst, g.by, tiy, z0, z1, ring);
-            else step_rows<T, T, 1, false, R, WAVES>(g.b, src, dst, g.by, tiy, z0, z1, ring);
+            if (tau1) step_rows<T, T, 1, true, R, WAVES>(g.b, src, dst, g.by, tiy, z0, z1, tin, tout, ring);
+            else step_rows<T, T, 1, false, R, WAVES>(g.b, src, dst, g.by, tiy, z0, z1, tin, tout, ring);
         }
     } else {
         if (g.b.psi == 0) {
-            if (tau1) step_tile<T, T, 0, true, R, PF, WAVES, BXT>(g.b, src, dst, tix, tiy, z0, z1, ring);
-            else step_tile<T, T, 0, false, R, PF, WAVES, BXT>(g.b, src, dst, tix, tiy, z0, z1, ring);
+            if (tau1) step_tile<T, T, 0, true, R, PF, WAVES, BXT>(g.b, src, dst, tix, tiy, z0, z1, tin, tout, ring);
+            else step_tile<T, T, 0, false, R, PF, WAVES, BXT>(g.b, src, dst, tix, tiy, z0, z1, tin, tout, ring);
         } else {
-            if (tau1) step_tile<T, T, 1, true, R, PF, WAVES, BXT>(g.b, src, dst, tix, tiy, z0, z1, ring);
-            else step_tile<T, T, 1, false, R, PF, WAVES, BXT>(g.b, src, dst, tix, tiy, z0, z1, ring);
+            if (tau1) step_tile<T, T, 1, true, R, PF, WAVES, BXT>(g.b, src, dst, tix, tiy, z0, z1, tin, tout, ring);
+            else step_tile<T, T, 1, false, R, PF, WAVES, BXT>(g.b, src, dst, tix, tiy, z0, z1, tin, tout, ring);
         }
     }
 }
@@ -1198,12 +1249,13 @@ __global__ __launch_bounds__(256) void k_stream_copy(const float* __restrict__ s
 // Host launchers
 // ------------------------------------------------------------------------------------------
 
-hipError_t launch_step(bool fp32, bool math64, const BoxDesc& b, const StepShape& s,
+hipError_t launch_step(bool fp32, bool math64, const BoxDesc& b, const StepShape& s, int sbuf,
                        const void* src, void* dst, hipStream_t st)
 {
-    if (!shape_supported(s)) return hipErrorInvalidValue;
+    if (!shape_supported(s) || (sbuf & ~1)) return hipErrorInvalidValue;
     StepArgs a;
     a.b = b;
+    a.s = sbuf;
     a.by = 0;
     if (s.tile_x == 0) {
         a.by = row_tile_rows(s, b.px);

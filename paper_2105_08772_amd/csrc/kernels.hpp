@@ -17,6 +17,8 @@ struct BoxDesc {
     unsigned pp;             // population pitch: elements between the population planes of one
                              // z-plane (>= pxy); population i of node (x, y, z) is stored at
                              // element (z * 19 + i) * pp + y * px + x
+    unsigned* tick;          // device: step counts that seed the FP32 rest-population dither;
+                             // tick[s] belongs to the state held in population buffer s
     int psi;                 // 0: exp(-1/n), 1: 1 - exp(-n)
     double G;
     double tau;
@@ -93,7 +95,8 @@ constexpr int OBS_BLOCKS = 512;
 
 // One step of one box. fp32: populations stored as float (shifted); math64: with fp32, the step's
 // arithmetic is done in double precision (storage and traffic unchanged).
-hipError_t launch_step(bool fp32, bool math64, const BoxDesc& b, const StepShape& s,
+// sbuf: index (0 or 1) of the source buffer, which selects the dither seed b.tick[sbuf].
+hipError_t launch_step(bool fp32, bool math64, const BoxDesc& b, const StepShape& s, int sbuf,
                        const void* src, void* dst, hipStream_t st);
 // Multi-box step. nitems work items; persistent: grid of `workers` workgroups over the queues.
 hipError_t launch_step_group(bool fp32, const StepShape& s, const GroupBox* boxes, int nbox,

@@ -26,7 +26,7 @@ TOL64 = 1e-11
 # converged 64^3 FP32 droplet, 32768 steps: measured 2.4e-8 with the dithered rest-population
 # rounding (plain round-to-nearest drifts about 1e-10 per step at the same densities, ~3e-6);
 # the bound is three times the measured value
-DRIFT_BOUND = 7.5e-8
+DRIFT_BOUND = 1e-8
 
 
 def say(*a):
@@ -421,8 +421,10 @@ def test_fp32_vs_fp64_droplet_after_2000_steps():
 def test_fp32_mass_drift_of_a_converged_droplet():
     """Once a droplet has converged its state repeats, and plain round-to-nearest of the rest
     population (which closes each node's mass) is biased the same way at every bulk node, so
-    the FP32 mass drifts linearly. The dithered rounding keeps that drift small: a 64^3 droplet
-    (R = 16) converged for 8192 steps, then 32768 more steps."""
+    the FP32 mass drifts linearly; a dither pattern fixed in time still leaves a linear drift
+    (measured 2.4e-8 here). The dither moved to an unrelated position every step leaves a random
+    walk of the rounding errors: a 64^3 droplet (R = 16) converged for 8192 steps, then 32768
+    more steps (measured 2.1e-9)."""
     say("FP32 mass drift of a converged 64^3 droplet")
     cfg = lbm.config(64, psi=0, geom=lbm.LBM_SC_DROPLET, prec=lbm.LBM_SC_FP32_SHIFTED,
                      g_over_gc=1.3, radius=16.0, width=2.0, noise_amp=1e-6, seed=5)
