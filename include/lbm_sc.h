@@ -161,11 +161,12 @@ int lbm_sc_set_populations(lbm_sc* h, const double* f, size_t len);
  * wave row covers two rows of 32 nodes), and a run of z_chunk planes along z. Supported shapes:
  * waves 4 with rows 1, 2 or 4 (rows 1 or 2 at tile_x 32) and either prefetch setting; waves 8
  * with rows 1 or 2 and prefetch 0. tile_x = 0 selects full-row tiles for boxes with short rows:
- * the workgroup (waves 8, prefetch 0) owns whole rows, `rows` (4, or 8 with FP32 arithmetic) is
- * the number of nodes each thread holds per plane, and a tile has rows*512/px - 2 rows, px being
- * nx rounded up to whole 128-byte lines (LBM_SC_EINVAL if that is below 1). */
+ * the workgroup (prefetch 0) owns whole rows, `rows` is the number of nodes each thread holds per
+ * plane (waves 8: 2, 4, or 8 with FP32 arithmetic; waves 4: 4), and a tile has
+ * rows*64*waves/px - 2 rows, px being nx rounded up to whole 128-byte lines (LBM_SC_EINVAL if
+ * that is below 1). */
 typedef struct {
-    int32_t rows;       /* tile rows per wave: 1, 2 or 4 (full-row tiles: nodes per thread, 4 or 8) */
+    int32_t rows;       /* tile rows per wave: 1, 2 or 4 (full-row tiles: nodes per thread, 2, 4, 8) */
     int32_t z_chunk;    /* planes per workgroup, >= 1 (clamped to nz) */
     int32_t xcd_remap;  /* 1: hand neighbouring tiles to the same XCD (shared L2); 0: identity */
     int32_t prefetch;   /* 1: issue the next plane's loads before the collision of the current one */

@@ -812,13 +812,16 @@ hipError_t launch_step_t(const StepArgs& a, const void* src, void* dst, hipStrea
 
 // Supported launch shapes (checked by shape_supported): 4 waves with rows 1, 2 or 4 and either
 // prefetch setting; 8 waves with rows 1 or 2 and no prefetch; tile width 32 with rows 1 or 2;
-// full-row tiles (tile width 0) with 8 waves, 4 or 8 nodes per thread and no prefetch.
+// full-row tiles (tile width 0) without prefetch, with 8 waves and 2, 4 or 8 nodes per thread, or
+// with 4 waves and 4 nodes per thread.
 template <typename T, typename C, int PSI, bool TAU1>
 hipError_t dispatch_pf(const StepShape& s, const StepArgs& a, const void* src, void* dst,
                        hipStream_t st)
 {
 #define LBM_STEP(R, PF, WV, BXT) launch_step_t<T, C, PSI, TAU1, R, PF, WV, BXT>(a, src, dst, st)
     if (s.tile_x == 0) {
+        if (s.waves == 4) return LBM_STEP(4, false, 4, 0);
+        if (s.rows == 2) return LBM_STEP(2, false, 8, 0);
         // 8 nodes per thread only with single-precision arithmetic (in double it spills)
         if constexpr (sizeof(C) == 8) return s.rows == 4 ? LBM_STEP(4, false, 8, 0) : hipErrorInvalidValue;
         else return s.rows == 4 ? LBM_STEP(4, false, 8, 0) : LBM_STEP(8, false, 8, 0);
@@ -1297,6 +1300,8 @@ hipError_t launch_group_shape(const StepShape& s, const GroupBox* boxes, int nbo
 #define LBM_GROUP(R, PF, WV, BXT) \
     launch_group_t<T, R, PF, WV, BXT>(boxes, nbox, nitems, parity, persistent, s.xcd_remap, workers, q, st)
     if (s.tile_x == 0) {
+        if (s.waves == 4) return LBM_GROUP(4, false, 4, 0);
+        if (s.rows == 2) return LBM_GROUP(2, false, 8, 0);
         if constexpr (sizeof(T) == 8) return s.rows == 4 ? LBM_GROUP(4, false, 8, 0) : hipErrorInvalidValue;
         else return s.rows == 4 ? LBM_GROUP(4, false, 8, 0) : LBM_GROUP(8, false, 8, 0);
     }

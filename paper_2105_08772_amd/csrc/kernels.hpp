@@ -39,11 +39,14 @@ struct StepShape {
 };
 
 // The compiled shapes: 4 waves with rows 1, 2 or 4 (rows 1 or 2 at tile width 32), either
-// prefetch setting; 8 waves with rows 1 or 2 and no prefetch.
+// prefetch setting; 8 waves with rows 1 or 2 and no prefetch; full-row tiles (tile width 0)
+// without prefetch, 8 waves with 2, 4 or 8 nodes per thread or 4 waves with 4.
 inline bool shape_supported(const StepShape& s)
 {
     if (s.z_chunk < 1 || (s.xcd_remap & ~1) || (s.prefetch & ~1)) return false;
-    if (s.tile_x == 0) return s.waves == 8 && s.prefetch == 0 && (s.rows == 4 || s.rows == 8);
+    if (s.tile_x == 0)
+        return s.prefetch == 0 && ((s.waves == 8 && (s.rows == 2 || s.rows == 4 || s.rows == 8)) ||
+                                   (s.waves == 4 && s.rows == 4));
     if (s.tile_x != 64 && s.tile_x != 32) return false;
     if (s.waves == 4) return s.rows == 1 || s.rows == 2 || (s.rows == 4 && s.tile_x == 64);
     if (s.waves == 8) return (s.rows == 1 || s.rows == 2) && s.prefetch == 0;

@@ -20,7 +20,7 @@ thread_local std::string g_err = "no error";
 
 const char* const SHAPE_MSG =
     "unsupported launch shape (tile_x 64: waves 4 with rows 1, 2, 4, or waves 8 with rows 1, 2 and no "
-    "prefetch; tile_x 32: rows 1, 2 (waves 8: no prefetch); tile_x 0: waves 8, rows 4 or 8, no prefetch)";
+    "prefetch; tile_x 32: rows 1, 2 (waves 8: no prefetch); tile_x 0: no prefetch, waves 8 with rows 2, 4 or 8, or waves 4 with rows 4)";
 
 int fail(int code, const std::string& msg)
 {

@@ -16,7 +16,8 @@ def _sync():
 SHAPES = [dict(waves=4, rows=r, prefetch=pf, tile_x=64) for r in (1, 2, 4) for pf in (0, 1)] + \
          [dict(waves=4, rows=r, prefetch=pf, tile_x=32) for r in (1, 2) for pf in (0, 1)] + \
          [dict(waves=8, rows=r, prefetch=0, tile_x=bx) for r in (1, 2) for bx in (64, 32)] + \
-         [dict(waves=8, rows=r, prefetch=0, tile_x=0) for r in (4, 8)]   # full-row tiles
+         [dict(waves=8, rows=r, prefetch=0, tile_x=0) for r in (2, 4, 8)] + \
+         [dict(waves=4, rows=4, prefetch=0, tile_x=0)]   # full-row tiles
 
 
 def group_candidates():

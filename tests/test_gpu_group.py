@@ -58,6 +58,10 @@ LAUNCHES = [
          waves=8, tile_x=0),
     dict(rows=4, z_chunk=16, xcd_remap=1, prefetch=0, persistent=1, workers=16, graph_steps=0,
          waves=8, tile_x=0),
+    dict(rows=2, z_chunk=5, xcd_remap=1, prefetch=0, persistent=0, workers=0, graph_steps=2,
+         waves=8, tile_x=0),
+    dict(rows=4, z_chunk=7, xcd_remap=0, prefetch=0, persistent=1, workers=24, graph_steps=4,
+         waves=4, tile_x=0),
     dict(rows=4, z_chunk=0, items_per_cu=1, xcd_remap=1, prefetch=0, persistent=0, workers=0,
          graph_steps=4, waves=8, tile_x=0),
     dict(rows=2, z_chunk=0, items_per_cu=0, xcd_remap=1, prefetch=1, persistent=1, workers=24,

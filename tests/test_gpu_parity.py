@@ -140,7 +140,7 @@ def test_launch_shapes_are_bitwise_identical(prec):
               (4, 5, 0, 1, 4, 64), (1, 64, 1, 1, 4, 64), (2, 3, 0, 0, 4, 64),
               (2, 9, 1, 0, 8, 64), (1, 33, 0, 0, 8, 64), (1, 2, 1, 1, 4, 32), (2, 5, 0, 1, 4, 32),
               (2, 11, 1, 0, 4, 32), (1, 4, 1, 0, 8, 32), (2, 33, 0, 0, 8, 32),
-              (4, 7, 1, 0, 8, 0), (4, 33, 0, 0, 8, 0))
+              (4, 7, 1, 0, 8, 0), (4, 33, 0, 0, 8, 0), (2, 6, 1, 0, 8, 0), (4, 5, 0, 0, 4, 0))
     if prec == lbm.LBM_SC_FP32_SHIFTED:
         shapes += ((8, 5, 1, 0, 8, 0), (8, 33, 0, 0, 8, 0))
     for rows, zc, remap, pf, waves, tx in shapes:
@@ -156,8 +156,8 @@ def test_launch_shapes_are_bitwise_identical(prec):
     with make_box(dims, prec=prec, rho_ref=rho_ref) as b:
         bad_shapes = [(3, 4, 1, 0, 4, 64), (2, 0, 1, 0, 4, 64), (2, 4, 2, 0, 4, 64),
                       (2, 4, 1, 0, 6, 64), (4, 4, 1, 0, 8, 64), (2, 4, 1, 1, 8, 64),
-                      (4, 4, 1, 0, 4, 32), (2, 4, 1, 0, 4, 16), (4, 4, 1, 0, 4, 0),
-                      (2, 4, 1, 0, 8, 0), (4, 4, 1, 1, 8, 0)]
+                      (4, 4, 1, 0, 4, 32), (2, 4, 1, 0, 4, 16), (2, 4, 1, 0, 4, 0),
+                      (8, 4, 1, 0, 4, 0), (1, 4, 1, 0, 8, 0), (4, 4, 1, 1, 8, 0)]
         if prec != lbm.LBM_SC_FP32_SHIFTED:
             bad_shapes.append((8, 4, 1, 0, 8, 0))   # 8 nodes per thread: FP32 arithmetic only
         for bad in bad_shapes:
@@ -240,7 +240,7 @@ def test_full_row_tiles_one_step(dims, prec):
     f = fp32_representable(inputs.random_populations(dims, 5 + sum(dims), W * 1.5, amp=0.3), rho_ref)
     G = 1.3 * lbm.lbm_sc_gc(0)
     outs = []
-    for launch in (None, (4, 3, 1, 0, 8, 0)) + (((8, 2, 0, 0, 8, 0),)
+    for launch in (None, (4, 3, 1, 0, 8, 0), (2, 3, 1, 0, 8, 0), (4, 2, 0, 0, 4, 0)) + (((8, 2, 0, 0, 8, 0),)
                                                  if prec == lbm.LBM_SC_FP32_SHIFTED else ()):
         with make_box(dims, prec=prec, rho_ref=rho_ref) as b:
             b.set(f)
