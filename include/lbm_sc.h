@@ -126,6 +126,21 @@ typedef struct {
  * On failure *out is NULL and nothing is leaked. */
 int lbm_sc_create(const lbm_sc_config* cfg, lbm_sc** out);
 
+/* Like lbm_sc_create, but the two population buffers (the ping-pong state, the bulk of a box's
+ * memory) are supplied by the caller, e.g. from a tensor allocator: a and b are device memory of
+ * the current device, 256-byte aligned, not overlapping, each with at least
+ * lbm_sc_population_bytes(cfg) bytes (`bytes`) inside its allocation. The library uses them in
+ * place, never frees them, and does not keep them beyond lbm_sc_destroy; the caller keeps them
+ * alive until then. The observation scratch is still allocated by the library (device_bytes of
+ * lbm_sc_get_info counts only that). LBM_SC_EINVAL, with nothing allocated, if a buffer is NULL,
+ * misaligned, too small, not device memory of the current device, or the two overlap. */
+int lbm_sc_create_with_buffers(const lbm_sc_config* cfg, void* a, void* b, size_t bytes,
+                               lbm_sc** out);
+
+/* Bytes of one population buffer of a box with this configuration (for
+ * lbm_sc_create_with_buffers); a negative lbm_sc_status if cfg is invalid. Host only. */
+int64_t lbm_sc_population_bytes(const lbm_sc_config* cfg);
+
 /* Enqueue nsteps (>= 0) time steps of Eq. (lbm) on the handle's stream: fused pull streaming,
  * density and psi, Shan-Chen force, Guo equilibrium velocity, BGK collision with the Guo term.
  * Runs of graph_steps steps (lbm_sc_launch) are replayed from a hipGraph the handle captures on

@@ -86,7 +86,7 @@ EXPORTS = ("lbm_sc_create", "lbm_sc_step", "lbm_sc_sync", "lbm_sc_observables",
            "lbm_sc_last_error", "lbm_sc_gc", "lbm_sc_coexistence", "lbm_sc_group_create",
            "lbm_sc_group_set", "lbm_sc_group_step", "lbm_sc_group_set_launch",
            "lbm_sc_group_get_launch", "lbm_sc_group_info", "lbm_sc_group_destroy",
-           "lbm_sc_device_bytes")
+           "lbm_sc_device_bytes", "lbm_sc_create_with_buffers", "lbm_sc_population_bytes")
 
 _lib = None
 
@@ -103,6 +103,9 @@ def load():
     L = ctypes.CDLL(LIB_PATH)
     P = ctypes.POINTER
     L.lbm_sc_create.argtypes = [P(LbmScConfig), P(_vp)]
+    L.lbm_sc_create_with_buffers.argtypes = [P(LbmScConfig), _vp, _vp, ctypes.c_size_t, P(_vp)]
+    L.lbm_sc_population_bytes.argtypes = [P(LbmScConfig)]
+    L.lbm_sc_population_bytes.restype = _i64
     L.lbm_sc_step.argtypes = [_vp, _i64]
     L.lbm_sc_sync.argtypes = [_vp]
     L.lbm_sc_observables.argtypes = [_vp, P(LbmScObs), P(_f64), ctypes.c_size_t]
@@ -181,6 +184,21 @@ def lbm_sc_create(cfg):
     return h
 
 
+def lbm_sc_population_bytes(cfg):
+    v = load().lbm_sc_population_bytes(ctypes.byref(cfg))
+    if v < 0:
+        raise LbmScError(v, lbm_sc_last_error())
+    return v
+
+
+def lbm_sc_create_with_buffers(cfg, a, b, nbytes):
+    """a, b: device addresses (ints) of the caller's two population buffers."""
+    h = _vp()
+    _check(load().lbm_sc_create_with_buffers(ctypes.byref(cfg), _vp(a), _vp(b), int(nbytes),
+                                             ctypes.byref(h)))
+    return h
+
+
 def lbm_sc_step(h, nsteps):
     _check(load().lbm_sc_step(h, int(nsteps)))
 
@@ -247,12 +265,20 @@ def lbm_sc_destroy(h):
 
 
 class Box:
-    """Owner of one lbm_sc handle (destroyed with the object)."""
+    """Owner of one lbm_sc handle (destroyed with the object). `buffers`: optionally two device
+    tensors (e.g. torch.empty(lbm_sc_population_bytes(cfg), dtype=torch.uint8, device="cuda"))
+    that hold the populations in place of library allocations; the box keeps them alive."""
 
-    def __init__(self, cfg):
+    def __init__(self, cfg, buffers=None):
         self.cfg = cfg
         self.dims = (cfg.nx, cfg.ny, cfg.nz)
-        self.h = lbm_sc_create(cfg)
+        self.buffers = buffers
+        if buffers is None:
+            self.h = lbm_sc_create(cfg)
+        else:
+            a, b = buffers
+            nbytes = min(a.numel() * a.element_size(), b.numel() * b.element_size())
+            self.h = lbm_sc_create_with_buffers(cfg, a.data_ptr(), b.data_ptr(), nbytes)
 
     def step(self, n):
         lbm_sc_step(self.h, n)
@@ -286,8 +312,9 @@ class Box:
 
     def close(self):
         if self.h is not None:
-            lbm_sc_destroy(self.h)
+            lbm_sc_destroy(self.h)   # waits for the box's stream: the buffers are free after it
             self.h = None
+        self.buffers = None
 
     def __del__(self):
         try:

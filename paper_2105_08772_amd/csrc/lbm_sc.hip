@@ -183,6 +183,7 @@ struct lbm_sc {
     int64_t step = 0;
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    bool own_pop = true;       // false: the population buffers belong to the caller
     double* d_n = nullptr;     // N doubles: density, also the staging buffer of get/set
     double* d_psi = nullptr;   // N doubles
     double* d_u = nullptr;     // 3N doubles: momentum, then velocity
@@ -249,8 +250,11 @@ void release(lbm_sc* h)
     if (!h) return;
     if (h->stream) (void)hipStreamSynchronize(h->stream);
     drop_box_graph(h);
-    void* bufs[] = {h->pop[0], h->pop[1], h->d_n, h->d_psi, h->d_u, h->d_uprev,
-                    h->d_parts, h->d_small, h->d_prof};
+    if (h->own_pop) {
+        for (void* p : h->pop)
+            if (p) (void)hipFree(p);
+    }
+    void* bufs[] = {h->d_n, h->d_psi, h->d_u, h->d_uprev, h->d_parts, h->d_small, h->d_prof};
     for (void* p : bufs)
         if (p) (void)hipFree(p);
     if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
@@ -488,6 +492,13 @@ int64_t lbm_sc_device_bytes(const lbm_sc_config* cfg)
     return (int64_t)sizes_for(cfg).total();
 }
 
+int64_t lbm_sc_population_bytes(const lbm_sc_config* cfg)
+{
+    int rc = validate(cfg);
+    if (rc) return rc;
+    return (int64_t)sizes_for(cfg).popbytes;
+}
+
 double lbm_sc_gc(int32_t psi)
 {
     if (psi != LBM_SC_PSI_EXP && psi != LBM_SC_PSI_ONEMINUS) return std::nan("");
@@ -506,7 +517,39 @@ int lbm_sc_coexistence(int32_t psi, double g_over_gc, double* n_gas, double* n_l
     return LBM_SC_OK;
 }
 
-int lbm_sc_create(const lbm_sc_config* cfg, lbm_sc** out)
+}  // extern "C"
+
+namespace {
+
+// A caller's population buffer: device memory of the current device, 256-byte aligned, with at
+// least `need` bytes from p inside one allocation.
+int check_caller_buffer(const void* p, size_t need, const char* name)
+{
+    if (!p) return fail(LBM_SC_EINVAL, std::string(name) + " is NULL");
+    if (reinterpret_cast<uintptr_t>(p) % 256 != 0)
+        return fail(LBM_SC_EINVAL, std::string(name) + " is not 256-byte aligned");
+    hipPointerAttribute_t attr;
+    int dev = -1;
+    if (hipPointerGetAttributes(&attr, p) != hipSuccess || hipGetDevice(&dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(LBM_SC_EINVAL, std::string(name) + " is not device memory known to HIP");
+    }
+    if (attr.type != hipMemoryTypeDevice || attr.device != dev)
+        return fail(LBM_SC_EINVAL, std::string(name) + " is not device memory of the current device");
+    hipDeviceptr_t base = nullptr;
+    size_t size = 0;
+    if (hipMemGetAddressRange(&base, &size, (hipDeviceptr_t)p) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(LBM_SC_EINVAL, std::string(name) + ": allocation range unknown");
+    }
+    const uintptr_t b = reinterpret_cast<uintptr_t>(base), q = reinterpret_cast<uintptr_t>(p);
+    if (q < b || q - b + need > size)
+        return fail(LBM_SC_EINVAL, std::string(name) + " has fewer than " + std::to_string(need) +
+                                       " bytes in its allocation");
+    return LBM_SC_OK;
+}
+
+int create_box(const lbm_sc_config* cfg, void* buf_a, void* buf_b, size_t buf_bytes, lbm_sc** out)
 {
     if (!out) return fail(LBM_SC_EINVAL, "out is NULL");
     *out = nullptr;
@@ -577,8 +620,31 @@ int lbm_sc_create(const lbm_sc_config* cfg, lbm_sc** out)
     }
 
     const Sizes sz = sizes_for(cfg);
-    if ((rc = alloc(h, &h->pop[0], sz.popbytes)) || (rc = alloc(h, &h->pop[1], sz.popbytes)) ||
-        (rc = alloc(h, (void**)&h->d_n, sz.n8)) || (rc = alloc(h, (void**)&h->d_psi, sz.n8)) ||
+    if (buf_a || buf_b) {
+        // caller-owned population buffers, used in place and never freed here
+        const uintptr_t qa = reinterpret_cast<uintptr_t>(buf_a), qb = reinterpret_cast<uintptr_t>(buf_b);
+        if (buf_bytes < sz.popbytes)
+            rc = fail(LBM_SC_EINVAL, "bytes must be at least lbm_sc_population_bytes(cfg) = " +
+                                         std::to_string(sz.popbytes));
+        else if ((rc = check_caller_buffer(buf_a, sz.popbytes, "buffer a")) ||
+                 (rc = check_caller_buffer(buf_b, sz.popbytes, "buffer b"))) {
+        } else if (qa < qb + sz.popbytes && qb < qa + sz.popbytes) {
+            rc = fail(LBM_SC_EINVAL, "buffers a and b overlap");
+        }
+        if (rc) {
+            std::string msg = g_err;
+            release(h);
+            return fail(rc, msg);
+        }
+        h->own_pop = false;
+        h->pop[0] = buf_a;
+        h->pop[1] = buf_b;
+    } else if ((rc = alloc(h, &h->pop[0], sz.popbytes)) || (rc = alloc(h, &h->pop[1], sz.popbytes))) {
+        std::string msg = g_err;
+        release(h);
+        return fail(rc, msg);
+    }
+    if ((rc = alloc(h, (void**)&h->d_n, sz.n8)) || (rc = alloc(h, (void**)&h->d_psi, sz.n8)) ||
         (rc = alloc(h, (void**)&h->d_u, sz.n24)) || (rc = alloc(h, (void**)&h->d_uprev, sz.n24)) ||
         (rc = alloc(h, (void**)&h->d_parts, sz.parts)) ||
         (rc = alloc(h, (void**)&h->d_small, sz.small)) ||
@@ -634,6 +700,24 @@ int lbm_sc_create(const lbm_sc_config* cfg, lbm_sc** out)
     h->step = 0;
     *out = h;
     return LBM_SC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_sc_create(const lbm_sc_config* cfg, lbm_sc** out)
+{
+    return create_box(cfg, nullptr, nullptr, 0, out);
+}
+
+int lbm_sc_create_with_buffers(const lbm_sc_config* cfg, void* a, void* b, size_t bytes, lbm_sc** out)
+{
+    if (!a || !b) {
+        if (out) *out = nullptr;
+        return fail(LBM_SC_EINVAL, "buffers a and b must both be given");
+    }
+    return create_box(cfg, a, b, bytes, out);
 }
 
 int lbm_sc_step(lbm_sc* h, int64_t nsteps)

@@ -81,6 +81,26 @@ def test_oversized_boxes_are_rejected_before_any_device_work(dims, prec):
     assert "2^31" in lbm.lbm_sc_last_error() or "4 GiB" in lbm.lbm_sc_last_error()
 
 
+def test_population_bytes_is_one_buffer_of_the_device_bytes():
+    for prec in (lbm.LBM_SC_FP64, lbm.LBM_SC_FP32_SHIFTED):
+        cfg = lbm.config(40, 33, 12, prec=prec, radius=3.0, width=2.0)
+        pb = lbm.lbm_sc_population_bytes(cfg)
+        # two buffers plus the FP64 observation scratch (64 B per node) and small arrays
+        assert 2 * pb + 64 * 40 * 33 * 12 < lbm.lbm_sc_device_bytes(cfg)
+        assert pb >= 19 * 40 * 33 * 12 * (8 if prec == lbm.LBM_SC_FP64 else 4)
+        assert pb % 256 == 0
+    with pytest.raises(lbm.LbmScError):
+        lbm.lbm_sc_population_bytes(lbm.config(0, 4, 4))
+
+
+def test_create_with_buffers_rejects_missing_buffers_before_any_device_work():
+    cfg = lbm.config(8, 8, 8, radius=3.0, width=2.0)
+    for a, b in ((0, 0), (0, 4096), (4096, 0)):
+        with pytest.raises(lbm.LbmScError) as e:
+            lbm.lbm_sc_create_with_buffers(cfg, a, b, 1 << 20)
+        assert e.value.code == lbm.LBM_SC_EINVAL
+
+
 def test_ctypes_structs_match_the_c_layout(tmp_path):
     """Compile a probe against include/lbm_sc.h and compare every field offset and struct size
     with the ctypes mirrors of the Python binding."""
