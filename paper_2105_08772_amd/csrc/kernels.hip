@@ -421,21 +421,27 @@ __device__ __forceinline__ void step_tile(const BoxDesc& bd, const T* __restrict
     double pdn[R];
     C pjx[R], pjy[R], pjz[R];
     const int nplanes = (z1 - z0) + 2;
-    // the step count behind the dither: a vector load (a relaxed atomic, so that it is not
-    // turned into a scalar load, whose wait would also hold up the LDS traffic) issued behind the
-    // first plane's row loads, so that it delays none of them, and moved to a scalar register once
-    // the plane is reduced (waiting for the halo loads issued after it has covered its latency)
+    // The step count behind the dither is read with a vector load (a relaxed atomic, so that it
+    // is not turned into a scalar load, whose wait would also hold up the LDS traffic). It is
+    // issued in every plane, behind that plane's population loads, so that it delays none of
+    // them and the load counter waits stay exact (a load in the first plane only would leave
+    // every later wait one load stricter); the first plane's value is used at the start of the
+    // second, when it has long arrived.
     unsigned tkv = 0u, tk = 0u, seed = 0u;
     if constexpr (PF) {
         const Planes zr = planes(z0 - 1);
 #pragma unroll
         for (int r = 0; r < R; ++r)
             if (ld[r]) load_node(zr, popb, yo[r], xo, fr[r]);
-        tkv = __hip_atomic_load(tick_in, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
         if (has_halo) load_node(zr, popb, hyo, hxo, fh);
+        tkv = __hip_atomic_load(tick_in, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
     }
     for (int k = 0; k < nplanes; ++k) {
         const int p = z0 - 1 + k;
+        if (k == 1) {
+            tk = __builtin_amdgcn_readfirstlane(tkv);
+            seed = dither_shift(tk);
+        }
         C(*slot)[LX] = ring[k & 3];
         double cdn[R];
         C cjx[R], cjy[R], cjz[R];
@@ -443,8 +449,6 @@ __device__ __forceinline__ void step_tile(const BoxDesc& bd, const T* __restrict
         for (int r = 0; r < R; ++r) {
             if constexpr (!PF) {
                 if (ld[r]) load_node(planes(p), popb, yo[r], xo, fr[r]);
-                if (k == 0 && r == R - 1)
-                    tkv = __hip_atomic_load(tick_in, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
             }
             moments(fr[r], cdn[r], cjx[r], cjy[r], cjz[r]);
             slot[(wv * R + r) * SUB + ls + 1][lc + 1] = psi_of<C, PSI>(rho_ref + (C)cdn[r]);
@@ -463,13 +467,12 @@ __device__ __forceinline__ void step_tile(const BoxDesc& bd, const T* __restrict
                 for (int r = 0; r < R; ++r)
                     if (ld[r]) load_node(zn, popb, yo[r], xo, fr[r]);
                 if (has_halo) load_node(zn, popb, hyo, hxo, fh);
+                tkv = __hip_atomic_load(tick_in, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
             }
+        } else {
+            tkv = __hip_atomic_load(tick_in, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
         }
         __syncthreads();
-        if (k == 0) {
-            tk = __builtin_amdgcn_readfirstlane(tkv);
-            seed = dither_shift(tk);
-        }
         if (k >= 2) {
             // collide plane q = p - 1 with psi of planes q - 1, q, q + 1
             const C(*pm)[LX] = ring[(k - 2) & 3];
@@ -594,11 +597,14 @@ __device__ __forceinline__ void step_rows(const BoxDesc& bd, const T* __restrict
     double pdn[NPT];
     C pjx[NPT], pjy[NPT], pjz[NPT];
     const int nplanes = (z1 - z0) + 2;
-    // step count behind the dither, loaded as in step_tile once the first plane is reduced and
-    // moved to a scalar register after the second (whose loads cover its latency)
+    // step count behind the dither, loaded in every plane and used as in step_tile
     unsigned tkv = 0u, tk = 0u, seed = 0u;
     for (int kp = 0; kp < nplanes; ++kp) {
         const int p = z0 - 1 + kp;
+        if (kp == 1) {
+            tk = __builtin_amdgcn_readfirstlane(tkv);
+            seed = dither_shift(tk);
+        }
         const Planes zr = planes(p);
         C* slot = ring[kp & 3];
         double cdn[NPT];
@@ -616,12 +622,8 @@ __device__ __forceinline__ void step_rows(const BoxDesc& bd, const T* __restrict
                 slot[lyk[k] * nx + xk[k]] = psi_of<C, PSI>(rho_ref + (C)cdn[k]);
             }
         }
-        if (kp == 0) tkv = __hip_atomic_load(tick_in, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        tkv = __hip_atomic_load(tick_in, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
         __syncthreads();
-        if (kp == 1) {
-            tk = __builtin_amdgcn_readfirstlane(tkv);
-            seed = dither_shift(tk);
-        }
         if (kp >= 2) {
             // collide plane q = p - 1 with psi of planes q - 1, q, q + 1
             const C* pm = ring[(kp - 2) & 3];
