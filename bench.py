@@ -206,7 +206,7 @@ def run_batched(args, torch, lbm, stream, steps, log):
     }
 
 
-def run_served(args, torch, lbm, log):
+def run_served(args, torch, lbm, log, capacity_mlups=None):
     """The served workload: seeded Poisson arrivals of droplet/bubble requests (L ~ U{32..192},
     radius ~ U[max(6, 0.15 L), min(60, 0.35 L)], G/G_c ~ U[1.05, 1.8], exp psi, FP32-shifted),
     continuously batched into one multi-box launch per step, admitted by free HBM (less an 8 GiB
@@ -214,7 +214,9 @@ def run_served(args, torch, lbm, log):
     observations 2048 steps apart; at most 100000 steps). Reports p50/p99 time to equilibrium
     and aggregate MLUPS. The same requests with the same arrivals and stop rule are then served
     by the plain single-box FP64 path, first come first served, one box at a time (measured, not
-    modelled), and each request's converged dP is compared between the two."""
+    modelled), and each request's converged dP is compared between the two. The offered load is
+    the arrival rate times the mean work of a request (nodes x steps it ran), stated against the
+    batched workload's throughput when that ran in the same invocation."""
     from tests import inputs
     from paper_2105_08772_amd import serve
     rate = args.served_rate
@@ -245,8 +247,12 @@ def run_served(args, torch, lbm, log):
     for a, b in zip(recs, recs64):
         if a.status == "converged" and b.status == "converged":
             errs.append(abs(a.obs["dP"] - b.obs["dP"]) / abs(b.obs["dP"]))
+    work = [r.L ** 3 * r.steps for r in recs]
+    offered = rate * sum(work) / len(work) / 1e6 if work else 0.0
     out = dict(summ)
     out.update({
+        "offered_load_MLUPS": round(offered, 1),
+        "offered_over_batched_capacity": round(offered / capacity_mlups, 3) if capacity_mlups else None,
         "workload": f"{len(spec)} requests, Poisson arrivals rate {rate}/s (seed 8772), L~U{{32..192}}, "
                     "R~U[max(6,0.15L),min(60,0.35L)], G/G_c~U[1.05,1.8], droplet/bubble, exp psi, "
                     "FP32-shifted, stop: dP change <1e-5 or max|du|<1e-9 per 2048 steps",
@@ -500,7 +506,12 @@ def main():
     ap.add_argument("--copy-reps", type=int, default=5)
     ap.add_argument("--served-count", type=int, default=0,
                     help="requests of the served workload to run after the main timing (0 = skip)")
-    ap.add_argument("--served-rate", type=float, default=1.2, help="request arrival rate (1/s)")
+    ap.add_argument("--served-rate", type=float, default=1.0,
+                    help="request arrival rate (1/s); the default offers about 0.8 of the batched "
+                         "throughput")
+    ap.add_argument("--served-capacity", type=float, default=None,
+                    help="batched throughput (MLUPS) to state the offered load against when the "
+                         "batched workload is not run in the same invocation")
     ap.add_argument("--tolman", action="store_true",
                     help="run the scaled droplet/bubble sweep and the Tolman analysis")
     ap.add_argument("--batched-steps", type=int, default=20000,
@@ -661,8 +672,9 @@ def main():
         out["tolman"] = run_tolman(args, torch, lbm,
                                    lambda m: print("# " + m, file=sys.stderr, flush=True))
     if args.served_count > 0:
+        cap = out["batched"]["MLUPS"] if "batched" in out else args.served_capacity
         out["served"] = run_served(args, torch, lbm,
-                                   lambda m: print("# " + m, file=sys.stderr, flush=True))
+                                   lambda m: print("# " + m, file=sys.stderr, flush=True), cap)
     if not args.no_cpu:
         print("# timing the oracle on the host cores", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args, nodes)
