@@ -497,7 +497,7 @@ def main():
     ap.add_argument("--waves", type=int, default=0)
     ap.add_argument("--tile-x", type=int, default=-1, help="64, 32, or 0 for full-row tiles")
     ap.add_argument("--tune", action="store_true", help="sweep launch shapes, keep the fastest")
-    ap.add_argument("--cpu-steps", type=int, default=15)
+    ap.add_argument("--cpu-steps", type=int, default=25)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-copy", action="store_true")
     ap.add_argument("--mode", choices=["step", "copy"], default="step",
