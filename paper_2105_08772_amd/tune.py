@@ -21,10 +21,10 @@ SHAPES = [dict(waves=4, rows=r, prefetch=pf, tile_x=64) for r in (1, 2, 4) for p
 
 
 def group_candidates():
-    """Every compiled shape with z chunks of 8..64 planes or per-box chunks (z_chunk 0) of
+    """Every compiled shape with z chunks of 6..64 planes or per-box chunks (z_chunk 0) of
     4, 8 or 16 items per CU, one workgroup per item or persistent workers."""
     out = []
-    chunks = [dict(z_chunk=zc, items_per_cu=0) for zc in (8, 16, 32, 64)]
+    chunks = [dict(z_chunk=zc, items_per_cu=0) for zc in (6, 8, 16, 32, 64)]
     chunks += [dict(z_chunk=0, items_per_cu=k) for k in (4, 8, 16)]
     for shape, ch in itertools.product(SHAPES, chunks):
         out.append(dict(shape, **ch, xcd_remap=1, persistent=0, workers=0))
