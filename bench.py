@@ -280,7 +280,7 @@ def run_served(args, torch, lbm, log, capacity_mlups=None):
 
 def run_tolman(args, torch, lbm, log):
     """A scaled version of the paper's droplet/bubble sweep (Sec. 4) for both pseudopotentials:
-    couplings G/G_c - 1 in {0.159, 0.215, 0.293}, odd box sizes L in {41, ..., 157}, R = L/4,
+    couplings G/G_c - 1 in {0.159, 0.215, 0.293}, odd box sizes L in {41, ..., 251}, R = L/4,
     droplets and bubbles, the paper's tanh profile (width 1), all boxes served together until
     the paper's criterion (relative dP change < 1e-5 over 2048 steps), once with FP32-shifted
     and once with FP64 populations. The Tolman fit per coupling gives sigma_0 and delta; sigma_0
@@ -289,7 +289,7 @@ def run_tolman(args, torch, lbm, log):
     against its FP64 counterpart, and the two pseudopotentials are compared through the
     mean-field prefactor sigma_0 / (G/G_c - 1)^(3/2)."""
     out = {"workload": "psi in {exp, 1-exp} x G/G_c-1 in {0.159,0.215,0.293} x L in "
-                       "{41,47,55,61,67,77,87,103,123,157} x {droplet,bubble}, R=L/4, tanh width "
+                       "{41,47,55,61,67,77,87,103,123,157,201,251} x {droplet,bubble}, R=L/4, tanh width "
                        "1, served together until |dP change|/dP < 1e-5 per 2048 steps; "
                        "FP32-shifted and FP64 sweeps"}
     for name, psi in (("exp", lbm.LBM_SC_PSI_EXP), ("oneminus", lbm.LBM_SC_PSI_ONEMINUS)):
@@ -307,7 +307,7 @@ def run_tolman(args, torch, lbm, log):
 def tolman_sweep(torch, lbm, log, psi):
     from paper_2105_08772_amd import analysis, serve
     ratios = (1.159, 1.215, 1.293)
-    sizes = (41, 47, 55, 61, 67, 77, 87, 103, 123, 157)
+    sizes = (41, 47, 55, 61, 67, 77, 87, 103, 123, 157, 201, 251)
     spec = {}
     rid = 0
     for g in ratios:
