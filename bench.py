@@ -519,7 +519,7 @@ def main():
                          "(0 = skip; default: the configuration's 20000)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1",
+        print("bench.py: the library runs on one GPU only (there is no multi-GPU path); use --gpus 1",
               file=sys.stderr)
         sys.exit(2)
 

@@ -134,3 +134,14 @@ def test_ctypes_structs_match_the_c_layout(tmp_path):
 def ctypes_sizeof(t):
     import ctypes
     return ctypes.sizeof(t)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys
+    import os
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode != 0
+    assert "one GPU" in (r.stdout + r.stderr)
