@@ -171,6 +171,13 @@ int lbm_sc_get_populations(lbm_sc* h, double* f, size_t len);
  * reference. Synchronises. Not for use inside a stream capture. */
 int lbm_sc_set_populations(lbm_sc* h, const double* f, size_t len);
 
+/* Set the step counter (>= 0; LBM_SC_EINVAL otherwise) together with the step count that seeds
+ * the FP32 rest-population dither, e.g. after lbm_sc_set_populations when resuming a saved
+ * state: a state saved with lbm_sc_get_populations at step n and restored with
+ * lbm_sc_set_populations + lbm_sc_set_step(n) continues bitwise as the uninterrupted run would
+ * (FP64 and FP32 storage alike). Synchronises. Not for use inside a stream capture. */
+int lbm_sc_set_step(lbm_sc* h, int64_t step);
+
 /* Launch shape of the fused step kernel. The workgroup is 64*waves threads (waves wave64s) and
  * owns an x-y tile tile_x nodes wide and waves*rows*(64/tile_x) rows high (at tile_x = 32 each
  * wave row covers two rows of 32 nodes), and a run of z_chunk planes along z. Supported shapes:

@@ -86,7 +86,8 @@ EXPORTS = ("lbm_sc_create", "lbm_sc_step", "lbm_sc_sync", "lbm_sc_observables",
            "lbm_sc_last_error", "lbm_sc_gc", "lbm_sc_coexistence", "lbm_sc_group_create",
            "lbm_sc_group_set", "lbm_sc_group_step", "lbm_sc_group_set_launch",
            "lbm_sc_group_get_launch", "lbm_sc_group_info", "lbm_sc_group_destroy",
-           "lbm_sc_device_bytes", "lbm_sc_create_with_buffers", "lbm_sc_population_bytes")
+           "lbm_sc_device_bytes", "lbm_sc_create_with_buffers", "lbm_sc_population_bytes",
+           "lbm_sc_set_step")
 
 _lib = None
 
@@ -111,6 +112,7 @@ def load():
     L.lbm_sc_observables.argtypes = [_vp, P(LbmScObs), P(_f64), ctypes.c_size_t]
     L.lbm_sc_get_populations.argtypes = [_vp, P(_f64), ctypes.c_size_t]
     L.lbm_sc_set_populations.argtypes = [_vp, P(_f64), ctypes.c_size_t]
+    L.lbm_sc_set_step.argtypes = [_vp, _i64]
     L.lbm_sc_set_launch.argtypes = [_vp, P(LbmScLaunch)]
     L.lbm_sc_get_launch.argtypes = [_vp, P(LbmScLaunch)]
     L.lbm_sc_stream_copy.argtypes = [_vp, _vp, ctypes.c_size_t, _vp]
@@ -236,6 +238,10 @@ def lbm_sc_set_populations(h, f):
     _check(load().lbm_sc_set_populations(h, f.ctypes.data_as(ctypes.POINTER(_f64)), f.size))
 
 
+def lbm_sc_set_step(h, step):
+    _check(load().lbm_sc_set_step(h, int(step)))
+
+
 def lbm_sc_set_launch(h, rows, z_chunk, xcd_remap=1, prefetch=0, waves=4, tile_x=64,
                       graph_steps=64):
     l = LbmScLaunch(rows, z_chunk, xcd_remap, prefetch, waves, tile_x, graph_steps)
@@ -299,6 +305,9 @@ class Box:
 
     def set(self, f):
         lbm_sc_set_populations(self.h, f)
+
+    def set_step(self, step):
+        lbm_sc_set_step(self.h, step)
 
     def set_launch(self, rows, z_chunk, xcd_remap=1, prefetch=0, waves=4, tile_x=64,
                    graph_steps=64):

@@ -827,6 +827,18 @@ int lbm_sc_set_populations(lbm_sc* h, const double* f, size_t len)
     return LBM_SC_OK;
 }
 
+int lbm_sc_set_step(lbm_sc* h, int64_t step)
+{
+    if (!h) return fail(LBM_SC_EINVAL, "handle is NULL");
+    if (step < 0) return fail(LBM_SC_EINVAL, "step must be >= 0");
+    // the dither's step count of the current buffer (kept modulo 2^32) follows the step counter
+    const unsigned t = (unsigned)(uint64_t)step;
+    HIP_TRY(hipMemcpyAsync(h->box.tick + h->cur, &t, sizeof(t), hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    h->step = step;
+    return LBM_SC_OK;
+}
+
 int lbm_sc_get_info(lbm_sc* h, lbm_sc_info* out)
 {
     if (!h || !out) return fail(LBM_SC_EINVAL, "handle or out is NULL");
