@@ -93,3 +93,27 @@ def test_bad_caller_buffers_are_rejected():
     h = lbm.lbm_sc_create_with_buffers(cfg, a.data_ptr(), b.data_ptr(), need)
     lbm.lbm_sc_step(h, 2)
     lbm.lbm_sc_destroy(h)
+
+
+@pytest.mark.parametrize("prec", [lbm.LBM_SC_FP32_SHIFTED, lbm.LBM_SC_FP64])
+def test_no_stale_reads_with_poisoned_buffers(prec):
+    """Poison check: both buffers are filled with NaN bytes before the box is created (the
+    initial state then overwrites the nodes of the first, leaving its padding poisoned); after
+    each of several steps the state must be finite and bitwise equal to a box on clean library
+    buffers, so the step reads nothing it did not write (row padding, pitch padding and halo
+    wrap included)."""
+    import torch
+    s = torch.cuda.Stream()
+    cfg = lbm.config(37, 29, 23, psi=0, geom=lbm.LBM_SC_DROPLET, prec=prec, g_over_gc=1.3,
+                     radius=7.0, width=2.0, noise_amp=1e-6, seed=21, stream=s.cuda_stream)
+    a, b = torch_buffers(torch, cfg)
+    a.fill_(0xFF)
+    b.fill_(0xFF)
+    torch.cuda.synchronize()
+    with lbm.Box(cfg) as ref, lbm.Box(cfg, buffers=(a, b)) as box:
+        for n in (1, 1, 3):
+            box.step(n)
+            ref.step(n)
+            got = box.get()
+            assert np.isfinite(got).all()
+            assert np.array_equal(got, ref.get())
