@@ -222,10 +222,10 @@ def run_served(args, torch, lbm, log, capacity_mlups=None):
     rate = args.served_rate
     spec = inputs.served_requests(seed=8772, count=args.served_count, rate=rate)
 
-    def serve_all(backend, **kw):
+    def serve_all(backend, journal=None, **kw):
         budget = backend.free_bytes() - (8 << 30)
         srv = serve.Server(backend, budget, chunk=512, observe_every=2048, max_steps=100000,
-                           dp_tol=1e-5, du_tol=1e-9, log=log, **kw)
+                           dp_tol=1e-5, du_tol=1e-9, log=log, journal=journal, **kw)
         for r in spec:
             srv.submit(serve.Request(**r))
         recs = srv.run()
@@ -238,7 +238,10 @@ def run_served(args, torch, lbm, log, capacity_mlups=None):
     # for a box whose rows are too long)
     be.set_launch(rows=4, waves=8, tile_x=0, z_chunk=8, prefetch=0, persistent=0, workers=0,
                   graph_steps=64)
-    srv, recs, budget = serve_all(be)
+    journal = open(args.served_journal, "w") if args.served_journal else None
+    srv, recs, budget = serve_all(be, journal=journal)
+    if journal:
+        journal.close()
     summ = srv.summary()
     log("served: FP64 single-box path, one request at a time")
     srv64, recs64, _ = serve_all(serve.GpuBackend(prec=lbm.LBM_SC_FP64, single=True), max_active=1)
@@ -509,6 +512,8 @@ def main():
     ap.add_argument("--served-rate", type=float, default=1.0,
                     help="request arrival rate (1/s); the default offers about 0.8 of the batched "
                          "throughput")
+    ap.add_argument("--served-journal", default=None,
+                    help="write one JSON line per served request (FP32 batched run) to this file")
     ap.add_argument("--served-capacity", type=float, default=None,
                     help="batched throughput (MLUPS) to state the offered load against when the "
                          "batched workload is not run in the same invocation")

@@ -30,6 +30,7 @@ The GPU work goes through a backend object (GpuBackend below); the scheduler its
 Python so that admission, cancellation and failure handling can be exercised on the CPU.
 """
 import dataclasses
+import json
 import time
 
 
@@ -61,6 +62,7 @@ class Record:
     final: object = None        # final populations, when the server keeps them
     contrast0: float = None     # |n_center - n_far| at admission
     valid: bool = None          # converged and centre of mass within com_tol of the centre
+    history: list = dataclasses.field(default_factory=list)  # (steps, dP) at every observation
 
     @property
     def time_to_equilibrium(self):
@@ -158,7 +160,7 @@ def percentile(values, q):
 class Server:
     def __init__(self, backend, budget_bytes, chunk=512, observe_every=2048, max_steps=200000,
                  dp_tol=1e-5, du_tol=1e-9, mass_tol=None, clock=None, sleep=None, log=None,
-                 keep_final=False, com_tol=1e-3, max_active=None):
+                 keep_final=False, com_tol=1e-3, max_active=None, journal=None):
         if observe_every % chunk:
             raise ValueError("observe_every must be a multiple of chunk")
         if observe_every % 2:
@@ -175,6 +177,9 @@ class Server:
         self.keep_final = keep_final
         self.com_tol = com_tol
         self.max_active_allowed = max_active   # None: limited by memory only
+        # journal: a writable text file; one JSON line per finished request (request, status,
+        # steps, times, tolerances, final observables, dP history)
+        self.journal = journal
         self.queue = []            # requests not yet admitted, arrival order
         self.active = {}           # rid -> (request, box, record, last_obs)
         self.records = {}
@@ -183,12 +188,14 @@ class Server:
         self.node_steps = 0
         self.max_active = 0
         self._cancel = set()
+        self._requests = {}
 
     # -- requests -------------------------------------------------------------------------------
     def submit(self, req):
         self.queue.append(req)
         self.queue.sort(key=lambda r: (r.arrival, r.rid))
         self.records[req.rid] = Record(rid=req.rid, L=req.L, arrival=req.arrival)
+        self._requests[req.rid] = req
 
     def cancel(self, rid):
         self._cancel.add(rid)
@@ -213,6 +220,26 @@ class Server:
         if self.log:
             self.log(f"retire {rid} L={req.L} {status} ({criterion}) steps={rec.steps} "
                      f"t={rec.finished:.3f}s")
+        self._write_journal(rec)
+
+    def _write_journal(self, rec):
+        if self.journal is None:
+            return
+        req = self._requests.get(rec.rid)
+        obs = None
+        if rec.obs is not None:
+            obs = {k: (list(v) if isinstance(v, (list, tuple)) else v) for k, v in rec.obs.items()
+                   if isinstance(v, (int, float, list, tuple))}
+        line = {"rid": rec.rid, "request": dataclasses.asdict(req) if req else None,
+                "status": rec.status, "criterion": rec.criterion, "steps": rec.steps,
+                "arrival_s": rec.arrival, "admitted_s": rec.admitted, "finished_s": rec.finished,
+                "time_to_equilibrium_s": rec.time_to_equilibrium, "valid": rec.valid,
+                "tolerances": {"dp_tol": self.dp_tol, "du_tol": self.du_tol,
+                               "mass_tol": self.mass_tol, "observe_every": self.every,
+                               "max_steps": self.max_steps},
+                "history": rec.history, "obs": obs}
+        self.journal.write(json.dumps(line) + "\n")
+        self.journal.flush()
 
     def _admit(self):
         changed = False
@@ -223,11 +250,13 @@ class Server:
             if req.rid in self._cancel:
                 self.queue.pop(0)
                 rec.status, rec.finished = "cancelled", now
+                self._write_journal(rec)
                 continue
             need = self.b.bytes_needed(req)
             if need > self.budget:
                 self.queue.pop(0)
                 rec.status, rec.finished, rec.criterion = "rejected", now, "larger than budget"
+                self._write_journal(rec)
                 continue
             if self.used + need > self.budget:
                 break                  # first in, first admitted: wait for memory
@@ -251,6 +280,7 @@ class Server:
     def _check(self, rid, obs):
         req, box, rec, last = self.active[rid]
         self.active[rid] = (req, box, rec, obs)
+        rec.history.append((rec.steps, obs.get("dP")))
         if not obs["finite"]:
             return "unstable", "non-finite or n <= 0"
         if abs(obs["n_center"] - obs["n_far"]) < 0.5 * rec.contrast0:

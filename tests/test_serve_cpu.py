@@ -176,3 +176,24 @@ def test_percentile_nearest_rank():
     assert serve.percentile(v, 99) == 99
     assert serve.percentile([3.0], 99) == 3.0
     assert serve.percentile([1, 2, 3, 4], 50) == 2
+
+
+def test_journal_has_one_json_line_per_request():
+    import io
+    import json
+    buf = io.StringIO()
+    reqs = [req(0, 10, 0.0), req(1, 10, 0.0), req(2, 10**3, 0.0), req(3, 10, 0.0)]
+    srv, be, clock = make(reqs, budget=5000, relax={0: 300.0, 1: 300.0}, fail_at={3: 4096},
+                          journal=buf)
+    srv.cancel(1)
+    srv.run()
+    lines = [json.loads(l) for l in buf.getvalue().splitlines()]
+    assert sorted(l["rid"] for l in lines) == [0, 1, 2, 3]
+    by = {l["rid"]: l for l in lines}
+    assert by[0]["status"] == "converged" and by[0]["criterion"] == "dP"
+    assert by[0]["request"]["L"] == 10 and by[0]["tolerances"]["dp_tol"] == 1e-5
+    assert [h[0] for h in by[0]["history"]] == list(range(2048, by[0]["steps"] + 1, 2048))
+    assert by[0]["obs"]["dP"] == by[0]["history"][-1][1]
+    assert by[0]["time_to_equilibrium_s"] > 0
+    assert by[1]["status"] == "cancelled" and by[2]["status"] == "rejected"
+    assert by[3]["status"] == "unstable" and by[3]["history"][-1][0] == 4096
