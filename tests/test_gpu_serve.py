@@ -48,13 +48,13 @@ REQS = [
 ]
 
 
-def serve_all(reqs, budget=None):
+def serve_all(reqs, budget=None, journal=None):
     clock = Clock()
     be = ChunkClockGpu(clock)
     if budget is None:
         budget = sum(be.bytes_needed(serve.Request(**r)) for r in reqs)
     srv = serve.Server(be, budget, chunk=256, observe_every=512, max_steps=40000, clock=clock,
-                       sleep=clock.sleep, keep_final=True)
+                       sleep=clock.sleep, keep_final=True, journal=journal)
     for r in reqs:
         srv.submit(serve.Request(**r))
     recs = {r.rid: r for r in srv.run()}
@@ -62,10 +62,32 @@ def serve_all(reqs, budget=None):
     return recs, srv
 
 
+JOURNAL = []
+
+
+class ListJournal:
+    def write(self, text):
+        JOURNAL.append(text)
+
+    def flush(self):
+        pass
+
+
 @pytest.fixture(scope="module")
 def mixed():
     say("serving 5 requests together")
-    return serve_all(REQS)
+    return serve_all(REQS, journal=ListJournal())
+
+
+def test_journal_records_every_request(mixed):
+    import json
+    recs, _ = mixed
+    lines = [json.loads(t) for t in JOURNAL]
+    assert sorted(l["rid"] for l in lines) == sorted(recs)
+    for l in lines:
+        r = recs[l["rid"]]
+        assert l["status"] == r.status and l["steps"] == r.steps
+        assert l["obs"]["dP"] == r.obs["dP"] and len(l["history"]) == r.steps // 512
 
 
 def test_requests_overlap_on_the_device(mixed):
