@@ -213,8 +213,7 @@ int lbm_sc_get_launch(lbm_sc* h, lbm_sc_launch* out);
  * work items, so boxes of different sizes, pseudopotentials, couplings and relaxation times share
  * the GPU in a single launch. The per-node arithmetic is the same as lbm_sc_step, so a box
  * stepped in a group ends bitwise equal to the same box stepped alone. All boxes of a group must
- * have the same precision, LBM_SC_FP64 or LBM_SC_FP32_SHIFTED (FP32_SHIFTED_MATH64 boxes are
- * stepped alone), and must have been created on the group's stream. Boxes stay
+ * have the same precision (any of the three) and must have been created on the group's stream. Boxes stay
  * owned by the caller; the group keeps their handles until the next lbm_sc_group_set or
  * lbm_sc_group_destroy, and they must not be destroyed in between.
  * ------------------------------------------------------------------------------------------ */
@@ -240,8 +239,7 @@ typedef struct {
 int lbm_sc_group_create(void* stream, lbm_sc_group** out);
 
 /* Set the boxes stepped by the group (nbox >= 0; an empty group steps nothing). Validates that
- * every box has the group's stream and that all share one precision, FP64 or FP32_SHIFTED
- * (LBM_SC_EINVAL otherwise),
+ * every box has the group's stream and that all share one precision (LBM_SC_EINVAL otherwise),
  * builds the work list for the current launch shape and uploads it (stream-ordered). */
 int lbm_sc_group_set(lbm_sc_group* g, lbm_sc* const* boxes, int32_t nbox);
 

@@ -713,10 +713,10 @@ __global__ __launch_bounds__(64 * WAVES) void k_step(StepArgs a, const T* __rest
 // (rows, prefetch) is shared. Box b reads pop[(phase_b + parity) & 1] and writes the other.
 // ------------------------------------------------------------------------------------------
 
-template <typename T, int R, bool PF, int WAVES, int BXT>
+template <typename T, typename C, int R, bool PF, int WAVES, int BXT>
 __device__ __forceinline__ void group_item(const GroupBox* __restrict__ boxes, int nbox,
                                            unsigned item, int parity,
-                                           RingOf<T, R, WAVES, BXT>& ring)
+                                           RingOf<C, R, WAVES, BXT>& ring)
 {
     // box of the item: last box whose first item is <= item
     int lo = 0, hi = nbox - 1;
@@ -742,31 +742,31 @@ __device__ __forceinline__ void group_item(const GroupBox* __restrict__ boxes, i
     const bool tau1 = g.b.tau == 1.0;
     if constexpr (BXT == 0) {
         if (g.b.psi == 0) {
-            if (tau1) step_rows<T, T, 0, true, R, WAVES>(g.b, src, dst, g.by, tiy, z0, z1, tin, tout, ring);
-            else step_rows<T, T, 0, false, R, WAVES>(g.b, src, dst, g.by, tiy, z0, z1, tin, tout, ring);
+            if (tau1) step_rows<T, C, 0, true, R, WAVES>(g.b, src, dst, g.by, tiy, z0, z1, tin, tout, ring);
+            else step_rows<T, C, 0, false, R, WAVES>(g.b, src, dst, g.by, tiy, z0, z1, tin, tout, ring);
         } else {
-            if (tau1) step_rows<T, T, 1, true, R, WAVES>(g.b, src, dst, g.by, tiy, z0, z1, tin, tout, ring);
-            else step_rows<T, T, 1, false, R, WAVES>(g.b, src, dst, g.by, tiy, z0, z1, tin, tout, ring);
+            if (tau1) step_rows<T, C, 1, true, R, WAVES>(g.b, src, dst, g.by, tiy, z0, z1, tin, tout, ring);
+            else step_rows<T, C, 1, false, R, WAVES>(g.b, src, dst, g.by, tiy, z0, z1, tin, tout, ring);
         }
     } else {
         if (g.b.psi == 0) {
-            if (tau1) step_tile<T, T, 0, true, R, PF, WAVES, BXT>(g.b, src, dst, tix, tiy, z0, z1, tin, tout, ring);
-            else step_tile<T, T, 0, false, R, PF, WAVES, BXT>(g.b, src, dst, tix, tiy, z0, z1, tin, tout, ring);
+            if (tau1) step_tile<T, C, 0, true, R, PF, WAVES, BXT>(g.b, src, dst, tix, tiy, z0, z1, tin, tout, ring);
+            else step_tile<T, C, 0, false, R, PF, WAVES, BXT>(g.b, src, dst, tix, tiy, z0, z1, tin, tout, ring);
         } else {
-            if (tau1) step_tile<T, T, 1, true, R, PF, WAVES, BXT>(g.b, src, dst, tix, tiy, z0, z1, tin, tout, ring);
-            else step_tile<T, T, 1, false, R, PF, WAVES, BXT>(g.b, src, dst, tix, tiy, z0, z1, tin, tout, ring);
+            if (tau1) step_tile<T, C, 1, true, R, PF, WAVES, BXT>(g.b, src, dst, tix, tiy, z0, z1, tin, tout, ring);
+            else step_tile<T, C, 1, false, R, PF, WAVES, BXT>(g.b, src, dst, tix, tiy, z0, z1, tin, tout, ring);
         }
     }
 }
 
 // One workgroup per work item (the hardware dispatcher balances the uneven items).
-template <typename T, int R, bool PF, int WAVES, int BXT>
+template <typename T, typename C, int R, bool PF, int WAVES, int BXT>
 __global__ __launch_bounds__(64 * WAVES) void k_step_group(const GroupBox* __restrict__ boxes,
                                                            int nbox, int parity, int remap)
 {
-    __shared__ RingOf<T, R, WAVES, BXT> ring;
+    __shared__ RingOf<C, R, WAVES, BXT> ring;
     const unsigned item = remap ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
-    group_item<T, R, PF, WAVES, BXT>(boxes, nbox, item, parity, ring);
+    group_item<T, C, R, PF, WAVES, BXT>(boxes, nbox, item, parity, ring);
 }
 
 // Persistent variant: a fixed grid whose workgroups take items from eight work queues, one per
@@ -775,11 +775,11 @@ __global__ __launch_bounds__(64 * WAVES) void k_step_group(const GroupBox* __res
 // draws tickets until its queue is exhausted; the last workgroup to finish clears the queues and
 // the finish counter for the next launch, so the kernel needs no host-side reset and can be
 // replayed from a captured graph.
-template <typename T, int R, bool PF, int WAVES, int BXT>
+template <typename T, typename C, int R, bool PF, int WAVES, int BXT>
 __global__ __launch_bounds__(64 * WAVES) void k_step_group_persistent(
     const GroupBox* __restrict__ boxes, int nbox, int parity, QueueState* __restrict__ q)
 {
-    __shared__ RingOf<T, R, WAVES, BXT> ring;
+    __shared__ RingOf<C, R, WAVES, BXT> ring;
     __shared__ unsigned ticket;
     const unsigned xcd = blockIdx.x % 8u;
     const unsigned begin = q->range[xcd], end = q->range[xcd + 1];
@@ -789,7 +789,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_step_group_persistent(
         const unsigned item = ticket;
         __syncthreads();
         if (item >= end) break;
-        group_item<T, R, PF, WAVES, BXT>(boxes, nbox, item, parity, ring);
+        group_item<T, C, R, PF, WAVES, BXT>(boxes, nbox, item, parity, ring);
         __syncthreads();  // the next item rewrites the LDS ring
     }
     if (threadIdx.x == 0) {
@@ -1280,31 +1280,31 @@ hipError_t launch_step(bool fp32, bool math64, const BoxDesc& b, const StepShape
                   : dispatch_step<float, float>(s, a, src, dst, st);
 }
 
-template <typename T, int R, bool PF, int WAVES, int BXT>
+template <typename T, typename C, int R, bool PF, int WAVES, int BXT>
 hipError_t launch_group_t(const GroupBox* boxes, int nbox, unsigned nitems, int parity,
                           int persistent, int remap, unsigned workers, QueueState* q,
                           hipStream_t st)
 {
     if (persistent)
-        hipLaunchKernelGGL((k_step_group_persistent<T, R, PF, WAVES, BXT>), dim3(workers),
+        hipLaunchKernelGGL((k_step_group_persistent<T, C, R, PF, WAVES, BXT>), dim3(workers),
                            dim3(64 * WAVES), 0, st, boxes, nbox, parity, q);
     else
-        hipLaunchKernelGGL((k_step_group<T, R, PF, WAVES, BXT>), dim3(nitems), dim3(64 * WAVES), 0,
+        hipLaunchKernelGGL((k_step_group<T, C, R, PF, WAVES, BXT>), dim3(nitems), dim3(64 * WAVES), 0,
                            st, boxes, nbox, parity, remap);
     return hipGetLastError();
 }
 
-template <typename T>
+template <typename T, typename C>
 hipError_t launch_group_shape(const StepShape& s, const GroupBox* boxes, int nbox, unsigned nitems,
                               int parity, int persistent, unsigned workers, QueueState* q,
                               hipStream_t st)
 {
 #define LBM_GROUP(R, PF, WV, BXT) \
-    launch_group_t<T, R, PF, WV, BXT>(boxes, nbox, nitems, parity, persistent, s.xcd_remap, workers, q, st)
+    launch_group_t<T, C, R, PF, WV, BXT>(boxes, nbox, nitems, parity, persistent, s.xcd_remap, workers, q, st)
     if (s.tile_x == 0) {
         if (s.waves == 4) return LBM_GROUP(4, false, 4, 0);
         if (s.rows == 2) return LBM_GROUP(2, false, 8, 0);
-        if constexpr (sizeof(T) == 8) return s.rows == 4 ? LBM_GROUP(4, false, 8, 0) : hipErrorInvalidValue;
+        if constexpr (sizeof(C) == 8) return s.rows == 4 ? LBM_GROUP(4, false, 8, 0) : hipErrorInvalidValue;
         else return s.rows == 4 ? LBM_GROUP(4, false, 8, 0) : LBM_GROUP(8, false, 8, 0);
     }
     if (s.waves == 8) {
@@ -1330,14 +1330,15 @@ hipError_t launch_group_shape(const StepShape& s, const GroupBox* boxes, int nbo
 #undef LBM_GROUP
 }
 
-hipError_t launch_step_group(bool fp32, const StepShape& s, const GroupBox* boxes, int nbox,
+hipError_t launch_step_group(bool fp32, bool math64, const StepShape& s, const GroupBox* boxes, int nbox,
                              unsigned nitems, int parity, int persistent, unsigned workers,
                              QueueState* q, hipStream_t st)
 {
     if (!shape_supported(s)) return hipErrorInvalidValue;
     if (nbox <= 0 || nitems == 0) return hipSuccess;
-    return fp32 ? launch_group_shape<float>(s, boxes, nbox, nitems, parity, persistent, workers, q, st)
-                : launch_group_shape<double>(s, boxes, nbox, nitems, parity, persistent, workers, q, st);
+    if (!fp32) return launch_group_shape<double, double>(s, boxes, nbox, nitems, parity, persistent, workers, q, st);
+    return math64 ? launch_group_shape<float, double>(s, boxes, nbox, nitems, parity, persistent, workers, q, st)
+                  : launch_group_shape<float, float>(s, boxes, nbox, nitems, parity, persistent, workers, q, st);
 }
 
 hipError_t launch_init(bool fp32, const BoxDesc& b, const InitDesc& d, double* dn, double* dpsi,

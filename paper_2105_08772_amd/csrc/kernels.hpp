@@ -102,7 +102,7 @@ constexpr int OBS_BLOCKS = 512;
 hipError_t launch_step(bool fp32, bool math64, const BoxDesc& b, const StepShape& s, int sbuf,
                        const void* src, void* dst, hipStream_t st);
 // Multi-box step. nitems work items; persistent: grid of `workers` workgroups over the queues.
-hipError_t launch_step_group(bool fp32, const StepShape& s, const GroupBox* boxes, int nbox,
+hipError_t launch_step_group(bool fp32, bool math64, const StepShape& s, const GroupBox* boxes, int nbox,
                              unsigned nitems, int parity, int persistent, unsigned workers,
                              QueueState* q, hipStream_t st);
 hipError_t launch_init(bool fp32, const BoxDesc& b, const InitDesc& d, double* dn, double* dpsi,

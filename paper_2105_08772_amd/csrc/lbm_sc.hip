@@ -934,6 +934,7 @@ struct lbm_sc_group {
     lbm::QueueState* d_queue = nullptr;
     lbm_sc_group_launch launch;
     bool fp32 = false;
+    bool math64 = false;          // FP32 storage with FP64 arithmetic (shared by every box)
     unsigned nitems = 0;
     int64_t nodes = 0;
     int64_t bytes_per_step = 0;
@@ -1065,7 +1066,7 @@ hipError_t group_launch(lbm_sc_group* g, int parity)
 {
     const lbm::StepShape s = group_shape(g->launch);
     const unsigned workers = g->launch.workers ? (unsigned)g->launch.workers : 256u;
-    return lbm::launch_step_group(g->fp32, s, g->d_desc, (int)g->desc.size(), g->nitems, parity,
+    return lbm::launch_step_group(g->fp32, g->math64, s, g->d_desc, (int)g->desc.size(), g->nitems, parity,
                                   g->launch.persistent, workers, g->d_queue, g->stream);
 }
 
@@ -1120,21 +1121,19 @@ int lbm_sc_group_set(lbm_sc_group* g, lbm_sc* const* boxes, int32_t nbox)
         if (!boxes[i]) return fail(LBM_SC_EINVAL, "box " + std::to_string(i) + " is NULL");
         if (boxes[i]->stream != g->stream)
             return fail(LBM_SC_EINVAL, "box " + std::to_string(i) + " was not created on the group's stream");
-        if (boxes[i]->math64)
-            return fail(LBM_SC_EINVAL, "box " + std::to_string(i) +
-                                           ": groups take FP64 and FP32_SHIFTED boxes only");
-        if (boxes[i]->fp32 != boxes[0]->fp32)
+        if (boxes[i]->fp32 != boxes[0]->fp32 || boxes[i]->math64 != boxes[0]->math64)
             return fail(LBM_SC_EINVAL, "all boxes of a group must share one precision");
         for (int j = 0; j < i; ++j)
             if (boxes[j] == boxes[i]) return fail(LBM_SC_EINVAL, "a box appears twice");
         if (!shape_fits(group_shape(g->launch), boxes[i]->box))
             return fail(LBM_SC_EINVAL, "box " + std::to_string(i) +
                                            ": rows too long for the group's full-row tiles");
-        if (g->launch.tile_x == 0 && g->launch.rows == 8 && !boxes[i]->fp32)
-            return fail(LBM_SC_EINVAL, "full-row tiles with 8 nodes per thread need FP32 boxes");
+        if (g->launch.tile_x == 0 && g->launch.rows == 8 && (!boxes[i]->fp32 || boxes[i]->math64))
+            return fail(LBM_SC_EINVAL, "full-row tiles with 8 nodes per thread need FP32 arithmetic");
     }
     g->boxes.assign(boxes, boxes + nbox);
     g->fp32 = nbox > 0 && boxes[0]->fp32;
+    g->math64 = nbox > 0 && boxes[0]->math64;
     return group_rebuild(g);
 }
 
@@ -1200,8 +1199,8 @@ int lbm_sc_group_set_launch(lbm_sc_group* g, const lbm_sc_group_launch* l)
         if (!shape_fits(group_shape(*l), g->boxes[i]->box))
             return fail(LBM_SC_EINVAL, "box " + std::to_string(i) +
                                            ": rows too long for full-row tiles of this launch");
-        if (l->tile_x == 0 && l->rows == 8 && !g->boxes[i]->fp32)
-            return fail(LBM_SC_EINVAL, "full-row tiles with 8 nodes per thread need FP32 boxes");
+        if (l->tile_x == 0 && l->rows == 8 && (!g->boxes[i]->fp32 || g->boxes[i]->math64))
+            return fail(LBM_SC_EINVAL, "full-row tiles with 8 nodes per thread need FP32 arithmetic");
     }
     g->launch = *l;
     return group_rebuild(g);

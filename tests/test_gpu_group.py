@@ -69,7 +69,8 @@ LAUNCHES = [
 ]
 
 
-@pytest.mark.parametrize("prec", [lbm.LBM_SC_FP32_SHIFTED, lbm.LBM_SC_FP64])
+@pytest.mark.parametrize("prec", [lbm.LBM_SC_FP32_SHIFTED, lbm.LBM_SC_FP64,
+                                  lbm.LBM_SC_FP32_SHIFTED_MATH64])
 @pytest.mark.parametrize("li", range(len(LAUNCHES)))
 def test_group_equals_boxes_alone(prec, li):
     import torch
@@ -95,8 +96,8 @@ def test_group_equals_boxes_alone(prec, li):
 
 
 def test_group_full_row_tiles_8_nodes_per_thread():
-    """8 nodes per thread (FP32 only): bitwise equal to the boxes stepped alone; FP64 groups
-    reject the shape."""
+    """8 nodes per thread (FP32 arithmetic only): bitwise equal to the boxes stepped alone;
+    groups of FP64 boxes or of boxes with FP64 arithmetic reject the shape."""
     import torch
     s = torch.cuda.Stream()
     launch = dict(rows=8, z_chunk=8, xcd_remap=1, prefetch=0, persistent=1, workers=64,
@@ -113,16 +114,17 @@ def test_group_full_row_tiles_8_nodes_per_thread():
         assert np.array_equal(a, b), f"box {k} differs from the same box stepped alone"
     for b in boxes:
         b.close()
-    b64 = lbm.Box(box_configs(lbm.LBM_SC_FP64, s.cuda_stream)[0])
-    with lbm.Group(s.cuda_stream) as g:
-        g.set([b64])
-        with pytest.raises(lbm.LbmScError):
-            g.set_launch(**launch)
-        g.set([])
-        g.set_launch(**launch)
-        with pytest.raises(lbm.LbmScError):
+    for prec in (lbm.LBM_SC_FP64, lbm.LBM_SC_FP32_SHIFTED_MATH64):
+        b64 = lbm.Box(box_configs(prec, s.cuda_stream)[0])
+        with lbm.Group(s.cuda_stream) as g:
             g.set([b64])
-    b64.close()
+            with pytest.raises(lbm.LbmScError):
+                g.set_launch(**launch)
+            g.set([])
+            g.set_launch(**launch)
+            with pytest.raises(lbm.LbmScError):
+                g.set([b64])
+        b64.close()
 
 
 def test_group_resyncs_after_a_box_steps_alone_and_after_resets():
@@ -161,7 +163,7 @@ def test_group_rejects_mixed_precision_and_foreign_streams():
     d = lbm.Box(lbm.config(8, 8, 8, radius=2.0, prec=lbm.LBM_SC_FP32_SHIFTED_MATH64,
                            stream=s.cuda_stream))
     with lbm.Group(s.cuda_stream) as g:
-        for bad in ([a, b], [a, c], [a, a], [d]):
+        for bad in ([a, b], [a, c], [a, a], [b, d]):
             with pytest.raises(lbm.LbmScError) as e:
                 g.set(bad)
             assert e.value.code == lbm.LBM_SC_EINVAL
