@@ -136,7 +136,8 @@ def load():
     L.lbm_sc_device_bytes.restype = _i64
     for name in EXPORTS:
         if name not in ("lbm_sc_destroy", "lbm_sc_last_error", "lbm_sc_gc",
-                        "lbm_sc_group_destroy", "lbm_sc_device_bytes"):
+                        "lbm_sc_group_destroy", "lbm_sc_device_bytes",
+                        "lbm_sc_population_bytes"):
             getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L

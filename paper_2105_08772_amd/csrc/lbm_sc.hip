@@ -203,6 +203,28 @@ struct lbm_sc {
 
 namespace {
 
+// Row pitch of the stored populations: nx rounded up to whole 128-byte lines, so that every row
+// starts on a line and the step kernel writes complete lines (it fills the padding of the last
+// line of each row, which nothing reads).
+unsigned row_pitch(int nx, size_t elem)
+{
+    const unsigned per_line = (unsigned)(128 / elem);
+    return ((unsigned)nx + per_line - 1) / per_line * per_line;
+}
+
+// Population pitch: elements between the 19 population planes of one z-plane, the plane px * ny
+// rounded up to 64 elements and, for planes of 64 KiB or more, padded by about a 19th of the
+// plane (rounded down to 256 B), so that the 19 planes start at offsets spread evenly modulo the
+// plane size instead of coinciding modulo a large power of two (measured at 256^3 against a
+// 256-byte pad: FP32 step 0.489 -> 0.487 ms, FP64 0.962 -> 0.937 ms).
+unsigned long long population_pitch(unsigned long long pxy, size_t elem)
+{
+    unsigned long long s = (pxy + 63ull) / 64ull * 64ull;
+    const unsigned long long bytes = s * elem;
+    if (bytes >= (64ull << 10)) s += bytes / 19ull / 256ull * 256ull / elem;
+    return s;
+}
+
 int validate(const lbm_sc_config* c)
 {
     if (!c) return fail(LBM_SC_EINVAL, "cfg is NULL");
@@ -235,6 +257,12 @@ int validate(const lbm_sc_config* c)
         if (!(c->noise_amp >= 0.0)) return fail(LBM_SC_EINVAL, "noise_amp must be >= 0");
     }
     if (!(c->rho_ref >= 0.0) || !std::isfinite(c->rho_ref)) return fail(LBM_SC_EINVAL, "rho_ref must be >= 0");
+    // the step kernel addresses the 19 populations of one z-plane through one buffer resource of
+    // at most 4 GiB
+    const size_t elem = c->prec == LBM_SC_FP64 ? 8 : 4;
+    const unsigned long long pxy = (unsigned long long)row_pitch(c->nx, elem) * c->ny;
+    if (19ull * population_pitch(pxy, elem) * elem >= (1ull << 32))
+        return fail(LBM_SC_EINVAL, "box too large: the 19 populations of one z-plane must fit in 4 GiB");
     return LBM_SC_OK;
 }
 
@@ -436,28 +464,6 @@ void default_shape(lbm_sc* h)
     h->shape.z_chunk = best;
 }
 
-// Row pitch of the stored populations: nx rounded up to whole 128-byte lines, so that every row
-// starts on a line and the step kernel writes complete lines (it fills the padding of the last
-// line of each row, which nothing reads).
-unsigned row_pitch(int nx, size_t elem)
-{
-    const unsigned per_line = (unsigned)(128 / elem);
-    return ((unsigned)nx + per_line - 1) / per_line * per_line;
-}
-
-// Population pitch: elements between the 19 population planes of one z-plane, the plane px * ny
-// rounded up to 64 elements and, for planes of 64 KiB or more, padded by about a 19th of the
-// plane (rounded down to 256 B), so that the 19 planes start at offsets spread evenly modulo the
-// plane size instead of coinciding modulo a large power of two (measured at 256^3 against a
-// 256-byte pad: FP32 step 0.489 -> 0.487 ms, FP64 0.962 -> 0.937 ms).
-unsigned long long population_pitch(unsigned long long pxy, size_t elem)
-{
-    unsigned long long s = (pxy + 63ull) / 64ull * 64ull;
-    const unsigned long long bytes = s * elem;
-    if (bytes >= (64ull << 10)) s += bytes / 19ull / 256ull * 256ull / elem;
-    return s;
-}
-
 struct Sizes {
     size_t popbytes, n8, n24, parts, small, prof;
     size_t total() const { return 2 * popbytes + 2 * n8 + 2 * n24 + parts + small + prof; }
@@ -592,15 +598,8 @@ int create_box(const lbm_sc_config* cfg, void* buf_a, void* buf_b, size_t buf_by
     b.n = b.nxy * (unsigned)cfg->nz;
     b.px = row_pitch(cfg->nx, h->elem);
     const unsigned long long pxy = (unsigned long long)b.px * (unsigned)cfg->ny;
-    b.pxy = (unsigned)pxy;   // < 2^32 whenever the plane check below passes
-    const unsigned long long pp = population_pitch(pxy, h->elem);
-    b.pp = (unsigned)pp;
-    // the step kernel addresses the 19 populations of one z-plane through one buffer resource of
-    // at most 4 GiB
-    if ((unsigned long long)19 * pp * h->elem >= (1ull << 32)) {
-        release(h);
-        return fail(LBM_SC_EINVAL, "box too large: the 19 populations of one z-plane must fit in 4 GiB");
-    }
+    b.pxy = (unsigned)pxy;   // < 2^32: validate bounds the plane
+    b.pp = (unsigned)population_pitch(pxy, h->elem);   // 19 * pp * elem < 2^32 (validate)
     b.psi = cfg->psi;
     b.G = h->G;
     b.tau = cfg->tau;

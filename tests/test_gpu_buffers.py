@@ -76,19 +76,25 @@ def test_bad_caller_buffers_are_rejected():
     cfg = cfgs(s.cuda_stream)[0]
     need = lbm.lbm_sc_population_bytes(cfg)
     a, b = torch_buffers(torch, cfg, extra=512)
-    host = torch.empty(need, dtype=torch.uint8)
+    # host buffers on a 256-byte boundary, so that they fail the memory-type check, not alignment
+    host = torch.empty(need + 256, dtype=torch.uint8)
+    pinned = torch.empty(need + 256, dtype=torch.uint8, pin_memory=True)
+    host_p = (host.data_ptr() + 255) // 256 * 256
+    pinned_p = (pinned.data_ptr() + 255) // 256 * 256
     bad = [
-        (a.data_ptr(), b.data_ptr(), need - 256, "too few bytes"),
-        (a.data_ptr() + 4, b.data_ptr(), need, "misaligned"),
-        (a.data_ptr(), a.data_ptr() + 256, need, "overlapping"),
-        (a.data_ptr(), a.data_ptr(), need, "the same buffer twice"),
-        (host.data_ptr(), b.data_ptr(), need, "host memory"),
+        (a.data_ptr(), b.data_ptr(), need - 256, "too few bytes", "at least"),
+        (a.data_ptr() + 4, b.data_ptr(), need, "misaligned", "aligned"),
+        (a.data_ptr(), a.data_ptr() + 256, need, "overlapping", "overlap"),
+        (a.data_ptr(), a.data_ptr(), need, "the same buffer twice", "overlap"),
+        (host_p, b.data_ptr(), need, "pageable host memory", "device memory"),
+        (a.data_ptr(), pinned_p, need, "pinned host memory", "device memory"),
     ]
-    for pa, pb, n, why in bad:
+    for pa, pb, n, why, msg in bad:
         with pytest.raises(lbm.LbmScError) as e:
             lbm.lbm_sc_create_with_buffers(cfg, pa, pb, n)
         assert e.value.code == lbm.LBM_SC_EINVAL, why
         say(f"{why}: {lbm.lbm_sc_last_error()}")
+        assert msg in lbm.lbm_sc_last_error(), why
     # the good pair still works afterwards
     h = lbm.lbm_sc_create_with_buffers(cfg, a.data_ptr(), b.data_ptr(), need)
     lbm.lbm_sc_step(h, 2)

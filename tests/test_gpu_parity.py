@@ -544,6 +544,41 @@ def test_box_beyond_32bit_offsets_sampled(L, prec, tol):
     assert abs(o1["mass"] - o0["mass"]) <= mtol * o0["mass"]
 
 
+def test_largest_z_plane_sampled():
+    """The largest z-plane one buffer resource can address: 7296 x 7358 nodes in FP32 (the 19
+    population planes of a z-plane, pitch padding included, take 4294717440 bytes, just under
+    4 GiB; a plane one row larger is rejected before anything is allocated). One step of a noisy flat box checked on sampled nodes - the far corner
+    of the plane included - against the oracle's single-node collision."""
+    say("largest z-plane (7296 x 7358 x 2, FP32): sampled one-step parity")
+    nx, ny, nz = 7296, 7358, 2
+    cfg = lbm.config(nx, ny, nz, psi=0, geom=lbm.LBM_SC_SLAB, prec=lbm.LBM_SC_FP32_SHIFTED,
+                     g_over_gc=1.3, slab_thickness=3000.0, width=2.0, slab_axis=0,
+                     noise_amp=1e-6, seed=17)
+    rng = np.random.default_rng(7296)
+    with lbm.Box(cfg) as b:
+        G = b.info()["G"]
+        f0 = b.get()
+        b.step(1)
+        f1 = b.get()
+    pts = [(int(rng.integers(0, nx)), int(rng.integers(0, ny)), int(rng.integers(0, nz)))
+           for _ in range(30)]
+    pts += [(nx - 1, ny - 1, nz - 1), (0, ny - 1, 0), (nx - 1, 0, 1), (nx // 2 + 1500, 17, 1)]
+    scale = np.abs(f0).max()
+    worst = 0.0
+    for (x, y, z) in pts:
+        fs = core.collide_at(f0, G, 1.0, 0, x, y, z)
+        for i in range(19):
+            d = ((x + XI[i, 0]) % nx, (y + XI[i, 1]) % ny, (z + XI[i, 2]) % nz)
+            worst = max(worst, abs(f1[i, d[2], d[1], d[0]] - fs[i]) / scale)
+    del f0, f1
+    say("worst sampled error / max|f| =", worst)
+    assert worst <= 1e-6
+    with pytest.raises(lbm.LbmScError):
+        lbm.lbm_sc_create(lbm.config(nx, ny + 1, nz, psi=0, geom=lbm.LBM_SC_SLAB,
+                                     prec=lbm.LBM_SC_FP32_SHIFTED, g_over_gc=1.3,
+                                     slab_thickness=3000.0, width=2.0, slab_axis=0))
+
+
 def test_full_size_batched_workload_sampled():
     """The 64-box batched workload (seed 2105, L ~ U{48..160}, FP32-shifted) in one group with
     the full-row tiles the benchmark's tuner picks (4 nodes per thread, z chunks of 8, hipGraph

@@ -93,6 +93,27 @@ def test_population_bytes_is_one_buffer_of_the_device_bytes():
         lbm.lbm_sc_population_bytes(lbm.config(0, 4, 4))
 
 
+def test_sizes_of_the_largest_z_plane():
+    # FP32, px = 7296: a 7296 x 7358 plane is the largest whose 19 populations (pitch rounded to
+    # 64 elements plus a pad of a 19th of the plane rounded down to 256 B) stay under 4 GiB; the
+    # byte counts exceed 2^32 and must come back whole, and one row more is invalid everywhere
+    kw = dict(geom=lbm.LBM_SC_SLAB, prec=lbm.LBM_SC_FP32_SHIFTED, slab_thickness=3000.0,
+              width=2.0)
+    def pitch(ny):
+        s = (7296 * ny + 63) // 64 * 64
+        return s + s * 4 // 19 // 256 * 256 // 4
+    pp = pitch(7358)
+    assert 19 * pp * 4 < 2**32 <= 19 * pitch(7359) * 4
+    cfg = lbm.config(7296, 7358, 2, **kw)
+    assert lbm.lbm_sc_population_bytes(cfg) == 2 * 19 * pp * 4
+    assert lbm.lbm_sc_device_bytes(cfg) > 2 * lbm.lbm_sc_population_bytes(cfg) > 2**33
+    big = lbm.config(7296, 7359, 2, **kw)
+    for f in (lbm.lbm_sc_population_bytes, lbm.lbm_sc_device_bytes, lbm.lbm_sc_create):
+        with pytest.raises(lbm.LbmScError) as e:
+            f(big)
+        assert e.value.code == lbm.LBM_SC_EINVAL and "4 GiB" in lbm.lbm_sc_last_error()
+
+
 def test_create_with_buffers_rejects_missing_buffers_before_any_device_work():
     cfg = lbm.config(8, 8, 8, radius=3.0, width=2.0)
     for a, b in ((0, 0), (0, 4096), (4096, 0)):
