@@ -122,6 +122,48 @@ def test_create_with_buffers_rejects_missing_buffers_before_any_device_work():
         assert e.value.code == lbm.LBM_SC_EINVAL
 
 
+def test_ctypes_signatures_match_the_header():
+    """Every prototype of include/lbm_sc.h against the argtypes and restype the Python binding
+    gives the loaded library (a 64-bit return read as int truncates sizes of 2 GiB and more)."""
+    import ctypes
+    P = ctypes.POINTER
+    structs = {"lbm_sc_config": lbm.LbmScConfig, "lbm_sc_obs": lbm.LbmScObs,
+               "lbm_sc_info": lbm.LbmScInfo, "lbm_sc_launch": lbm.LbmScLaunch,
+               "lbm_sc_group_launch": lbm.LbmScGroupLaunch}
+    scalars = {"int": ctypes.c_int, "int32_t": ctypes.c_int32, "int64_t": ctypes.c_int64,
+               "size_t": ctypes.c_size_t, "double": ctypes.c_double, "void": None}
+
+    def ctype(decl, is_return):
+        t = re.sub(r"\bconst\b", "", decl).strip()
+        stars = t.count("*")
+        base = t.replace("*", " ").split()[0]
+        if stars == 0:
+            return scalars[base]
+        if stars == 1 and base == "char" and is_return:
+            return ctypes.c_char_p
+        if stars == 1 and base in structs:
+            return P(structs[base])
+        if stars == 1 and base in ("double", "int32_t", "int64_t"):
+            return P(scalars[base])
+        if stars == 1:           # opaque handles and raw device or host addresses
+            return ctypes.c_void_p
+        assert stars == 2, decl  # handle out-parameters and arrays of handles
+        return P(ctypes.c_void_p)
+
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    protos = re.findall(r"([\w\s\*]+?)\b(lbm_sc_\w+)\s*\(([^)]*)\)\s*;", text)
+    L = lbm.load()
+    assert {name for _, name, _ in protos} == set(lbm.EXPORTS)
+    for ret, name, args in protos:
+        fn = getattr(L, name)
+        assert fn.restype is ctype(ret, True), name
+        # every parameter is named: drop the trailing name, keep the type
+        want = [] if args.strip() in ("", "void") else [
+            ctype(re.match(r"(.*?)\s*\b\w+$", a.strip()).group(1), False) for a in args.split(",")]
+        assert list(fn.argtypes or []) == want, name
+
+
 def test_ctypes_structs_match_the_c_layout(tmp_path):
     """Compile a probe against include/lbm_sc.h and compare every field offset and struct size
     with the ctypes mirrors of the Python binding."""
