@@ -14,7 +14,7 @@
  *   - the two pseudopotentials of Sec. 4: exp(-1/n) and 1-exp(-n);
  *   - the tanh initial profile of Sec. 4.
  *
- * Readings taken where the paper is silent or garbled (each one is listed in the design doc):
+ * Readings taken where the paper is silent or garbled:
  *   - the quadratic term of the equilibrium carries the usual factor 1/2, (xi.u)^2/(2 c_s^4);
  *     without it the second moment is not n c_s^2 delta + n u u;
  *   - D3Q19 weights are the standard 1/3, 1/18, 1/36 (the paper cites textbooks for them);
