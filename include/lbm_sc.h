@@ -132,8 +132,10 @@ int lbm_sc_create(const lbm_sc_config* cfg, lbm_sc** out);
  * lbm_sc_population_bytes(cfg) bytes (`bytes`) inside its allocation. The library uses them in
  * place, never frees them, and does not keep them beyond lbm_sc_destroy; the caller keeps them
  * alive until then. The observation scratch is still allocated by the library (device_bytes of
- * lbm_sc_get_info counts only that). LBM_SC_EINVAL, with nothing allocated, if a buffer is NULL,
- * misaligned, too small, not device memory of the current device, or the two overlap. */
+ * lbm_sc_get_info counts only that). Work of other streams on a or b must have finished before
+ * this call (the initial state is written on the box's stream, unordered with other streams).
+ * LBM_SC_EINVAL, with nothing allocated, if a buffer is NULL, misaligned, too small, not device
+ * memory of the current device, or the two overlap. */
 int lbm_sc_create_with_buffers(const lbm_sc_config* cfg, void* a, void* b, size_t bytes,
                                lbm_sc** out);
 

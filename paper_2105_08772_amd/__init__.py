@@ -283,8 +283,15 @@ class Box:
         if buffers is None:
             self.h = lbm_sc_create(cfg)
         else:
+            import torch
             a, b = buffers
+            for t in (a, b):
+                if not (isinstance(t, torch.Tensor) and t.is_cuda and t.is_contiguous()):
+                    raise ValueError("buffers must be two contiguous device tensors")
             nbytes = min(a.numel() * a.element_size(), b.numel() * b.element_size())
+            # work already queued on torch's stream for this memory (a caching allocator hands
+            # out blocks whose last use may still be running) ends before the box's stream uses it
+            torch.cuda.current_stream(a.device).synchronize()
             self.h = lbm_sc_create_with_buffers(cfg, a.data_ptr(), b.data_ptr(), nbytes)
 
     def step(self, n):

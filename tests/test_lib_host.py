@@ -122,6 +122,15 @@ def test_create_with_buffers_rejects_missing_buffers_before_any_device_work():
         assert e.value.code == lbm.LBM_SC_EINVAL
 
 
+def test_box_buffers_must_be_contiguous_device_tensors():
+    import torch
+    cfg = lbm.config(8, 8, 8, radius=3.0, width=2.0)
+    host = torch.empty(1 << 20, dtype=torch.uint8)
+    for bufs in ((host, host), (np.empty(16), np.empty(16))):
+        with pytest.raises(ValueError):
+            lbm.Box(cfg, buffers=bufs)
+
+
 def test_ctypes_signatures_match_the_header():
     """Every prototype of include/lbm_sc.h against the argtypes and restype the Python binding
     gives the loaded library (a 64-bit return read as int truncates sizes of 2 GiB and more)."""
