@@ -91,6 +91,7 @@ class GpuBackend:
         self.launch = None
         self.single = single
         self.active = []
+        self.fallen_back = None    # the launch shape replaced by FALLBACK, while it is replaced
 
     def config(self, r):
         return self._config(r.L, psi=r.psi, geom=self._bubble if r.bubble else self._droplet,
@@ -115,6 +116,11 @@ class GpuBackend:
         if self.single:
             self.active = list(boxes)
             return
+        if self.fallen_back is not None:
+            # back to the chosen shape: the box that needed x-y tiles may have left
+            self.group.set([])
+            self.group.set_launch(**self.fallen_back)
+            self.fallen_back = None
         try:
             self.group.set(boxes)
         except self._error:
@@ -125,8 +131,10 @@ class GpuBackend:
             self.group.set([])
             self.group.set_launch(**self.FALLBACK)
             self.group.set(boxes)
+            self.fallen_back = launch
 
     def set_launch(self, **kw):
+        self.fallen_back = None
         self.group.set_launch(**kw)
 
     def step(self, n):

@@ -128,7 +128,8 @@ def test_memory_limited_admission_gives_the_same_results(mixed):
 
 def test_backend_falls_back_to_xy_tiles_for_long_rows():
     """A group on full-row tiles cannot take a box whose rows are too long for the workgroup;
-    the backend then switches the group to x-y tiles, and stepping still equals the boxes alone."""
+    the backend then switches the group to x-y tiles, stepping still equals the boxes alone, and
+    the group returns to the full-row tiles once that box has left."""
     import paper_2105_08772_amd as lbm
     be = serve.GpuBackend()
     be.set_launch(rows=4, waves=8, tile_x=0, z_chunk=8, prefetch=0, persistent=0, workers=0,
@@ -139,7 +140,8 @@ def test_backend_falls_back_to_xy_tiles_for_long_rows():
                      stream=be.stream.cuda_stream)
     wide = lbm.Box(cfg)
     be.set_active([small])
-    assert be.group.launch()["tile_x"] == 0
+    want = be.group.launch()
+    assert want["tile_x"] == 0
     be.set_active([small, wide])
     assert be.group.launch()["tile_x"] == 64
     f_small, f_wide = small.get(), wide.get()
@@ -149,6 +151,15 @@ def test_backend_falls_back_to_xy_tiles_for_long_rows():
         b.set(f)
         b.step(4)
     assert np.array_equal(got[0], small.get()) and np.array_equal(got[1], wide.get())
+    be.set_active([small])
+    assert be.group.launch() == want
+    f_small = small.get()
+    be.step(2)
+    got = small.get()
+    small.set(f_small)
+    small.set_step(4)        # the state was 4 steps old: restores the dither's step count
+    small.step(2)
+    assert np.array_equal(got, small.get())
     be.group.set([])
     small.close()
     wide.close()

@@ -197,3 +197,38 @@ def test_journal_has_one_json_line_per_request():
     assert by[0]["time_to_equilibrium_s"] > 0
     assert by[1]["status"] == "cancelled" and by[2]["status"] == "rejected"
     assert by[3]["status"] == "unstable" and by[3]["history"][-1][0] == 4096
+
+
+def test_backend_leaves_the_xy_tile_fallback_when_the_wide_box_leaves():
+    """GpuBackend.set_active on a stand-in group: a box too wide for the full-row tiles switches
+    the group to x-y tiles; once it has left, the chosen full-row shape comes back."""
+    from paper_2105_08772_amd import LbmScError
+
+    class FakeGroup:
+        def __init__(self):
+            self.shape = dict(tile_x=0, rows=4, waves=8, z_chunk=8, prefetch=0)
+            self.boxes = []
+
+        def set(self, boxes):
+            if self.shape["tile_x"] == 0 and "wide" in boxes:
+                raise LbmScError(-1, "rows too long for full-row tiles")
+            self.boxes = list(boxes)
+
+        def set_launch(self, **kw):
+            assert not self.boxes
+            self.shape.update(kw)
+
+        def launch(self):
+            return dict(self.shape)
+
+    be = object.__new__(serve.GpuBackend)
+    be.single, be.group, be.fallen_back, be._error = False, FakeGroup(), None, LbmScError
+    chosen = be.group.launch()
+    be.set_active(["small"])
+    assert be.group.launch() == chosen
+    be.set_active(["small", "wide"])
+    assert be.group.launch()["tile_x"] == 64 and be.group.boxes == ["small", "wide"]
+    be.set_active(["small", "wide", "other"])
+    assert be.group.launch()["tile_x"] == 64
+    be.set_active(["small"])
+    assert be.group.launch() == chosen and be.group.boxes == ["small"]
