@@ -146,8 +146,11 @@ int64_t lbm_sc_population_bytes(const lbm_sc_config* cfg);
 /* Enqueue nsteps (>= 0) time steps of Eq. (lbm) on the handle's stream: fused pull streaming,
  * density and psi, Shan-Chen force, Guo equilibrium velocity, BGK collision with the Guo term.
  * Runs of graph_steps steps (lbm_sc_launch) are replayed from a hipGraph the handle captures on
- * first use (plain launches while the caller is capturing the stream). Returns after enqueueing
- * (asynchronous); LBM_SC_EDEVICE if a launch fails. */
+ * first use. While the caller is capturing the stream the call records plain launches into the
+ * caller's graph: nsteps must then be even (LBM_SC_EINVAL otherwise, nothing recorded), every
+ * replay advances the box by nsteps, and the host step counter advances once, at the capture
+ * (lbm_sc_set_step corrects it after replays). Returns after enqueueing (asynchronous);
+ * LBM_SC_EDEVICE if a launch fails. */
 int lbm_sc_step(lbm_sc* h, int64_t nsteps);
 
 /* Wait until all work enqueued on the handle's stream has finished. */
@@ -247,7 +250,8 @@ int lbm_sc_group_set(lbm_sc_group* g, lbm_sc* const* boxes, int32_t nbox);
 
 /* Enqueue nsteps (>= 0) time steps of every box of the group: one multi-box launch per step,
  * replayed from a captured hipGraph in chunks of graph_steps. Each box's step counter advances by
- * nsteps. Asynchronous. */
+ * nsteps. Asynchronous. LBM_SC_EINVAL, with nothing enqueued, while the group's stream is being
+ * captured by the caller. */
 int lbm_sc_group_step(lbm_sc_group* g, int64_t nsteps);
 
 /* Set / read the group's launch shape (the work list is rebuilt; results are unchanged). */

@@ -732,7 +732,11 @@ int lbm_sc_step(lbm_sc* h, int64_t nsteps)
     const int K = h->graph_steps;
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     HIP_TRY(hipStreamIsCapturing(h->stream, &cs));
-    // inside a caller's capture the launches are recorded into the caller's graph instead
+    // inside a caller's capture the launches are recorded into the caller's graph instead; each
+    // recorded launch has fixed source and destination buffers, so only an even count leaves the
+    // state where a replay expects it (an odd one would recompute the same step on every replay)
+    if (cs != hipStreamCaptureStatusNone && (nsteps & 1))
+        return fail(LBM_SC_EINVAL, "inside a stream capture nsteps must be even");
     const bool use_graph = K > 0 && nsteps >= K && cs == hipStreamCaptureStatusNone;
     if (use_graph && (!h->graph || h->graph_len != K)) {
         // K (even) launches alternating the two buffers, starting from the current one
@@ -1140,6 +1144,10 @@ int lbm_sc_group_step(lbm_sc_group* g, int64_t nsteps)
 {
     if (!g) return fail(LBM_SC_EINVAL, "group is NULL");
     if (nsteps < 0) return fail(LBM_SC_EINVAL, "nsteps must be >= 0");
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    HIP_TRY(hipStreamIsCapturing(g->stream, &cs));
+    if (cs != hipStreamCaptureStatusNone)
+        return fail(LBM_SC_EINVAL, "lbm_sc_group_step is not for use inside a stream capture");
     if (g->boxes.empty() || nsteps == 0) return LBM_SC_OK;
     // a box stepped alone since the last call is out of phase with the work list: rebuild
     for (size_t i = 0; i < g->boxes.size(); ++i)

@@ -207,7 +207,9 @@ def test_graph_replay_equals_plain_launches():
 def test_steps_recorded_into_a_caller_graph():
     """lbm_sc_step inside a caller's stream capture records plain launches into the caller's
     graph; replaying it (several times, with eager work and synchronisation between the
-    replays) matches a box stepped eagerly from the same state after every replay."""
+    replays) matches a box stepped eagerly from the same state after every replay. An odd step
+    count is refused inside the capture (its replays would repeat one step), and so is a group
+    step; the host step counter, advanced once at the capture, is set right with set_step."""
     import torch
     say("steps inside a caller's graph capture")
     s = torch.cuda.Stream()
@@ -220,14 +222,27 @@ def test_steps_recorded_into_a_caller_graph():
         b.set(f)
         ref.set(f)
         torch.cuda.synchronize()
+        grp = lbm.Group(s.cuda_stream)
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g, stream=s):
+            with pytest.raises(lbm.LbmScError) as odd:
+                b.step(3)
+            with pytest.raises(lbm.LbmScError) as in_group:
+                grp.step(2)
             b.step(4)
+        assert odd.value.code == lbm.LBM_SC_EINVAL and in_group.value.code == lbm.LBM_SC_EINVAL
+        grp.close()
         for _ in range(3):
             g.replay()
             torch.cuda.synchronize()
             ref.step(4)
             assert np.array_equal(b.get(), ref.get())
+        assert b.observables(profile=False)[0]["step"] == 4
+        b.set_step(12)
+        b.step(2)
+        ref.step(2)
+        assert np.array_equal(b.get(), ref.get())
+        assert b.observables(profile=False)[0]["step"] == ref.observables(profile=False)[0]["step"] == 14
 
 
 @pytest.mark.parametrize("dims", SHAPES + [(100, 37, 9), (129, 5, 4)])
