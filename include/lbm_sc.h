@@ -153,7 +153,9 @@ int64_t lbm_sc_population_bytes(const lbm_sc_config* cfg);
  * LBM_SC_EDEVICE if a launch fails. */
 int lbm_sc_step(lbm_sc* h, int64_t nsteps);
 
-/* Wait until all work enqueued on the handle's stream has finished. */
+/* Wait until all work enqueued on the handle's stream has finished. This call, and every other
+ * call documented as synchronising or uploading, returns LBM_SC_EINVAL without touching the
+ * stream while the caller is capturing it (a capture can hold neither). */
 int lbm_sc_sync(lbm_sc* h);
 
 /* Compute the observables of the current state in FP64 (listed in lbm_sc_obs) and synchronise.
@@ -161,12 +163,12 @@ int lbm_sc_sync(lbm_sc* h);
  * y = floor(ny/2), z = floor(nz/2), x = 0..nx-1) or the box length along slab_axis (slab: averages
  * over planes normal to the axis); it receives [n, P^xx, P^yy, P^zz] each of length L. The
  * velocity field of this call becomes the reference of the next call's du_l1/du_max. Returns
- * LBM_SC_EUNSTABLE (with *out filled) if out->finite is 0. */
+ * LBM_SC_EUNSTABLE (with *out filled) if out->finite is 0. Not for use inside a stream capture. */
 int lbm_sc_observables(lbm_sc* h, lbm_sc_obs* out, double* prof, size_t prof_len);
 
 /* Copy the current pre-collision populations f_i(x, t) to the host array f (canonical layout,
  * len must be 19*nx*ny*nz). Shifted FP32 states are widened to FP64 and the shift w_i rho_ref
- * added back. Synchronises. */
+ * added back. Synchronises. Not for use inside a stream capture. */
 int lbm_sc_get_populations(lbm_sc* h, double* f, size_t len);
 
 /* Replace the state by the host array f (canonical layout, pre-collision populations at the
@@ -245,7 +247,8 @@ int lbm_sc_group_create(void* stream, lbm_sc_group** out);
 
 /* Set the boxes stepped by the group (nbox >= 0; an empty group steps nothing). Validates that
  * every box has the group's stream and that all share one precision (LBM_SC_EINVAL otherwise),
- * builds the work list for the current launch shape and uploads it (stream-ordered). */
+ * builds the work list for the current launch shape and uploads it (stream-ordered). Not for use
+ * inside a stream capture. */
 int lbm_sc_group_set(lbm_sc_group* g, lbm_sc* const* boxes, int32_t nbox);
 
 /* Enqueue nsteps (>= 0) time steps of every box of the group: one multi-box launch per step,
@@ -254,7 +257,8 @@ int lbm_sc_group_set(lbm_sc_group* g, lbm_sc* const* boxes, int32_t nbox);
  * captured by the caller. */
 int lbm_sc_group_step(lbm_sc_group* g, int64_t nsteps);
 
-/* Set / read the group's launch shape (the work list is rebuilt; results are unchanged). */
+/* Set / read the group's launch shape (the work list is rebuilt; results are unchanged). Setting
+ * it is not for use inside a stream capture. */
 int lbm_sc_group_set_launch(lbm_sc_group* g, const lbm_sc_group_launch* launch);
 int lbm_sc_group_get_launch(lbm_sc_group* g, lbm_sc_group_launch* out);
 

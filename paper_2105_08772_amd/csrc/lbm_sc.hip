@@ -273,6 +273,18 @@ void drop_box_graph(lbm_sc* h)
     h->graph_len = 0;
 }
 
+// LBM_SC_EINVAL while the caller is capturing the stream: the calls guarded by this wait for the
+// stream or copy through host memory, neither of which a capture can hold (inside a capture they
+// would fail and end the caller's capture)
+int refuse_in_capture(hipStream_t s, const char* what)
+{
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    HIP_TRY(hipStreamIsCapturing(s, &cs));
+    if (cs != hipStreamCaptureStatusNone)
+        return fail(LBM_SC_EINVAL, std::string(what) + " is not for use inside a stream capture");
+    return LBM_SC_OK;
+}
+
 void release(lbm_sc* h)
 {
     if (!h) return;
@@ -781,6 +793,7 @@ int lbm_sc_step(lbm_sc* h, int64_t nsteps)
 int lbm_sc_sync(lbm_sc* h)
 {
     if (!h) return fail(LBM_SC_EINVAL, "handle is NULL");
+    if (int rc = refuse_in_capture(h->stream, "lbm_sc_sync")) return rc;
     HIP_TRY(hipStreamSynchronize(h->stream));
     return LBM_SC_OK;
 }
@@ -790,6 +803,7 @@ int lbm_sc_observables(lbm_sc* h, lbm_sc_obs* out, double* prof, size_t prof_len
     if (!h || !out) return fail(LBM_SC_EINVAL, "handle or out is NULL");
     if (prof && prof_len != 4 * (size_t)profile_len(h))
         return fail(LBM_SC_EINVAL, "prof_len must be 4 * " + std::to_string(profile_len(h)));
+    if (int rc = refuse_in_capture(h->stream, "lbm_sc_observables")) return rc;
     int rc = observe(h, out, prof);
     if (rc) return rc;
     if (!out->finite) return fail(LBM_SC_EUNSTABLE, "non-finite value or n <= 0 in the state");
@@ -801,6 +815,7 @@ int lbm_sc_get_populations(lbm_sc* h, double* f, size_t len)
     if (!h || !f) return fail(LBM_SC_EINVAL, "handle or f is NULL");
     const size_t N = h->box.n;
     if (len != 19 * N) return fail(LBM_SC_EINVAL, "len must be 19*nx*ny*nz");
+    if (int rc = refuse_in_capture(h->stream, "lbm_sc_get_populations")) return rc;
     for (int i = 0; i < 19; ++i) {
         HIP_TRY(lbm::launch_get(h->fp32, h->box, i, h->pop[h->cur], h->d_n, h->stream));
         HIP_TRY(hipMemcpyAsync(f + (size_t)i * N, h->d_n, N * 8, hipMemcpyDeviceToHost, h->stream));
@@ -814,6 +829,7 @@ int lbm_sc_set_populations(lbm_sc* h, const double* f, size_t len)
     if (!h || !f) return fail(LBM_SC_EINVAL, "handle or f is NULL");
     const size_t N = h->box.n;
     if (len != 19 * N) return fail(LBM_SC_EINVAL, "len must be 19*nx*ny*nz");
+    if (int rc = refuse_in_capture(h->stream, "lbm_sc_set_populations")) return rc;
     // a set state starts again at step 0 (the dither sequence restarts with it)
     HIP_TRY(hipMemsetAsync(h->box.tick, 0, 2 * sizeof(unsigned), h->stream));
     for (int i = 0; i < 19; ++i) {
@@ -834,6 +850,7 @@ int lbm_sc_set_step(lbm_sc* h, int64_t step)
 {
     if (!h) return fail(LBM_SC_EINVAL, "handle is NULL");
     if (step < 0) return fail(LBM_SC_EINVAL, "step must be >= 0");
+    if (int rc = refuse_in_capture(h->stream, "lbm_sc_set_step")) return rc;
     // the dither's step count of the current buffer (kept modulo 2^32) follows the step counter
     const unsigned t = (unsigned)(uint64_t)step;
     HIP_TRY(hipMemcpyAsync(h->box.tick + h->cur, &t, sizeof(t), hipMemcpyHostToDevice, h->stream));
@@ -1120,6 +1137,7 @@ int lbm_sc_group_set(lbm_sc_group* g, lbm_sc* const* boxes, int32_t nbox)
 {
     if (!g) return fail(LBM_SC_EINVAL, "group is NULL");
     if (nbox < 0 || (nbox > 0 && !boxes)) return fail(LBM_SC_EINVAL, "bad box list");
+    if (int rc = refuse_in_capture(g->stream, "lbm_sc_group_set")) return rc;
     for (int i = 0; i < nbox; ++i) {
         if (!boxes[i]) return fail(LBM_SC_EINVAL, "box " + std::to_string(i) + " is NULL");
         if (boxes[i]->stream != g->stream)
@@ -1144,10 +1162,7 @@ int lbm_sc_group_step(lbm_sc_group* g, int64_t nsteps)
 {
     if (!g) return fail(LBM_SC_EINVAL, "group is NULL");
     if (nsteps < 0) return fail(LBM_SC_EINVAL, "nsteps must be >= 0");
-    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-    HIP_TRY(hipStreamIsCapturing(g->stream, &cs));
-    if (cs != hipStreamCaptureStatusNone)
-        return fail(LBM_SC_EINVAL, "lbm_sc_group_step is not for use inside a stream capture");
+    if (int rc = refuse_in_capture(g->stream, "lbm_sc_group_step")) return rc;
     if (g->boxes.empty() || nsteps == 0) return LBM_SC_OK;
     // a box stepped alone since the last call is out of phase with the work list: rebuild
     for (size_t i = 0; i < g->boxes.size(); ++i)
@@ -1202,6 +1217,7 @@ int lbm_sc_group_set_launch(lbm_sc_group* g, const lbm_sc_group_launch* l)
     if (!g || !l) return fail(LBM_SC_EINVAL, "group or launch is NULL");
     int rc = check_group_launch(l);
     if (rc) return rc;
+    if ((rc = refuse_in_capture(g->stream, "lbm_sc_group_set_launch"))) return rc;
     for (size_t i = 0; i < g->boxes.size(); ++i) {
         if (!shape_fits(group_shape(*l), g->boxes[i]->box))
             return fail(LBM_SC_EINVAL, "box " + std::to_string(i) +

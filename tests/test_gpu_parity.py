@@ -229,8 +229,16 @@ def test_steps_recorded_into_a_caller_graph():
                 b.step(3)
             with pytest.raises(lbm.LbmScError) as in_group:
                 grp.step(2)
+            refused = []   # calls that wait for the stream or go through host memory
+            for call in (b.sync, b.get, lambda: b.set(f), lambda: b.set_step(1),
+                         lambda: b.observables(profile=False), lambda: grp.set([b]),
+                         lambda: grp.set_launch(rows=2)):
+                with pytest.raises(lbm.LbmScError) as e:
+                    call()
+                refused.append(e.value.code)
             b.step(4)
         assert odd.value.code == lbm.LBM_SC_EINVAL and in_group.value.code == lbm.LBM_SC_EINVAL
+        assert refused == [lbm.LBM_SC_EINVAL] * 7
         grp.close()
         for _ in range(3):
             g.replay()
