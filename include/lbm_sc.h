@@ -266,7 +266,8 @@ int lbm_sc_group_get_launch(lbm_sc_group* g, lbm_sc_group_launch* out);
 int lbm_sc_group_info(lbm_sc_group* g, int32_t* nbox, int64_t* items, int64_t* nodes,
                       int64_t* bytes_per_step);
 
-/* Release the group (after waiting for its stream); the boxes are untouched. NULL is ignored. */
+/* Release the group (after waiting for its stream); the boxes are untouched. NULL is ignored.
+ * Not for use inside a stream capture (it waits and frees device memory). */
 void lbm_sc_group_destroy(lbm_sc_group* g);
 
 /* Measurement helper, not part of the method: copy `bytes` (a multiple of 16; src and dst
@@ -278,7 +279,9 @@ int lbm_sc_stream_copy(const void* src, void* dst, size_t bytes, void* stream);
 /* Describe the handle (coupling, densities, sizes, launch shape). */
 int lbm_sc_get_info(lbm_sc* h, lbm_sc_info* out);
 
-/* Release everything the handle owns (after waiting for its stream). NULL is ignored. */
+/* Release everything the handle owns (after waiting for its stream). NULL is ignored. Not for
+ * use inside a stream capture (it waits and frees device memory), nor while a graph that the
+ * caller recorded from this handle's steps may still be replayed. */
 void lbm_sc_destroy(lbm_sc* h);
 
 /* Message of the last failure on the calling thread; valid until the next call on that thread.
