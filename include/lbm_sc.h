@@ -281,7 +281,8 @@ int lbm_sc_get_info(lbm_sc* h, lbm_sc_info* out);
 
 /* Release everything the handle owns (after waiting for its stream). NULL is ignored. Not for
  * use inside a stream capture (it waits and frees device memory), nor while a graph that the
- * caller recorded from this handle's steps may still be replayed. */
+ * caller recorded from this handle's steps may still be replayed. A box that groups still list
+ * leaves them: each rebuilds its work list without it before its next launch. */
 void lbm_sc_destroy(lbm_sc* h);
 
 /* Message of the last failure on the calling thread; valid until the next call on that thread.

@@ -199,6 +199,7 @@ struct lbm_sc {
     hipGraphExec_t graph = nullptr;    // graph_len launches captured from buffer graph_cur
     int graph_len = 0;
     int graph_cur = 0;
+    std::vector<lbm_sc_group*> groups;  // groups whose box list holds this box
 };
 
 namespace {
@@ -937,8 +938,6 @@ int lbm_sc_stream_copy(const void* src, void* dst, size_t bytes, void* stream)
     return LBM_SC_OK;
 }
 
-void lbm_sc_destroy(lbm_sc* h) { release(h); }
-
 }  // extern "C"
 
 // ------------------------------------------------------------------------------------------
@@ -965,6 +964,11 @@ struct lbm_sc_group {
 };
 
 namespace {
+
+void detach(lbm_sc* b, lbm_sc_group* g)
+{
+    b->groups.erase(std::remove(b->groups.begin(), b->groups.end(), g), b->groups.end());
+}
 
 void drop_graph(lbm_sc_group* g)
 {
@@ -1152,7 +1156,9 @@ int lbm_sc_group_set(lbm_sc_group* g, lbm_sc* const* boxes, int32_t nbox)
         if (g->launch.tile_x == 0 && g->launch.rows == 8 && (!boxes[i]->fp32 || boxes[i]->math64))
             return fail(LBM_SC_EINVAL, "full-row tiles with 8 nodes per thread need FP32 arithmetic");
     }
+    for (lbm_sc* b : g->boxes) detach(b, g);
     g->boxes.assign(boxes, boxes + nbox);
+    for (lbm_sc* b : g->boxes) b->groups.push_back(g);
     g->fp32 = nbox > 0 && boxes[0]->fp32;
     g->math64 = nbox > 0 && boxes[0]->math64;
     return group_rebuild(g);
@@ -1240,6 +1246,10 @@ int lbm_sc_group_info(lbm_sc_group* g, int32_t* nbox, int64_t* items, int64_t* n
                       int64_t* bytes_per_step)
 {
     if (!g) return fail(LBM_SC_EINVAL, "group is NULL");
+    if (g->dirty && !g->boxes.empty()) {   // a box left (destroyed): count the rebuilt work list
+        if (int rc = refuse_in_capture(g->stream, "lbm_sc_group_info")) return rc;
+        if (int rc = group_rebuild(g)) return rc;
+    }
     if (nbox) *nbox = (int32_t)g->boxes.size();
     if (items) *items = g->nitems;
     if (nodes) *nodes = g->nodes;
@@ -1250,11 +1260,25 @@ int lbm_sc_group_info(lbm_sc_group* g, int32_t* nbox, int64_t* items, int64_t* n
 void lbm_sc_group_destroy(lbm_sc_group* g)
 {
     if (!g) return;
+    for (lbm_sc* b : g->boxes) detach(b, g);
     (void)hipStreamSynchronize(g->stream);
     drop_graph(g);
     if (g->d_desc) (void)hipFree(g->d_desc);
     if (g->d_queue) (void)hipFree(g->d_queue);
     delete g;
+}
+
+void lbm_sc_destroy(lbm_sc* h)
+{
+    if (!h) return;
+    // leave every group that lists the box, so that no group launch reaches its freed buffers:
+    // the group's next step rebuilds its work list without it (release waits for the stream,
+    // which the box shares with its groups, so launches already enqueued finish first)
+    for (lbm_sc_group* g : h->groups) {
+        g->boxes.erase(std::remove(g->boxes.begin(), g->boxes.end(), h), g->boxes.end());
+        g->dirty = true;
+    }
+    release(h);
 }
 
 }  // extern "C"

@@ -153,6 +153,34 @@ def test_group_resyncs_after_a_box_steps_alone_and_after_resets():
         b.close()
 
 
+def test_destroying_a_box_removes_it_from_its_groups():
+    """A box destroyed while groups still list it leaves them: the next group step rebuilds the
+    work list without it (no launch reaches its freed buffers) and the remaining boxes go on
+    bitwise as if stepped alone; a group destroyed first leaves its boxes usable."""
+    import torch
+    s = torch.cuda.Stream()
+    cfgs = box_configs(lbm.LBM_SC_FP32_SHIFTED, s.cuda_stream)[:3]
+    want0, want2 = alone([cfgs[0], cfgs[2]], 13)
+    boxes = [lbm.Box(c) for c in cfgs]
+    g1, g2 = lbm.Group(s.cuda_stream), lbm.Group(s.cuda_stream)
+    g1.set_launch(graph_steps=2)
+    g1.set(boxes)
+    g2.set(boxes[1:])
+    g1.step(4)                   # graph chunks captured over all three boxes
+    boxes[1].close()             # listed by both groups
+    assert g1.info()["nbox"] == 2 and g2.info()["nbox"] == 1
+    g1.step(6)
+    g2.step(3)                   # box 2 runs ahead in the other group ...
+    boxes[0].step(3)             # ... and box 0 alone
+    assert np.array_equal(boxes[0].get(), want0) and np.array_equal(boxes[2].get(), want2)
+    g2.close()                   # box 2 stays usable without the group
+    boxes[2].step(1)
+    g1.step(2)
+    g1.close()
+    boxes[0].close()
+    boxes[2].close()
+
+
 def test_group_rejects_mixed_precision_and_foreign_streams():
     import torch
     s = torch.cuda.Stream()
