@@ -273,7 +273,9 @@ void lbm_sc_group_destroy(lbm_sc_group* g);
 /* Measurement helper, not part of the method: copy `bytes` (a multiple of 16; src and dst
  * 16-byte aligned device pointers that do not overlap) with a plain streaming kernel on `stream`
  * (hipStream_t or NULL for the null stream). Asynchronous. It measures the achievable HBM
- * bandwidth that the step kernel is compared with. LBM_SC_EINVAL on bad sizes or alignment. */
+ * bandwidth that the step kernel is compared with. LBM_SC_EINVAL, with nothing launched, on bad
+ * sizes or alignment, or unless each of the two ranges lies inside one device allocation of the
+ * current device. */
 int lbm_sc_stream_copy(const void* src, void* dst, size_t bytes, void* stream);
 
 /* Describe the handle (coupling, densities, sizes, launch shape). */

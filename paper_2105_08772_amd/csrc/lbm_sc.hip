@@ -542,11 +542,9 @@ namespace {
 
 // A caller's population buffer: device memory of the current device, 256-byte aligned, with at
 // least `need` bytes from p inside one allocation.
-int check_caller_buffer(const void* p, size_t need, const char* name)
+// LBM_SC_EINVAL unless [p, p + need) lies inside one device allocation of the current device.
+int check_device_range(const void* p, size_t need, const std::string& name)
 {
-    if (!p) return fail(LBM_SC_EINVAL, std::string(name) + " is NULL");
-    if (reinterpret_cast<uintptr_t>(p) % 256 != 0)
-        return fail(LBM_SC_EINVAL, std::string(name) + " is not 256-byte aligned");
     hipPointerAttribute_t attr;
     int dev = -1;
     if (hipPointerGetAttributes(&attr, p) != hipSuccess || hipGetDevice(&dev) != hipSuccess) {
@@ -566,6 +564,14 @@ int check_caller_buffer(const void* p, size_t need, const char* name)
         return fail(LBM_SC_EINVAL, std::string(name) + " has fewer than " + std::to_string(need) +
                                        " bytes in its allocation");
     return LBM_SC_OK;
+}
+
+int check_caller_buffer(const void* p, size_t need, const char* name)
+{
+    if (!p) return fail(LBM_SC_EINVAL, std::string(name) + " is NULL");
+    if (reinterpret_cast<uintptr_t>(p) % 256 != 0)
+        return fail(LBM_SC_EINVAL, std::string(name) + " is not 256-byte aligned");
+    return check_device_range(p, need, name);
 }
 
 int create_box(const lbm_sc_config* cfg, void* buf_a, void* buf_b, size_t buf_bytes, lbm_sc** out)
@@ -934,6 +940,8 @@ int lbm_sc_stream_copy(const void* src, void* dst, size_t bytes, void* stream)
     const char* s = (const char*)src;
     const char* d = (const char*)dst;
     if (s < d + bytes && d < s + bytes) return fail(LBM_SC_EINVAL, "src and dst overlap");
+    if (int rc = check_device_range(src, bytes, "src")) return rc;
+    if (int rc = check_device_range(dst, bytes, "dst")) return rc;
     HIP_TRY(lbm::launch_stream_copy(src, dst, bytes, (hipStream_t)stream));
     return LBM_SC_OK;
 }

@@ -486,6 +486,22 @@ def test_stream_copy_helper():
     assert torch.equal(a, b)
     with pytest.raises(lbm.LbmScError):
         lbm.lbm_sc_stream_copy(a.data_ptr(), b.data_ptr(), 12)
+    # ranges that are not device memory, or run past their allocation, are refused before the
+    # copy kernel could touch them
+    host = torch.empty(1 << 22, dtype=torch.uint8, pin_memory=True)
+    hp = (host.data_ptr() + 255) // 256 * 256
+    with pytest.raises(lbm.LbmScError) as e:
+        lbm.lbm_sc_stream_copy(hp, b.data_ptr(), 1 << 20)
+    assert "device memory" in lbm.lbm_sc_last_error()
+    big = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+    small = torch.empty(64 << 20, dtype=torch.uint8, device="cuda")
+    n = 512 << 20
+    with pytest.raises(lbm.LbmScError) as e:
+        lbm.lbm_sc_stream_copy(big.data_ptr(), small.data_ptr(), n)
+    assert e.value.code == lbm.LBM_SC_EINVAL
+    p, q = big.data_ptr(), small.data_ptr()
+    if not (p < q + n and q < p + n):
+        assert "allocation" in lbm.lbm_sc_last_error()
 
 
 def test_zero_steps_is_a_no_op():
