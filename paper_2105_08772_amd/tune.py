@@ -35,8 +35,10 @@ def group_candidates():
 
 def tune_group(group, steps=8, candidates=None, log=None):
     """Try each candidate on `group` (a paper_2105_08772_amd.Group) for `steps` steps; set and
-    return the fastest as a dict with its seconds per step."""
+    return the fastest as a dict with its seconds per step. The group keeps its own graph chunk
+    length (candidates are timed with chunks of `steps`)."""
     from . import LbmScError
+    graph_steps = group.launch()["graph_steps"]
     best = None
     for cand in candidates or group_candidates():
         try:
@@ -53,7 +55,9 @@ def tune_group(group, steps=8, candidates=None, log=None):
             log(f"tune group {cand}: {t * 1e3:.3f} ms/step")
         if best is None or t < best[0]:
             best = (t, cand)
-    group.set_launch(**best[1])
+    if best is None:
+        raise ValueError("no candidate launch shape fits the boxes of this group")
+    group.set_launch(**best[1], graph_steps=graph_steps)
     return dict(best[1], seconds_per_step=best[0])
 
 
@@ -85,6 +89,8 @@ def tune_box(box, steps=16, candidates=None, log=None):
             log(f"tune box {cand}: {t * 1e3:.3f} ms/step")
         if best is None or t < best[0]:
             best = (t, cand)
+    if best is None:
+        raise ValueError("no candidate launch shape fits this box")
     c = best[1]
     box.set_launch(c["rows"], c["z_chunk"], c["xcd_remap"], c["prefetch"], c["waves"],
                    c["tile_x"])

@@ -1,5 +1,7 @@
 """The autotuner's candidate lists (host logic, no GPU): every compiled launch shape appears,
 each candidate once, with valid chunking and worker settings."""
+import pytest
+
 import paper_2105_08772_amd.tune as tune
 
 
@@ -46,3 +48,37 @@ def test_box_candidates_respect_the_box_height():
         assert all(c["z_chunk"] <= max(nz, 8) for c in cands)
         keys = [tuple(sorted(c.items())) for c in cands]
         assert len(keys) == len(set(keys))
+
+
+def test_tune_group_keeps_the_graph_chunk_and_refuses_when_nothing_fits(monkeypatch):
+    """On a stand-in group: the fastest candidate is set with the group's own graph chunk length
+    restored (candidates are timed with chunks of `steps`), and a group that no candidate fits
+    raises instead of failing on an empty result."""
+    from paper_2105_08772_amd import LbmScError
+
+    class FakeGroup:
+        def __init__(self, cost, fits=lambda c: True):
+            self.shape = dict(graph_steps=64, rows=1)
+            self.cost, self.fits = cost, fits
+
+        def set_launch(self, **kw):
+            if not self.fits(kw):
+                raise LbmScError(-1, "does not fit")
+            self.shape.update(kw)
+
+        def launch(self):
+            return dict(self.shape)
+
+        def step(self, n):
+            clock[0] += n * self.cost[self.shape["rows"]]
+
+    clock = [0.0]
+    monkeypatch.setattr(tune, "_sync", lambda: None)
+    monkeypatch.setattr(tune.time, "perf_counter", lambda: clock[0])
+    cands = [dict(rows=r) for r in (1, 2, 4)]
+    g = FakeGroup({1: 3.0, 2: 1.0, 4: 2.0}, fits=lambda c: c.get("rows") != 4)
+    best = tune.tune_group(g, steps=8, candidates=cands)
+    assert best["rows"] == 2 and best["seconds_per_step"] == 1.0
+    assert g.launch() == dict(graph_steps=64, rows=2)
+    with pytest.raises(ValueError):
+        tune.tune_group(FakeGroup({}, fits=lambda c: False), candidates=cands)
