@@ -14,6 +14,7 @@ timed on the host cores on a bounded sample of the same workload.
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -360,17 +361,19 @@ def tolman_sweep(torch, lbm, log, psi):
         f = fits32.get(round(g, 10))
         f64 = fits64.get(round(g, 10))
         entry = {"flat_sigma0": flat[g]["sigma0"], "flat_pn_spread_rel": flat[g]["pn_spread_rel"]}
+        # a coupling with fewer than two distinct curvatures has no fit (NaN): reported as null
+        fin = lambda v: v if not (isinstance(v, float) and math.isnan(v)) else None  # noqa: E731
         if f:
-            entry.update({k: f[k] for k in ("sigma0", "delta", "rms", "npoints", "delta_hat0",
-                                            "no_minimum")})
-            entry["sigma0_fit_over_flat"] = f["sigma0"] / flat[g]["sigma0"]
+            entry.update({k: fin(f[k]) for k in ("sigma0", "delta", "rms", "npoints", "delta_hat0",
+                                                 "no_minimum")})
+            entry["sigma0_fit_over_flat"] = fin(f["sigma0"] / flat[g]["sigma0"])
             entry["points"] = [dict(kappa=round(p["kappa"], 6), sigma_s=round(p["sigma_s"], 8),
                                     R_s=round(p["R_s"], 4), R_e=round(p["R_e"], 4),
                                     bubble=p["bubble"]) for p in f["points"]]
         if f and f64:
-            entry["fp64"] = {k: f64[k] for k in ("sigma0", "delta", "delta_hat0", "npoints")}
-            entry["sigma0_rel_err_fp32_vs_fp64"] = abs(f["sigma0"] - f64["sigma0"]) / f64["sigma0"]
-            entry["delta_err_fp32_vs_fp64"] = abs(f["delta"] - f64["delta"])
+            entry["fp64"] = {k: fin(f64[k]) for k in ("sigma0", "delta", "delta_hat0", "npoints")}
+            entry["sigma0_rel_err_fp32_vs_fp64"] = fin(abs(f["sigma0"] - f64["sigma0"]) / f64["sigma0"])
+            entry["delta_err_fp32_vs_fp64"] = fin(abs(f["delta"] - f64["delta"]))
         # per run, where both precisions converged
         errs = {"dP": [], "sigma_s": [], "R_s": []}
         for k in sorted(set(conv32) & set(conv64)):
@@ -387,7 +390,8 @@ def tolman_sweep(torch, lbm, log, psi):
             k: {"max": max(v), "median": sorted(v)[len(v) // 2], "runs": len(v)}
             for k, v in errs.items() if v}
         out["couplings"][str(g)] = entry
-    gs = [g for g in ratios if fits32.get(round(g, 10))]
+    gs = [g for g in ratios if fits32.get(round(g, 10))
+          and not math.isnan(fits32[round(g, 10)]["sigma0"])]
     if len(gs) >= 2:
         x = [g - 1 for g in gs]
         out["sigma0_exponent"] = analysis.scaling_exponent(

@@ -27,9 +27,12 @@ def laplace_point(obs, bubble):
 
 
 def fit_line(x, y, w=None):
-    """Weighted least-squares line y = a + b x; returns (a, b, residual rms)."""
+    """Weighted least-squares line y = a + b x; returns (a, b, residual rms). A line needs at
+    least two distinct abscissae (ValueError otherwise)."""
     x = np.asarray(x, dtype=float)
     y = np.asarray(y, dtype=float)
+    if len(np.unique(x)) < 2:
+        raise ValueError("a line fit needs at least two distinct abscissae")
     w = np.ones_like(x) if w is None else np.asarray(w, dtype=float)
     A = np.stack([np.ones_like(x), x], axis=1) * np.sqrt(w)[:, None]
     coef, *_ = np.linalg.lstsq(A, y * np.sqrt(w), rcond=None)
@@ -63,7 +66,8 @@ def scaling_exponent(g_minus_1, values):
 def analyse(runs):
     """runs: iterable of dicts with keys g_over_gc, bubble, obs (converged observables).
     Returns, per coupling, the points and both fits; runs whose sigma[R] has no minimum
-    (dP <= 0 or C <= 0) are counted under "no_minimum" and left out."""
+    (dP <= 0 or C <= 0) are counted under "no_minimum" and left out. A coupling with fewer than
+    two distinct curvatures keeps its points and gets NaN fits."""
     by_g = {}
     skipped = {}
     for r in runs:
@@ -78,9 +82,14 @@ def analyse(runs):
     for g, pts in sorted(by_g.items()):
         kap = [p[0] for p in pts]
         sig = [p[1] for p in pts]
-        fit = tolman_fit(kap, sig)
         dh = [delta_hat(p[3], p[2], p[4]) for p in pts]
+        if len(set(kap)) >= 2:
+            fits = dict(tolman_fit(kap, sig), **delta_hat_flat(kap, dh))
+        else:
+            nan = float("nan")
+            fits = dict(sigma0=nan, delta=nan, rms=nan, npoints=len(kap), delta_hat0=nan,
+                        delta_hat_slope=nan, delta_hat_rms=nan)
         out[g] = dict(points=[dict(kappa=p[0], sigma_s=p[1], R_s=p[2], R_e=p[3], bubble=p[4])
                               for p in pts],
-                      no_minimum=skipped.get(g, 0), **fit, **delta_hat_flat(kap, dh))
+                      no_minimum=skipped.get(g, 0), **fits)
     return out

@@ -54,3 +54,13 @@ def test_laplace_point_rejects_runs_without_surface_of_tension():
         analysis.laplace_point(dict(R_s=float("nan"), dP=0.0, R_e=3.0), False)
     k, s, Rs, Re = analysis.laplace_point(dict(R_s=10.0, dP=0.01, R_e=10.5), True)
     assert k == -0.1 and s == pytest.approx(0.05) and math.isclose(Re, 10.5)
+
+
+def test_a_coupling_with_one_curvature_gets_nan_fits():
+    runs = synthetic_runs(1.3, 0.05, 0.8, [10, 12]) + synthetic_runs(1.5, 0.07, 0.6, [20])[:1]
+    out = analysis.analyse(runs)
+    assert out[1.3]["sigma0"] == pytest.approx(0.05, rel=1e-12)
+    assert len(out[1.5]["points"]) == 1
+    assert all(math.isnan(out[1.5][k]) for k in ("sigma0", "delta", "delta_hat0"))
+    with pytest.raises(ValueError):
+        analysis.fit_line([1.0, 1.0], [2.0, 3.0])
