@@ -217,3 +217,21 @@ def test_bench_refuses_more_than_one_gpu():
                        capture_output=True, text=True, timeout=300)
     assert r.returncode != 0
     assert "one GPU" in (r.stdout + r.stderr)
+
+
+def test_every_header_declaration_is_documented():
+    """Each prototype of include/lbm_sc.h follows a comment block, directly or after the
+    prototypes it shares that comment with (a set/get pair)."""
+    lines = open(HEADER).read().splitlines()
+    decl = re.compile(r"^(?:const\s+)?\w+\s*\*?\s*lbm_sc_\w+\s*\(")   # at column 0
+    undocumented = []
+    for k, line in enumerate(lines):
+        if not decl.match(line):
+            continue
+        j = k - 1
+        while j >= 0 and (decl.match(lines[j]) or lines[j].startswith((" ", "\t")) and
+                          not lines[j].lstrip().startswith(("*", "/*"))):
+            j -= 1            # earlier prototypes of the same group, or their continuation lines
+        if j < 0 or not lines[j].rstrip().endswith("*/"):
+            undocumented.append(line.strip())
+    assert not undocumented, undocumented
