@@ -1178,8 +1178,10 @@ int lbm_sc_group_step(lbm_sc_group* g, int64_t nsteps)
     if (nsteps < 0) return fail(LBM_SC_EINVAL, "nsteps must be >= 0");
     if (int rc = refuse_in_capture(g->stream, "lbm_sc_group_step")) return rc;
     if (g->boxes.empty() || nsteps == 0) return LBM_SC_OK;
-    // a box stepped alone since the last call is out of phase with the work list: rebuild
-    for (size_t i = 0; i < g->boxes.size(); ++i)
+    // a box stepped alone since the last call is out of phase with the work list: rebuild (so
+    // does a work list that does not match the boxes, e.g. after a failed rebuild)
+    if (g->desc.size() != g->boxes.size()) g->dirty = true;
+    for (size_t i = 0; i < g->boxes.size() && !g->dirty; ++i)
         if (((g->desc[i].phase + g->par) & 1) != g->boxes[i]->cur) g->dirty = true;
     if (g->dirty) {
         int rc = group_rebuild(g);
