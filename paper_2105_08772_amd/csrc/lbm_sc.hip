@@ -337,12 +337,17 @@ int observe(lbm_sc* h, lbm_sc_obs* o, double* prof_out)
                                          h->d_small + lbm::OBS_PARTS, h->stream));
     double small[lbm::OBS_PARTS + 4];
     std::vector<double> prof(4 * (size_t)L);
-    HIP_TRY(hipMemcpyAsync(small, h->d_small, sizeof(small), hipMemcpyDeviceToHost, h->stream));
-    HIP_TRY(hipMemcpyAsync(prof.data(), h->d_prof, prof.size() * sizeof(double),
-                           hipMemcpyDeviceToHost, h->stream));
-    HIP_TRY(hipMemcpyAsync(h->d_uprev, h->d_u, 3 * (size_t)b.n * sizeof(double),
-                           hipMemcpyDeviceToDevice, h->stream));
-    HIP_TRY(hipStreamSynchronize(h->stream));
+    hipError_t e = hipMemcpyAsync(small, h->d_small, sizeof(small), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(prof.data(), h->d_prof, prof.size() * sizeof(double),
+                           hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(h->d_uprev, h->d_u, 3 * (size_t)b.n * sizeof(double),
+                           hipMemcpyDeviceToDevice, h->stream);
+    // wait also when an enqueue failed: no copy may still write into small or prof after return
+    const hipError_t se = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return fail_hip("hipMemcpyAsync", e);
+    if (se != hipSuccess) return fail_hip("hipStreamSynchronize", se);
 
     std::memset(o, 0, sizeof(*o));
     const double nan = std::nan("");
@@ -841,8 +846,11 @@ int lbm_sc_set_populations(lbm_sc* h, const double* f, size_t len)
     HIP_TRY(hipMemsetAsync(h->box.tick, 0, 2 * sizeof(unsigned), h->stream));
     for (int i = 0; i < 19; ++i) {
         HIP_TRY(hipMemcpyAsync(h->d_n, f + (size_t)i * N, N * 8, hipMemcpyHostToDevice, h->stream));
-        HIP_TRY(lbm::launch_set(h->fp32, h->box, i, h->d_n, h->pop[h->cur], h->stream));
-        HIP_TRY(hipStreamSynchronize(h->stream));
+        const hipError_t e = lbm::launch_set(h->fp32, h->box, i, h->d_n, h->pop[h->cur], h->stream);
+        // wait also when the launch failed: the copy must be done with f before returning
+        const hipError_t se = hipStreamSynchronize(h->stream);
+        if (e != hipSuccess) return fail_hip("launch_set", e);
+        if (se != hipSuccess) return fail_hip("hipStreamSynchronize", se);
     }
     h->step = 0;
     h->has_prev = 0;
