@@ -251,6 +251,16 @@ def test_steps_recorded_into_a_caller_graph():
         ref.step(2)
         assert np.array_equal(b.get(), ref.get())
         assert b.observables(profile=False)[0]["step"] == ref.observables(profile=False)[0]["step"] == 14
+        # a count of at least the box's own graph chunk (64 steps), which outside a capture it
+        # replays from its internal graph, is recorded as plain launches too
+        g2 = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g2, stream=s):
+            b.step(66)
+        for _ in range(2):
+            g2.replay()
+            torch.cuda.synchronize()
+            ref.step(66)
+            assert np.array_equal(b.get(), ref.get())
 
 
 @pytest.mark.parametrize("dims", SHAPES + [(100, 37, 9), (129, 5, 4)])
