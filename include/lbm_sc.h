@@ -270,6 +270,30 @@ int lbm_sc_group_info(lbm_sc_group* g, int32_t* nbox, int64_t* items, int64_t* n
  * Not for use inside a stream capture (it waits and frees device memory). */
 void lbm_sc_group_destroy(lbm_sc_group* g);
 
+/* Most boxes one call of lbm_sc_step_boxes_noalloc takes. */
+#define LBM_SC_NOALLOC_MAX_BOXES 1024
+
+/* For callers that cannot allocate device memory: code recording into a HIP graph of its own,
+ * serving loops that must not call hipMalloc/hipFree, harnesses that forbid it. Enqueues nsteps
+ * (>= 0) time steps of the nbox boxes with one multi-box launch per step, like a group holding
+ * these boxes under `launch` (same kernels, so the result is bitwise that of lbm_sc_group_step
+ * and of lbm_sc_step), but without a group object: the work list and the persistent kernel's
+ * queue state are written, by small kernels on the boxes' stream, into a fixed device array that
+ * the library holds once per GPU (122,952 bytes, kept until the process ends). Nothing is
+ * allocated on the device or freed, and no host buffer is staged. Limit: at most
+ * LBM_SC_NOALLOC_MAX_BOXES boxes per call (LBM_SC_EINVAL beyond, nothing enqueued).
+ * The boxes stay owned by the caller; every box must be non-NULL, appear once, share one
+ * precision and have been created on one stream, where the work is enqueued; launch follows the
+ * rules of lbm_sc_group_set_launch and must fit every box (LBM_SC_EINVAL otherwise, nothing
+ * enqueued). Each box's step counter advances by nsteps. Asynchronous. Calls that overlap in time
+ * on one GPU (enqueued on different streams) race on the shared array; calls on one stream are
+ * ordered. While the caller is capturing the stream the launches are recorded into the caller's
+ * graph: nsteps must then be even, every replay advances the boxes by nsteps, and the host step
+ * counters advance once, at the capture. LBM_SC_EDEVICE if a launch fails (the counters then
+ * advance by the steps enqueued before it). */
+int lbm_sc_step_boxes_noalloc(lbm_sc* const* boxes, int32_t nbox, int64_t nsteps,
+                              const lbm_sc_group_launch* launch);
+
 /* Measurement helper, not part of the method: copy `bytes` (a multiple of 16; src and dst
  * 16-byte aligned device pointers that do not overlap) with a plain streaming kernel on `stream`
  * (hipStream_t or NULL for the null stream). Asynchronous. It measures the achievable HBM

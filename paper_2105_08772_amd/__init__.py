@@ -87,7 +87,7 @@ EXPORTS = ("lbm_sc_create", "lbm_sc_step", "lbm_sc_sync", "lbm_sc_observables",
            "lbm_sc_group_set", "lbm_sc_group_step", "lbm_sc_group_set_launch",
            "lbm_sc_group_get_launch", "lbm_sc_group_info", "lbm_sc_group_destroy",
            "lbm_sc_device_bytes", "lbm_sc_create_with_buffers", "lbm_sc_population_bytes",
-           "lbm_sc_set_step")
+           "lbm_sc_set_step", "lbm_sc_step_boxes_noalloc")
 
 _lib = None
 
@@ -132,6 +132,7 @@ def load():
     L.lbm_sc_group_info.argtypes = [_vp, P(_i32), P(_i64), P(_i64), P(_i64)]
     L.lbm_sc_group_destroy.argtypes = [_vp]
     L.lbm_sc_group_destroy.restype = None
+    L.lbm_sc_step_boxes_noalloc.argtypes = [P(_vp), _i32, _i64, P(LbmScGroupLaunch)]
     L.lbm_sc_device_bytes.argtypes = [P(LbmScConfig)]
     L.lbm_sc_device_bytes.restype = _i64
     for name in EXPORTS:
@@ -384,6 +385,17 @@ def lbm_sc_group_info(g):
 def lbm_sc_group_destroy(g):
     if g is not None and g.value:
         load().lbm_sc_group_destroy(g)
+
+
+LBM_SC_NOALLOC_MAX_BOXES = 1024
+
+
+def lbm_sc_step_boxes_noalloc(handles, nsteps, **launch):
+    """nsteps steps of the boxes (handles) with one multi-box launch per step and no device
+    allocation; `launch` holds the fields of lbm_sc_group_launch."""
+    l = LbmScGroupLaunch(**launch)
+    arr = (_vp * max(len(handles), 1))(*[h.value for h in handles])
+    _check(load().lbm_sc_step_boxes_noalloc(arr, len(handles), int(nsteps), ctypes.byref(l)))
 
 
 class Group:

@@ -17,10 +17,18 @@
 //   LDS ring of four psi planes, and collides plane q once the psi of plane q + 1 is in LDS. Only
 //   the halo and the two end planes of each chunk are pulled twice; the repeated reads are meant
 //   to hit L2 because neighbouring tiles run together on the same XCD.
+#include <mutex>
 #include <type_traits>
 
 #include "kernels.hpp"
 #include "d3q19.hpp"
+
+// Work list and queue state of the allocation-free multi-box step (lbm_sc_step_boxes_noalloc):
+// one fixed array per GPU, held until the process ends. Host code never uses this name as an
+// address (it is a host-side stand-in there); it reads the device address once per device with
+// hipGetSymbolAddress (noalloc_scratch_address) and passes that to the kernels.
+static __device__ __align__(256) unsigned char scratch[lbm::noalloc_queue_offset() +
+                                                       sizeof(lbm::QueueState)];
 
 namespace lbm {
 namespace {
@@ -1248,11 +1256,69 @@ __global__ __launch_bounds__(256) void k_stream_copy(const float* __restrict__ s
     for (; i < n; i += stride) dst[i] = src[i];
 }
 
+// Copy a batch of work-list descriptors, passed by value as a kernel argument, to their slots in
+// the allocation-free step's array (word by word; the batch is a few KB).
+__global__ __launch_bounds__(256) void k_put_descs(DescBatch b, GroupBox* __restrict__ dst)
+{
+    static_assert(sizeof(GroupBox) % 4 == 0, "descriptors are copied in 32-bit words");
+    constexpr int WORDS = (int)(sizeof(GroupBox) / 4);
+    const unsigned* src = reinterpret_cast<const unsigned*>(b.d);
+    unsigned* out = reinterpret_cast<unsigned*>(dst + b.first);
+    for (int k = threadIdx.x; k < b.count * WORDS; k += blockDim.x) out[k] = src[k];
+}
+
+__global__ void k_put_queue(QueueState q, QueueState* __restrict__ dst)
+{
+    if (threadIdx.x == 0) *dst = q;
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------------------------------
 // Host launchers
 // ------------------------------------------------------------------------------------------
+
+// Device address of `scratch` on the current device. Each GPU holds its own copy of the array at
+// its own address, so the address is looked up once per device (with that device current) and
+// kept; every later call returns the kept address.
+hipError_t noalloc_scratch_address(void** ptr)
+{
+    constexpr int MAX_DEVICES = 64;
+    static std::mutex mu;
+    static void* addr[MAX_DEVICES] = {};
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        addr[dev] = p;
+    }
+    *ptr = addr[dev];
+    return hipSuccess;
+}
+
+hipError_t launch_put_descs(const DescBatch& b, void* scratch_dev, hipStream_t st)
+{
+    if (b.count < 1 || b.count > NOALLOC_BATCH || b.first < 0 ||
+        b.first + b.count > NOALLOC_MAX_BOXES)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_put_descs, dim3(1), dim3(256), 0, st, b,
+                       reinterpret_cast<GroupBox*>(scratch_dev));
+    return hipGetLastError();
+}
+
+hipError_t launch_put_queue(const QueueState& q, void* scratch_dev, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_put_queue, dim3(1), dim3(64), 0, st, q,
+                       reinterpret_cast<QueueState*>(static_cast<char*>(scratch_dev) +
+                                                     noalloc_queue_offset()));
+    return hipGetLastError();
+}
 
 hipError_t launch_step(bool fp32, bool math64, const BoxDesc& b, const StepShape& s, int sbuf,
                        const void* src, void* dst, hipStream_t st)

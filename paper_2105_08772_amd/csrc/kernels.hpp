@@ -91,6 +91,30 @@ struct InitDesc {
     unsigned long long seed;
 };
 
+// Allocation-free multi-box step: the work list (at most NOALLOC_MAX_BOXES descriptors) and the
+// persistent kernel's queue state live in one fixed device array per GPU, written by small
+// stream-ordered kernels that take the descriptors as kernel arguments (no host staging, no
+// device allocation).
+constexpr int NOALLOC_MAX_BOXES = 1024;
+constexpr int NOALLOC_BATCH = 16;     // descriptors per writing launch (kernel-argument size)
+struct DescBatch {
+    GroupBox d[NOALLOC_BATCH];
+    int count;                        // descriptors used in d
+    int first;                        // index of d[0] in the device work list
+};
+// Device address of the current device's array (looked up with hipGetSymbolAddress on the
+// first call on each device and kept). Its first NOALLOC_MAX_BOXES * sizeof(GroupBox) bytes hold
+// the work list, followed by the queue state at noalloc_queue_offset().
+hipError_t noalloc_scratch_address(void** ptr);
+constexpr size_t noalloc_queue_offset()
+{
+    return ((size_t)NOALLOC_MAX_BOXES * sizeof(GroupBox) + 255) / 256 * 256;
+}
+// Write a batch of descriptors / the queue state into the array at `scratch` (a device address
+// returned by noalloc_scratch_address).
+hipError_t launch_put_descs(const DescBatch& b, void* scratch, hipStream_t st);
+hipError_t launch_put_queue(const QueueState& q, void* scratch, hipStream_t st);
+
 // Number of per-block partial sums written by the observation reduction.
 constexpr int OBS_PARTS = 14;
 // Fixed grid of the observation reduction (deterministic order of the partial sums).

@@ -16,17 +16,21 @@
 
 namespace {
 
-thread_local std::string g_err = "no error";
+// Message of the last failure on this thread, in a fixed buffer so that recording an error
+// allocates nothing.
+thread_local char g_err[512] = "no error";
 
 const char* const SHAPE_MSG =
     "unsupported launch shape (tile_x 64: waves 4 with rows 1, 2, 4, or waves 8 with rows 1, 2 and no "
     "prefetch; tile_x 32: rows 1, 2 (waves 8: no prefetch); tile_x 0: no prefetch, waves 8 with rows 2, 4 or 8, or waves 4 with rows 4)";
 
-int fail(int code, const std::string& msg)
+int fail(int code, const char* msg)
 {
-    g_err = msg;
+    std::snprintf(g_err, sizeof(g_err), "%s", msg);
     return code;
 }
+
+int fail(int code, const std::string& msg) { return fail(code, msg.c_str()); }
 
 int fail_hip(const char* what, hipError_t e)
 {
@@ -507,7 +511,7 @@ Sizes sizes_for(const lbm_sc_config* c)
 
 extern "C" {
 
-const char* lbm_sc_last_error(void) { return g_err.c_str(); }
+const char* lbm_sc_last_error(void) { return g_err; }
 
 int64_t lbm_sc_device_bytes(const lbm_sc_config* cfg)
 {
@@ -1005,6 +1009,104 @@ lbm::StepShape group_shape(const lbm_sc_group_launch& L)
     return s;
 }
 
+// z_chunk 0: each box is cut into z chunks of about the same work, items_per_cu items per CU in
+// total, so that small boxes march their whole height (no chunk ends pulled twice) and large
+// ones are split for balance. Returns the work (nodes) of one item, 0 for fixed z chunks.
+double chunk_work(lbm_sc* const* boxes, size_t nbox, const lbm_sc_group_launch& L)
+{
+    if (L.z_chunk != 0) return 0.0;
+    double total = 0.0;
+    for (size_t i = 0; i < nbox; ++i) total += (double)boxes[i]->box.n;
+    int cus = 0, dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus <= 0)
+        cus = 256;
+    const int per_cu = L.items_per_cu > 0 ? L.items_per_cu : 8;
+    return total / ((double)per_cu * cus);
+}
+
+// Work-list descriptor of box h under launch L; its items start at item_begin.
+lbm::GroupBox box_desc(const lbm_sc* h, const lbm_sc_group_launch& L, double item_work,
+                       unsigned item_begin)
+{
+    const lbm::StepShape shape = group_shape(L);
+    int bx, by;
+    tile_dims(shape, h->box, bx, by);
+    lbm::GroupBox d;
+    std::memset(&d, 0, sizeof(d));
+    d.b = h->box;
+    d.pop[0] = h->pop[0];
+    d.pop[1] = h->pop[1];
+    d.phase = h->cur;
+    d.by = shape.tile_x == 0 ? by : 0;
+    d.tiles_x = (h->box.nx + bx - 1) / bx;
+    d.tiles_y = (h->box.ny + by - 1) / by;
+    if (L.z_chunk == 0) {
+        const double tiles = (double)d.tiles_x * d.tiles_y;
+        long chunks = item_work > 0.0 ? std::lround((double)h->box.n / item_work / tiles) : 1;
+        chunks = std::max(1L, std::min(chunks, (long)h->box.nz));
+        d.zc = (int)((h->box.nz + chunks - 1) / chunks);
+    } else {
+        d.zc = L.z_chunk < h->box.nz ? L.z_chunk : h->box.nz;
+    }
+    const unsigned nch = (unsigned)((h->box.nz + d.zc - 1) / d.zc);
+    d.item_begin = item_begin;
+    d.items = (unsigned)d.tiles_x * (unsigned)d.tiles_y * nch;
+    return d;
+}
+
+// Nodes updated by item `it` (0 <= it < d.items) of a box's descriptor.
+double item_nodes(const lbm::GroupBox& d, const lbm_sc_group_launch& L, unsigned it)
+{
+    int bx, by;
+    tile_dims(group_shape(L), d.b, bx, by);
+    const unsigned tix = it % d.tiles_x, t2 = it / d.tiles_x;
+    const unsigned tiy = t2 % d.tiles_y, ch = t2 / d.tiles_y;
+    const int w = std::min(bx, d.b.nx - (int)tix * bx);
+    const int hgt = std::min(by, d.b.ny - (int)tiy * by);
+    const int dz = std::min(d.zc, d.b.nz - (int)ch * d.zc);
+    return (double)std::max(w, 1) * std::max(hgt, 1) * std::max(dz, 1);
+}
+
+// Queue state of the persistent kernel: eight contiguous, work-balanced runs of the box-major
+// item list (desc(i) returns the descriptor of box i), counters at zero.
+template <typename Desc>
+lbm::QueueState queue_ranges(Desc desc, size_t nbox, unsigned nitems, const lbm_sc_group_launch& L)
+{
+    lbm::QueueState q;
+    std::memset(&q, 0, sizeof(q));
+    double total = 0.0;
+    for (size_t i = 0; i < nbox; ++i) {
+        const lbm::GroupBox d = desc(i);
+        for (unsigned it = 0; it < d.items; ++it) total += item_nodes(d, L, it);
+    }
+    // walk the items in order; queue x starts at the first item whose midpoint lies past x/8 of
+    // the total work
+    size_t bi = 0;
+    unsigned it = 0, k = 0;
+    lbm::GroupBox cur = nbox ? desc(0) : lbm::GroupBox{};
+    double acc = 0.0;
+    q.range[0] = 0;
+    for (int x = 1; x < 8; ++x) {
+        const double target = total * x / 8.0;
+        while (k < nitems) {
+            while (it >= cur.items && bi + 1 < nbox) {
+                cur = desc(++bi);
+                it = 0;
+            }
+            const double w = item_nodes(cur, L, it);
+            if (!(acc + 0.5 * w < target)) break;
+            acc += w;
+            ++it;
+            ++k;
+        }
+        q.range[x] = k;
+    }
+    q.range[8] = nitems;
+    return q;
+}
+
 // Build the work list and queue ranges for the current boxes and launch shape, and upload them.
 // Phases align every box's current buffer with parity 0.
 int group_rebuild(lbm_sc_group* g)
@@ -1014,54 +1116,9 @@ int group_rebuild(lbm_sc_group* g)
     g->nitems = 0;
     g->nodes = 0;
     g->bytes_per_step = 0;
-    std::vector<double> work;   // nodes per item, box-major
-    const lbm::StepShape shape = group_shape(L);
-    // z_chunk 0: each box is cut into z chunks of about the same work, items_per_cu items per CU
-    // in total, so that small boxes march their whole height (no chunk ends pulled twice) and
-    // large ones are split for balance
-    double item_work = 0.0;
-    if (L.z_chunk == 0) {
-        double total = 0.0;
-        for (lbm_sc* h : g->boxes) total += (double)h->box.n;
-        int cus = 0, dev = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-            cus <= 0)
-            cus = 256;
-        const int per_cu = L.items_per_cu > 0 ? L.items_per_cu : 8;
-        item_work = total / ((double)per_cu * cus);
-    }
+    const double item_work = chunk_work(g->boxes.data(), g->boxes.size(), L);
     for (lbm_sc* h : g->boxes) {
-        int bx, by;
-        tile_dims(shape, h->box, bx, by);
-        lbm::GroupBox d;
-        std::memset(&d, 0, sizeof(d));
-        d.b = h->box;
-        d.pop[0] = h->pop[0];
-        d.pop[1] = h->pop[1];
-        d.phase = h->cur;
-        d.by = shape.tile_x == 0 ? by : 0;
-        d.tiles_x = (h->box.nx + bx - 1) / bx;
-        d.tiles_y = (h->box.ny + by - 1) / by;
-        if (L.z_chunk == 0) {
-            const double tiles = (double)d.tiles_x * d.tiles_y;
-            long chunks = item_work > 0.0 ? std::lround((double)h->box.n / item_work / tiles) : 1;
-            chunks = std::max(1L, std::min(chunks, (long)h->box.nz));
-            d.zc = (int)((h->box.nz + chunks - 1) / chunks);
-        } else {
-            d.zc = L.z_chunk < h->box.nz ? L.z_chunk : h->box.nz;
-        }
-        const unsigned nch = (unsigned)((h->box.nz + d.zc - 1) / d.zc);
-        d.item_begin = g->nitems;
-        d.items = (unsigned)d.tiles_x * (unsigned)d.tiles_y * nch;
-        for (unsigned it = 0; it < d.items; ++it) {
-            const unsigned tix = it % d.tiles_x, t2 = it / d.tiles_x;
-            const unsigned tiy = t2 % d.tiles_y, ch = t2 / d.tiles_y;
-            const int w = std::min(bx, h->box.nx - (int)tix * bx);
-            const int hgt = std::min(by, h->box.ny - (int)tiy * by);
-            const int dz = std::min(d.zc, h->box.nz - (int)ch * d.zc);
-            work.push_back((double)std::max(w, 1) * std::max(hgt, 1) * std::max(dz, 1));
-        }
+        const lbm::GroupBox d = box_desc(h, L, item_work, g->nitems);
         g->nitems += d.items;
         g->nodes += (int64_t)h->box.n;
         g->bytes_per_step += (int64_t)2 * 19 * (int64_t)h->elem * (int64_t)h->box.n;
@@ -1079,20 +1136,8 @@ int group_rebuild(lbm_sc_group* g)
         }
         HIP_TRY(hipMemcpyAsync(g->d_desc, g->desc.data(), bytes, hipMemcpyHostToDevice, g->stream));
     }
-    // eight contiguous, work-balanced queue ranges
-    lbm::QueueState q;
-    std::memset(&q, 0, sizeof(q));
-    double total = 0.0;
-    for (double w : work) total += w;
-    unsigned k = 0;
-    double acc = 0.0;
-    q.range[0] = 0;
-    for (int x = 1; x < 8; ++x) {
-        const double target = total * x / 8.0;
-        while (k < g->nitems && acc + 0.5 * work[k] < target) acc += work[k++];
-        q.range[x] = k;
-    }
-    q.range[8] = g->nitems;
+    const lbm::QueueState q = queue_ranges([&](size_t i) { return g->desc[i]; }, g->desc.size(),
+                                           g->nitems, L);
     HIP_TRY(hipMemcpyAsync(g->d_queue, &q, sizeof(q), hipMemcpyHostToDevice, g->stream));
     // the queue state is read by later launches: keep the host copy alive until it has landed
     HIP_TRY(hipStreamSynchronize(g->stream));
@@ -1284,6 +1329,86 @@ void lbm_sc_group_destroy(lbm_sc_group* g)
     if (g->d_desc) (void)hipFree(g->d_desc);
     if (g->d_queue) (void)hipFree(g->d_queue);
     delete g;
+}
+
+int lbm_sc_step_boxes_noalloc(lbm_sc* const* boxes, int32_t nbox, int64_t nsteps,
+                              const lbm_sc_group_launch* launch)
+{
+    if (nbox < 0 || (nbox > 0 && !boxes) || !launch) return fail(LBM_SC_EINVAL, "bad box list or launch");
+    if (nbox > lbm::NOALLOC_MAX_BOXES)
+        return fail(LBM_SC_EINVAL, "lbm_sc_step_boxes_noalloc takes at most 1024 boxes");
+    if (nsteps < 0) return fail(LBM_SC_EINVAL, "nsteps must be >= 0");
+    if (int rc = check_group_launch(launch)) return rc;
+    const lbm_sc_group_launch& L = *launch;
+    const lbm::StepShape shape = group_shape(L);
+    for (int i = 0; i < nbox; ++i) {
+        const lbm_sc* b = boxes[i];
+        if (!b) return fail(LBM_SC_EINVAL, "a box is NULL");
+        if (b->stream != boxes[0]->stream)
+            return fail(LBM_SC_EINVAL, "all boxes must have been created on one stream");
+        if (b->fp32 != boxes[0]->fp32 || b->math64 != boxes[0]->math64)
+            return fail(LBM_SC_EINVAL, "all boxes must share one precision");
+        for (int j = 0; j < i; ++j)
+            if (boxes[j] == b) return fail(LBM_SC_EINVAL, "a box appears twice");
+        if (!shape_fits(shape, b->box))
+            return fail(LBM_SC_EINVAL, "a box's rows are too long for the full-row tiles of this launch");
+        if (L.tile_x == 0 && L.rows == 8 && (!b->fp32 || b->math64))
+            return fail(LBM_SC_EINVAL, "full-row tiles with 8 nodes per thread need FP32 arithmetic");
+    }
+    if (nbox == 0 || nsteps == 0) return LBM_SC_OK;
+    hipStream_t st = boxes[0]->stream;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    HIP_TRY(hipStreamIsCapturing(st, &cs));
+    // a recorded launch has fixed source and destination buffers: only an even count leaves every
+    // box where a replay expects it
+    if (cs != hipStreamCaptureStatusNone && (nsteps & 1))
+        return fail(LBM_SC_EINVAL, "inside a stream capture nsteps must be even");
+    void* scratch = nullptr;
+    HIP_TRY(lbm::noalloc_scratch_address(&scratch));
+
+    // work list, written into the device array in batches carried by kernel arguments (no host
+    // staging buffer, no device allocation); phases align every box's current buffer with parity 0
+    const double item_work = chunk_work(boxes, (size_t)nbox, L);
+    lbm::DescBatch batch;
+    std::memset(&batch, 0, sizeof(batch));
+    unsigned nitems = 0;
+    for (int i = 0; i < nbox; ++i) {
+        const lbm::GroupBox d = box_desc(boxes[i], L, item_work, nitems);
+        if ((uint64_t)nitems + d.items > 0xFFFFFFFFull)
+            return fail(LBM_SC_EINVAL, "too many work items");
+        nitems += d.items;
+        if (batch.count == 0) batch.first = i;
+        batch.d[batch.count++] = d;
+        if (batch.count == lbm::NOALLOC_BATCH || i == nbox - 1) {
+            HIP_TRY(lbm::launch_put_descs(batch, scratch, st));
+            batch.count = 0;
+        }
+    }
+    const lbm::GroupBox* d_desc = static_cast<const lbm::GroupBox*>(scratch);
+    lbm::QueueState* d_queue = reinterpret_cast<lbm::QueueState*>(static_cast<char*>(scratch) +
+                                                                  lbm::noalloc_queue_offset());
+    if (L.persistent) {
+        // the queue ranges, with every counter at zero (the kernel's last workgroup clears them
+        // again after each launch)
+        const lbm::QueueState q = queue_ranges(
+            [&](size_t i) { return box_desc(boxes[i], L, item_work, 0); }, (size_t)nbox, nitems, L);
+        HIP_TRY(lbm::launch_put_queue(q, scratch, st));
+    }
+    const unsigned workers = L.workers ? (unsigned)L.workers : 256u;
+    const bool fp32 = boxes[0]->fp32, math64 = boxes[0]->math64;
+    int64_t done = 0;
+    hipError_t e = hipSuccess;
+    for (; done < nsteps && e == hipSuccess; ++done)
+        e = lbm::launch_step_group(fp32, math64, shape, d_desc, nbox, nitems, (int)(done & 1),
+                                   L.persistent, workers, d_queue, st);
+    if (e != hipSuccess) --done;   // the failed launch did not step
+    for (int i = 0; i < nbox; ++i) {
+        lbm_sc* h = boxes[i];
+        h->cur = (int)((h->cur + done) & 1);
+        h->step += done;
+    }
+    if (e != hipSuccess) return fail_hip("launch_step_group", e);
+    return LBM_SC_OK;
 }
 
 void lbm_sc_destroy(lbm_sc* h)

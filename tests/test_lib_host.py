@@ -161,6 +161,7 @@ def test_ctypes_signatures_match_the_header():
 
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"^#.*$", " ", text, flags=re.M)     # preprocessor lines
     protos = re.findall(r"([\w\s\*]+?)\b(lbm_sc_\w+)\s*\(([^)]*)\)\s*;", text)
     L = lbm.load()
     assert {name for _, name, _ in protos} == set(lbm.EXPORTS)
@@ -235,3 +236,24 @@ def test_every_header_declaration_is_documented():
         if j < 0 or not lines[j].rstrip().endswith("*/"):
             undocumented.append(line.strip())
     assert not undocumented, undocumented
+
+
+def test_noalloc_step_checks_its_arguments_before_any_device_work():
+    """The allocation-free multi-box step rejects more boxes than its fixed array holds, NULL
+    boxes and unsupported launch shapes before touching a box or the device; no boxes is a
+    no-op."""
+    import ctypes
+    base = dict(rows=2, z_chunk=32, xcd_remap=1, prefetch=0, persistent=0, workers=0,
+                graph_steps=0, waves=4, tile_x=64, items_per_cu=0)
+    lbm.lbm_sc_step_boxes_noalloc([], 4, **base)
+    cases = [([ctypes.c_void_p(8)] * (lbm.LBM_SC_NOALLOC_MAX_BOXES + 1), base, "at most 1024"),
+             ([ctypes.c_void_p(None)], base, "NULL"),
+             ([], dict(base, rows=3), "unsupported launch shape"),
+             ([], dict(base, persistent=1, workers=12), "workers")]
+    for hs, launch, msg in cases:
+        with pytest.raises(lbm.LbmScError) as e:
+            lbm.lbm_sc_step_boxes_noalloc(hs, 2, **launch)
+        assert e.value.code == lbm.LBM_SC_EINVAL
+        assert msg in lbm.lbm_sc_last_error()
+    with pytest.raises(lbm.LbmScError):
+        lbm.lbm_sc_step_boxes_noalloc([], -1, **base)
