@@ -296,11 +296,12 @@ int lbm_sc_step_boxes_noalloc(lbm_sc* const* boxes, int32_t nbox, int64_t nsteps
 
 /* Measurement helper, not part of the method: copy `bytes` (a multiple of 16; src and dst
  * 16-byte aligned device pointers that do not overlap) with a plain streaming kernel on `stream`
- * (hipStream_t or NULL for the null stream). Asynchronous. It measures the achievable HBM
- * bandwidth that the step kernel is compared with. LBM_SC_EINVAL, with nothing launched, on bad
- * sizes or alignment, or unless each of the two ranges lies inside one device allocation of the
- * current device. */
-int lbm_sc_stream_copy(const void* src, void* dst, size_t bytes, void* stream);
+ * (hipStream_t or NULL for the null stream), each lane moving lane_bytes (4, 8 or 16) per access.
+ * Asynchronous. It measures the achievable HBM bandwidth that the step kernel is compared with;
+ * the 4-byte form has the access width of the FP32 step. LBM_SC_EINVAL, with nothing launched, on
+ * bad sizes, alignment or lane_bytes, or unless each of the two ranges lies inside one device
+ * allocation of the current device. */
+int lbm_sc_stream_copy(const void* src, void* dst, size_t bytes, int32_t lane_bytes, void* stream);
 
 /* Describe the handle (coupling, densities, sizes, launch shape). */
 int lbm_sc_get_info(lbm_sc* h, lbm_sc_info* out);

@@ -115,7 +115,7 @@ def load():
     L.lbm_sc_set_step.argtypes = [_vp, _i64]
     L.lbm_sc_set_launch.argtypes = [_vp, P(LbmScLaunch)]
     L.lbm_sc_get_launch.argtypes = [_vp, P(LbmScLaunch)]
-    L.lbm_sc_stream_copy.argtypes = [_vp, _vp, ctypes.c_size_t, _vp]
+    L.lbm_sc_stream_copy.argtypes = [_vp, _vp, ctypes.c_size_t, _i32, _vp]
     L.lbm_sc_get_info.argtypes = [_vp, P(LbmScInfo)]
     L.lbm_sc_destroy.argtypes = [_vp]
     L.lbm_sc_destroy.restype = None
@@ -256,9 +256,10 @@ def lbm_sc_get_launch(h):
     return l.to_dict()
 
 
-def lbm_sc_stream_copy(src_ptr, dst_ptr, nbytes, stream=None):
-    """Streaming copy between device pointers (ints), e.g. torch tensors' data_ptr()."""
-    _check(load().lbm_sc_stream_copy(src_ptr, dst_ptr, nbytes, stream))
+def lbm_sc_stream_copy(src_ptr, dst_ptr, nbytes, stream=None, lane_bytes=4):
+    """Streaming copy of nbytes between device addresses (measurement helper); lane_bytes: 4, 8
+    or 16 bytes moved by each lane per access."""
+    _check(load().lbm_sc_stream_copy(src_ptr, dst_ptr, nbytes, int(lane_bytes), stream))
 
 
 def lbm_sc_get_info(h):

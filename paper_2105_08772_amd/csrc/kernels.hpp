@@ -141,7 +141,9 @@ hipError_t launch_observe(bool fp32, const BoxDesc& b, const void* src, double* 
                           double* scal, hipStream_t st);
 hipError_t launch_profile_line(const BoxDesc& b, const double* dn, const double* dpsi,
                                double* prof, double* probes, hipStream_t st);
-hipError_t launch_stream_copy(const void* src, void* dst, size_t bytes, hipStream_t st);
+// lane_bytes: bytes each lane moves per access (4, 8 or 16).
+hipError_t launch_stream_copy(const void* src, void* dst, size_t bytes, int lane_bytes,
+                              hipStream_t st);
 hipError_t launch_profile_planes(const BoxDesc& b, int axis, const double* dn, const double* dpsi,
                                  double* prof, double* probes, hipStream_t st);
 

@@ -944,9 +944,11 @@ int lbm_sc_get_launch(lbm_sc* h, lbm_sc_launch* out)
     return LBM_SC_OK;
 }
 
-int lbm_sc_stream_copy(const void* src, void* dst, size_t bytes, void* stream)
+int lbm_sc_stream_copy(const void* src, void* dst, size_t bytes, int32_t lane_bytes, void* stream)
 {
     if (!src || !dst) return fail(LBM_SC_EINVAL, "src or dst is NULL");
+    if (lane_bytes != 4 && lane_bytes != 8 && lane_bytes != 16)
+        return fail(LBM_SC_EINVAL, "lane_bytes must be 4, 8 or 16");
     if (bytes % 16 || ((uintptr_t)src | (uintptr_t)dst) % 16)
         return fail(LBM_SC_EINVAL, "bytes and both pointers must be multiples of 16");
     const char* s = (const char*)src;
@@ -954,7 +956,7 @@ int lbm_sc_stream_copy(const void* src, void* dst, size_t bytes, void* stream)
     if (s < d + bytes && d < s + bytes) return fail(LBM_SC_EINVAL, "src and dst overlap");
     if (int rc = check_device_range(src, bytes, "src")) return rc;
     if (int rc = check_device_range(dst, bytes, "dst")) return rc;
-    HIP_TRY(lbm::launch_stream_copy(src, dst, bytes, (hipStream_t)stream));
+    HIP_TRY(lbm::launch_stream_copy(src, dst, bytes, lane_bytes, (hipStream_t)stream));
     return LBM_SC_OK;
 }
 

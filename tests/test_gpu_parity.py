@@ -489,13 +489,17 @@ def test_unstable_state_is_reported():
 
 def test_stream_copy_helper():
     import torch
-    a = torch.arange(1 << 20, dtype=torch.float32, device="cuda")
-    b = torch.zeros_like(a)
-    lbm.lbm_sc_stream_copy(a.data_ptr(), b.data_ptr(), a.numel() * 4)
-    torch.cuda.synchronize()
-    assert torch.equal(a, b)
+    # 1 M floats plus a tail that is not a whole number of 1024-element blocks
+    a = torch.arange((1 << 20) + 4 * 333, dtype=torch.float32, device="cuda")
+    for lane in (4, 8, 16):
+        b = torch.zeros_like(a)
+        lbm.lbm_sc_stream_copy(a.data_ptr(), b.data_ptr(), a.numel() * 4, lane_bytes=lane)
+        torch.cuda.synchronize()
+        assert torch.equal(a, b), lane
     with pytest.raises(lbm.LbmScError):
         lbm.lbm_sc_stream_copy(a.data_ptr(), b.data_ptr(), 12)
+    with pytest.raises(lbm.LbmScError):
+        lbm.lbm_sc_stream_copy(a.data_ptr(), b.data_ptr(), 1 << 20, lane_bytes=2)
     # ranges that are not device memory, or run past their allocation, are refused before the
     # copy kernel could touch them
     host = torch.empty(1 << 22, dtype=torch.uint8, pin_memory=True)
