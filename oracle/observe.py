@@ -84,8 +84,10 @@ def surface_of_tension_numeric(dP, C, R_lo, R_hi, npts=201, rounds=4):
 
 
 def equimolar_radius(M, V, n_in, n_out):
-    """R_e from M = 4 pi R_e^3 n_in / 3 + (V - 4 pi R_e^3 / 3) n_out."""
-    v = 3.0 * (M - V * n_out) / (4.0 * np.pi * (n_in - n_out))
+    """R_e from M = 4 pi R_e^3 n_in / 3 + (V - 4 pi R_e^3 / 3) n_out (IEEE division: infinite or
+    NaN when n_in equals n_out, as in the library)."""
+    with np.errstate(divide="ignore", invalid="ignore"):
+        v = np.float64(3.0) * (M - V * n_out) / (np.float64(4.0 * np.pi) * (n_in - n_out))
     return float(np.cbrt(v))
 
 
