@@ -19,7 +19,11 @@ Stop rule (Sec. 4 convergence criteria read for a served workload):
                sign every step cancels); FP64 boxes must in addition keep their mass to mass_tol;
   unstable   - the observation saw a non-finite value or n <= 0;
   step_limit - the box reached max_steps without converging;
-  cancelled  - the request was cancelled (queued or running).
+  cancelled  - the request was cancelled (queued or running);
+  failed     - the backend raised its error while creating or observing the box (the error text
+               is kept as the criterion); the other requests keep being served. An error of a
+               multi-box step fails every box on the GPU (each gets its record and journal line)
+               and is raised again.
 Converged results also carry the paper's validity flag: every coordinate of the centre of mass
 within com_tol (1e-3) of the box centre.
 A box's evolution and stop decision depend only on its own state and step count, so its result is
@@ -44,6 +48,8 @@ class Request:
     seed: int
     arrival: float = 0.0        # seconds after the server's start
     psi: int = 0
+    n_in: float = 0.0           # initial densities inside/outside; both 0: flat coexistence
+    n_out: float = 0.0
 
 
 @dataclasses.dataclass
@@ -51,7 +57,7 @@ class Record:
     rid: int
     L: int
     status: str = "queued"      # queued, running, converged, evaporated, unstable, step_limit,
-                                # cancelled, rejected
+                                # cancelled, rejected, failed
     arrival: float = 0.0
     admitted: float = None
     finished: float = None
@@ -83,7 +89,7 @@ class GpuBackend:
         self.stream = stream or torch.cuda.Stream()
         self.prec = LBM_SC_FP32_SHIFTED if prec is None else prec
         self._Box, self._Group, self._config = Box, Group, config
-        self._error = LbmScError
+        self.error = LbmScError     # the error the scheduler treats as a failed request
         self._bubble, self._droplet = LBM_SC_BUBBLE, LBM_SC_DROPLET
         self._bytes = lbm_sc_device_bytes
         self.tau, self.width, self.noise_amp = tau, width, noise_amp
@@ -97,7 +103,8 @@ class GpuBackend:
         return self._config(r.L, psi=r.psi, geom=self._bubble if r.bubble else self._droplet,
                             prec=self.prec, tau=self.tau, g_over_gc=r.g_over_gc,
                             radius=r.radius, width=self.width, noise_amp=self.noise_amp,
-                            seed=r.seed, stream=self.stream.cuda_stream)
+                            seed=r.seed, n_in=r.n_in, n_out=r.n_out,
+                            stream=self.stream.cuda_stream)
 
     def bytes_needed(self, r):
         return int(self._bytes(self.config(r)))
@@ -123,7 +130,7 @@ class GpuBackend:
             self.fallen_back = None
         try:
             self.group.set(boxes)
-        except self._error:
+        except self.error:
             launch = self.group.launch()
             if launch["tile_x"] != 0:
                 raise
@@ -221,7 +228,7 @@ class Server:
         if status == "converged" and last is not None and "com" in last:
             c = [L // 2 for L in (req.L, req.L, req.L)]
             rec.valid = all(abs(x - y) <= self.com_tol for x, y in zip(last["com"], c))
-        if self.keep_final:
+        if self.keep_final and status != "failed":
             rec.final = self.b.snapshot(box)
         self.b.destroy(box)
         self.used -= rec.bytes
@@ -249,9 +256,16 @@ class Server:
         self.journal.write(json.dumps(line) + "\n")
         self.journal.flush()
 
+    def _fail(self, rec, err, now):
+        rec.status, rec.finished, rec.criterion = "failed", now, str(err)
+        if self.log:
+            self.log(f"request {rec.rid} failed: {err}")
+        self._write_journal(rec)
+
     def _admit(self):
         changed = False
         now = self._now()
+        error = getattr(self.b, "error", Exception)
         while self.queue and self.queue[0].arrival <= now:
             req = self.queue[0]
             rec = self.records[req.rid]
@@ -260,7 +274,12 @@ class Server:
                 rec.status, rec.finished = "cancelled", now
                 self._write_journal(rec)
                 continue
-            need = self.b.bytes_needed(req)
+            try:
+                need = self.b.bytes_needed(req)
+            except error as e:
+                self.queue.pop(0)
+                self._fail(rec, e, now)
+                continue
             if need > self.budget:
                 self.queue.pop(0)
                 rec.status, rec.finished, rec.criterion = "rejected", now, "larger than budget"
@@ -271,12 +290,20 @@ class Server:
             if self.max_active_allowed is not None and len(self.active) >= self.max_active_allowed:
                 break
             self.queue.pop(0)
-            box = self.b.create(req)
+            box = None
+            try:
+                box = self.b.create(req)
+                first = self.b.observe(box)
+            except error as e:
+                if box is not None:
+                    self.b.destroy(box)
+                rec.admitted = now
+                self._fail(rec, e, now)
+                continue
             rec.bytes = need
             self.used += need
             rec.admitted = now
             rec.status = "running"
-            first = self.b.observe(box)
             rec.contrast0 = abs(first["n_center"] - first["n_far"])
             self.active[req.rid] = (req, box, rec, first)
             changed = True
@@ -318,11 +345,18 @@ class Server:
                         self.sleep(wait)
                 continue
             keys = sorted(self.active)
-            if changed or keys != members:
-                self.b.set_active([self.active[k][1] for k in keys])
-                members = keys
-            self.max_active = max(self.max_active, len(keys))
-            self.b.step(self.chunk)
+            error = getattr(self.b, "error", Exception)
+            try:
+                if changed or keys != members:
+                    self.b.set_active([self.active[k][1] for k in keys])
+                    members = keys
+                self.max_active = max(self.max_active, len(keys))
+                self.b.step(self.chunk)
+            except error as e:
+                # the shared launch failed: no box on the GPU has a trustworthy state
+                for k in keys:
+                    self._retire(k, "failed", str(e))
+                raise
             for k in keys:
                 rec = self.active[k][2]
                 rec.steps += self.chunk
@@ -330,7 +364,12 @@ class Server:
             for k in keys:
                 rec = self.active[k][2]
                 if rec.steps % self.every == 0:
-                    status, crit = self._check(k, self.b.observe(self.active[k][1]))
+                    try:
+                        obs = self.b.observe(self.active[k][1])
+                    except error as e:
+                        self._retire(k, "failed", str(e))
+                        continue
+                    status, crit = self._check(k, obs)
                     if status:
                         self._retire(k, status, crit)
         self.wall = self._now()

@@ -222,7 +222,7 @@ def test_backend_leaves_the_xy_tile_fallback_when_the_wide_box_leaves():
             return dict(self.shape)
 
     be = object.__new__(serve.GpuBackend)
-    be.single, be.group, be.fallen_back, be._error = False, FakeGroup(), None, LbmScError
+    be.single, be.group, be.fallen_back, be.error = False, FakeGroup(), None, LbmScError
     chosen = be.group.launch()
     be.set_active(["small"])
     assert be.group.launch() == chosen
@@ -232,3 +232,108 @@ def test_backend_leaves_the_xy_tile_fallback_when_the_wide_box_leaves():
     assert be.group.launch()["tile_x"] == 64
     be.set_active(["small"])
     assert be.group.launch() == chosen and be.group.boxes == ["small"]
+
+
+class BackendError(RuntimeError):
+    pass
+
+
+class FailingBackend(ScriptedBackend):
+    """The scripted backend whose calls raise its error for chosen requests: bytes_needed, create
+    or the first observation at admission, an observation at a given step, or a multi-box step
+    once a given clock time is reached."""
+    error = BackendError
+
+    def __init__(self, clock, fail_bytes=(), fail_create=(), fail_first_obs=(), fail_obs_at=None,
+                 fail_step_at=None, **kw):
+        super().__init__(clock, **kw)
+        self.fail_bytes, self.fail_create = set(fail_bytes), set(fail_create)
+        self.fail_first_obs = set(fail_first_obs)
+        self.fail_obs_at = fail_obs_at or {}
+        self.fail_step_at = fail_step_at
+
+    def bytes_needed(self, r):
+        if r.rid in self.fail_bytes:
+            raise BackendError(f"invalid configuration of request {r.rid}")
+        return super().bytes_needed(r)
+
+    def create(self, r):
+        if r.rid in self.fail_create:
+            raise BackendError("out of device memory")
+        return super().create(r)
+
+    def observe(self, b):
+        rid = b.req.rid
+        if rid in self.fail_first_obs and b.steps == 0:
+            raise BackendError("observation failed")
+        if rid in self.fail_obs_at and b.steps >= self.fail_obs_at[rid]:
+            raise BackendError("observation failed")
+        return super().observe(b)
+
+    def step(self, n):
+        if self.fail_step_at is not None and self.clock.t >= self.fail_step_at:
+            raise BackendError("launch failed")
+        super().step(n)
+
+
+class ListJournal:
+    def __init__(self):
+        self.lines = []
+
+    def write(self, text):
+        self.lines.append(text)
+
+    def flush(self):
+        pass
+
+
+def test_backend_errors_at_admission_fail_only_that_request():
+    """A request whose memory estimate, creation or first observation raises the backend's
+    error is recorded as failed (with the error text and a journal line) and holds no memory;
+    a box created before the failing observation is destroyed; the others are served."""
+    import json
+    clock = Clock()
+    be = FailingBackend(clock, fail_bytes={1}, fail_create={2}, fail_first_obs={3})
+    journal = ListJournal()
+    srv = serve.Server(be, 10 ** 6, chunk=512, observe_every=2048, clock=clock, sleep=clock.sleep,
+                       journal=journal)
+    for k in range(5):
+        srv.submit(req(k, 10, 0.1 * k))
+    recs = {r.rid: r for r in srv.run()}
+    assert recs[0].status == "converged" and recs[4].status == "converged"
+    for rid, text in ((1, "invalid configuration"), (2, "out of device memory"),
+                      (3, "observation failed")):
+        assert recs[rid].status == "failed" and text in recs[rid].criterion, rid
+        assert recs[rid].bytes == 0 and recs[rid].finished is not None
+    assert srv.used == 0 and not be.live
+    lines = [json.loads(x) for x in journal.lines]
+    assert sorted(x["rid"] for x in lines) == [0, 1, 2, 3, 4]
+    assert {x["rid"]: x["status"] for x in lines}[2] == "failed"
+
+
+def test_backend_error_while_observing_a_running_box():
+    clock = Clock()
+    # request 1 never converges by itself; its observation at step 4096 raises
+    be = FailingBackend(clock, fail_obs_at={1: 4096}, never={1})
+    srv = serve.Server(be, 10 ** 6, chunk=512, observe_every=2048, clock=clock, sleep=clock.sleep)
+    for k in range(3):
+        srv.submit(req(k, 10, 0.0))
+    recs = {r.rid: r for r in srv.run()}
+    assert recs[1].status == "failed" and recs[1].steps == 4096
+    assert recs[0].status == recs[2].status == "converged"
+    assert srv.used == 0 and not be.live
+
+
+def test_backend_error_of_the_shared_step_fails_every_running_box_and_is_raised():
+    clock = Clock()
+    be = FailingBackend(clock, fail_step_at=2.0)
+    journal = ListJournal()
+    srv = serve.Server(be, 10 ** 6, chunk=512, observe_every=2048, clock=clock, sleep=clock.sleep,
+                       journal=journal, keep_final=True)
+    for k in range(3):
+        srv.submit(req(k, 10, 0.0))
+    with pytest.raises(BackendError):
+        srv.run()
+    assert all(srv.records[k].status == "failed" for k in range(3))
+    assert all(srv.records[k].final is None for k in range(3))
+    assert len(journal.lines) == 3 and srv.used == 0 and not be.live
