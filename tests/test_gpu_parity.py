@@ -5,7 +5,8 @@ Bars (written into each test):
     identical state, and the same along the 2000-step 32^3 droplet;
   - FP32-shifted storage: one step from the identical (FP32-representable) state within a bound
     derived from single-precision rounding of the collision (a few ulp of the largest shifted
-    population), and after 2000 steps densities within 1e-4 n_l and dP within 1e-3 of FP64;
+    population), and after 2000 steps densities, dP and mass within three times the measured
+    differences from FP64 (FP32_DROPLET_BOUNDS);
   - FP32-shifted storage with FP64 arithmetic: one step within half an ulp of the oracle per
     stored population (the rest population within the sum of the others' rounding errors);
   - launch shapes: bitwise identical results (the per-node arithmetic does not depend on them).
@@ -88,8 +89,11 @@ def test_one_step_fp32_shifted(dims, tau, prefetch):
         g = b.get()
     ref = core.step(f, G, tau, 0)
     # single-precision collision: each shifted population carries a few roundings of quantities
-    # no larger than the largest |f|; 1e-6 relative to max |f| leaves a margin of ~10 ulp
-    assert rel_err(g, ref) <= 1e-6
+    # no larger than the largest |f| (measured at most 4.0e-8 of max |f| over these cases; the
+    # bound is three times that, about 2 ulp of the largest population)
+    err = rel_err(g, ref)
+    say(f"  max |f_gpu - f_oracle| / max |f_oracle| = {err:.3e}")
+    assert err <= 1.2e-7
     # mass per node is closed exactly up to the last rounding
     n_g = g.sum(axis=0)
     n_r = ref.sum(axis=0)
@@ -427,9 +431,16 @@ def test_slab_along_x_equals_slab_along_z():
     assert np.abs(pz[3] - px[1]).max() < 1e-13   # P_N: P^zz of the z slab = P^xx of the x slab
 
 
+# FP32 against FP64 on the 32^3 droplet after 2000 steps, three times the measured values:
+# largest density difference / n_l, relative dP difference, relative mass drift of the FP32 run
+# (measured: FP32 arithmetic 8.0e-7, 9.6e-7, 8.2e-10; FP64 arithmetic 5.2e-7, 4.4e-7, 9.2e-9)
+FP32_DROPLET_BOUNDS = {lbm.LBM_SC_FP32_SHIFTED: (2.5e-6, 3e-6, 3e-9),
+                       lbm.LBM_SC_FP32_SHIFTED_MATH64: (1.6e-6, 1.4e-6, 3e-8)}
+
+
 def test_fp32_vs_fp64_droplet_after_2000_steps():
     """FP32-shifted populations (single- or double-precision arithmetic) against FP64 on the 32^3
-    droplet: densities within 1e-4 n_l and dP within 1e-3 dP after 2000 steps."""
+    droplet: densities, dP and the mass drift after 2000 steps within FP32_DROPLET_BOUNDS."""
     say("32^3 droplet FP32-shifted vs FP64, 2000 steps")
     res = {}
     for prec in (lbm.LBM_SC_FP64, lbm.LBM_SC_FP32_SHIFTED, lbm.LBM_SC_FP32_SHIFTED_MATH64):
@@ -446,9 +457,10 @@ def test_fp32_vs_fp64_droplet_after_2000_steps():
         say(f"prec {prec}: max |n32-n64| / n_l = {np.abs(n32 - n64).max() / nl:.3e}, "
             f"|dP32-dP64|/dP64 = {abs(o32['dP'] - o64['dP']) / o64['dP']:.3e}, "
             f"relative mass drift {drift:.3e}")
-        assert np.abs(n32 - n64).max() <= 1e-4 * nl
-        assert abs(o32["dP"] - o64["dP"]) <= 1e-3 * o64["dP"]
-        assert drift <= 2e-6
+        b_n, b_dp, b_drift = FP32_DROPLET_BOUNDS[prec]
+        assert np.abs(n32 - n64).max() <= b_n * nl
+        assert abs(o32["dP"] - o64["dP"]) <= b_dp * o64["dP"]
+        assert drift <= b_drift
 
 
 def test_fp32_mass_drift_of_a_converged_droplet():

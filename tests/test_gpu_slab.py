@@ -2,23 +2,26 @@
 exp psi, G/G_c in {1.1, 1.2, 1.4, 1.6}, 20000 steps, FP64 and FP32-shifted populations.
 
 An x-y uniform D3Q19 state evolves exactly as D1Q3 (pinned on the CPU against the oracle), so
-the full-size FP64 slab is checked node by node against the oracle's independent D1Q3 code:
-one step from the GPU's own state at step 19999 within 1e-11 relative (the per-step bar), and
-the whole 20000-step trajectory from the common initial profile within 1e-9 relative (rounding
-orders differ between the two codes and the differences accumulate over 20000 steps).
-FP32-shifted is compared with FP64 on the coexistence densities and sigma_0 (flat-interface
-integral of Sec. 4): max |n32 - n64| <= 1e-4 n_l and |sigma0_32 - sigma0_64| <= 1e-3 sigma0_64
-after 20000 steps.
+the full-size FP64 slab is checked node by node against the oracle's independent D1Q3 code: one
+step from the GPU's own state at step 19999 within 1e-11 relative (the per-step bar), and the
+whole 20000-step trajectory from the common initial profile within 1e-10 relative (rounding
+orders differ between the two codes; measured 2.2e-11, 2.2e-11, 8.4e-12); the GPU's flat
+sigma_0, P_N spread and bulk densities at step 20000 are compared with those of the D1Q3
+trajectory measured by the independent flat-interface reduction (Sec. 4 sigma_0 integral).
 
-At G/G_c = 1.6 the slab is still far from equilibrium after 20000 steps: plane-averaged P_N,
-which a flat interface in mechanical equilibrium holds constant, still varies by ~9 % of p0 (an
-undamped long-wavelength oscillation of the 256-long box). There any rounding-level difference
-becomes a phase difference of that oscillation, so FP32 and FP64 are compared on what the phase
-does not change by more than the oscillation itself: the bulk densities within the FP64 run's
-own P_N swing (relative to p0), the profiles within 0.15 n_l and sigma_0 within 4e-2 (measured
-FP64 trajectory difference 1.7e-8; FP32-FP64 profile difference 2-5e-2 n_l at the moving
-interfaces, bulk densities up to 6 %, sigma_0 up to 1.3e-2, depending on the FP32 rounding).
-The per-step bar is the same for every coupling.
+FP32-shifted against FP64 at G/G_c <= 1.4, after 20000 steps: profiles within 5e-5 n_l (measured
+1.5e-5, 1.6e-5, 4.3e-6), bulk densities within 4e-6 relative (measured <= 1.3e-6) and sigma_0 within
+3e-6 relative (measured 2.7e-7, 3.0e-7, 8.8e-7).
+
+At G/G_c = 1.6 the flat state does not settle at tau = 1: in the exact D1Q3 reduction (FP64)
+the plane-averaged P_N still varies by about 10 % of p0 after 2e5 steps, the bulk densities
+swing by 1-2 % and a staggered momentum mode grows out of rounding from 1e-16 to 1e-2 by step
+56000. Trajectories that start within rounding of each other separate after about 1e4 steps
+(FP64 GPU against D1Q3: 1.7e-8 at step 20000). FP32 and FP64 are therefore compared on run
+averages that this separation does not move: n_l, n_g, sigma_0 and p0 averaged over observations
+every 10 steps of the whole run (measured on the GPU: 1.5e-4, 1.0e-3, 4.0e-4 and 1.0e-3 relative;
+emulating FP32 storage in the D1Q3 code gives 1.6e-4, 9e-4, 1.2e-3 and 8.7e-4; the bounds are three
+times the GPU's values).
 """
 import sys
 
@@ -55,6 +58,25 @@ def project_z(f):
     return out, spread
 
 
+AVG_EVERY = 10
+
+
+def run_average(b, steps, every):
+    """Step the slab `steps` times, observing every `every` steps; the averages over those
+    observations of n_l (slab centre), n_g (plane 0), sigma_0 and p0 (mean of P_N over the planes)."""
+    acc = {"n_l": 0.0, "n_g": 0.0, "sigma0": 0.0, "p0": 0.0}
+    k = 0
+    for _ in range(steps // every):
+        b.step(every)
+        o, prof = b.observables()
+        acc["n_l"] += prof[0][NZ // 2]
+        acc["n_g"] += prof[0][0]
+        acc["sigma0"] += o["sigma0_flat"]
+        acc["p0"] += float(np.mean(prof[3]))
+        k += 1
+    return {key: v / k for key, v in acc.items()}
+
+
 @pytest.fixture(scope="module")
 def slabs():
     res = {}
@@ -65,12 +87,17 @@ def slabs():
             with lbm.Box(slab_cfg(ratio, prec)) as b:
                 info = b.info()
                 f0 = project_z(b.get()) if fp64 else None
-                b.step(STEPS - 1)
+                avg = None
+                if ratio == 1.6:
+                    avg = run_average(b, STEPS - AVG_EVERY, AVG_EVERY)
+                    b.step(AVG_EVERY - 1)
+                else:
+                    b.step(STEPS - 1)
                 fa = project_z(b.get()) if fp64 else None
                 b.step(1)
                 obs, prof = b.observables()
                 f = project_z(b.get()) if fp64 else None
-            res[ratio, prec] = dict(info=info, f0=f0, fa=fa, obs=obs, prof=prof, f=f)
+            res[ratio, prec] = dict(info=info, f0=f0, fa=fa, obs=obs, prof=prof, f=f, avg=avg)
     return res
 
 
@@ -92,14 +119,28 @@ def test_fp64_slab_equals_independent_d1q3(slabs, ratio):
     for _ in range(STEPS):
         d = reduced.D1Q3.step(d, G, 1.0, core.PSI_EXP)
     err = float(np.abs(g - d).max() / np.abs(d).max())
+    # flat-interface observables of the D1Q3 trajectory (independent D2Q9 reduction, Sec. 4)
+    fl = reduced.flat_observables(d, G, core.PSI_EXP)
+    o, prof = r["obs"], r["prof"]
+    ds = abs(o["sigma0_flat"] - fl["sigma0"]) / fl["sigma0"]
+    dspread = abs(o["pn_spread"] - fl["pn_spread"]) / fl["p0"]
+    dn = max(abs(prof[0][NZ // 2] - fl["n_l"]) / fl["n_l"], abs(prof[0][0] - fl["n_g"]) / fl["n_g"])
     say(f"G/Gc={ratio}: FP64 slab vs D1Q3: one step {one:.2e}; {STEPS}-step trajectory {err:.2e};"
-        f" x-y spread {spread:.1e}")
+        f" x-y spread {spread:.1e}; sigma0 {o['sigma0_flat']:.10f} vs {fl['sigma0']:.10f} "
+        f"({ds:.2e}), P_N spread/p0 {dspread:.2e}, bulk densities {dn:.2e}")
     assert spread_a <= 1e-14 and spread <= 1e-14
     assert one <= 1e-11
-    assert err <= (5e-8 if ratio == 1.6 else 1e-9)
+    chaotic = ratio == 1.6
+    assert err <= (5e-8 if chaotic else 1e-10)
+    # three times the measured differences (sigma_0: 4.8e-14, 3.6e-13, 1.4e-12, 1.2e-8; P_N
+    # spread / p0: 3.0e-15, 2.0e-16, 7.7e-12, 3.0e-8; bulk densities: 8.7e-15, 2.2e-14, 2.3e-12,
+    # 5.5e-9 at G/G_c = 1.1, 1.2, 1.4, 1.6)
+    assert ds <= (4e-8 if chaotic else 5e-12)
+    assert dspread <= (1e-7 if chaotic else 3e-11)
+    assert dn <= (2e-8 if chaotic else 1e-11)
 
 
-@pytest.mark.parametrize("ratio", [1.1, 1.2, 1.4, 1.6])
+@pytest.mark.parametrize("ratio", [1.1, 1.2, 1.4])
 def test_fp32_shifted_slab_against_fp64(slabs, ratio):
     r64 = slabs[ratio, lbm.LBM_SC_FP64]
     r32 = slabs[ratio, lbm.LBM_SC_FP32_SHIFTED]
@@ -109,20 +150,34 @@ def test_fp32_shifted_slab_against_fp64(slabs, ratio):
     s64 = r64["obs"]["sigma0_flat"]
     s32 = r32["obs"]["sigma0_flat"]
     dn = float(np.abs(n32 - n64).max())
-    say(f"G/Gc={ratio}: n_l {n64[128]:.8f} n_g {n64[0]:.8f} sigma0 {s64:.8f} "
-        f"(FP32: {n32[128]:.8f} {n32[0]:.8f} {s32:.8f}); max|dn|/n_l {dn / nl:.2e}, "
-        f"|dsigma0|/sigma0 {abs(s32 - s64) / s64:.2e}; P_N spread/p0 FP64 "
+    bulk = [abs(n32[z] - n64[z]) / n64[z] for z in (NZ // 2, 0)]
+    say(f"G/Gc={ratio}: n_l {n64[NZ // 2]:.8f} n_g {n64[0]:.8f} sigma0 {s64:.8f} "
+        f"(FP32: {n32[NZ // 2]:.8f} {n32[0]:.8f} {s32:.8f}); max|dn|/n_l {dn / nl:.2e}, "
+        f"bulk {max(bulk):.2e}, |dsigma0|/sigma0 {abs(s32 - s64) / s64:.2e}; P_N spread/p0 FP64 "
         f"{r64['obs']['pn_spread'] / r64['obs']['P_out']:.2e}")
-    unconverged = ratio == 1.6
-    assert dn <= (0.15 if unconverged else 1e-4) * nl
-    assert abs(s32 - s64) <= (4e-2 if unconverged else 1e-3) * s64
-    # bulk coexistence densities: slab centre (liquid) and the far plane (gas); unconverged, within
-    # the oscillation's own relative pressure swing
-    swing = r64["obs"]["pn_spread"] / r64["obs"]["P_out"]
-    for z in (128, 0):
-        assert abs(n32[z] - n64[z]) <= (swing if unconverged else 1e-4) * n64[z]
+    assert dn <= 5e-5 * nl
+    assert max(bulk) <= 4e-6
+    assert abs(s32 - s64) <= 3e-6 * s64
     # both slabs keep their mass
     for r in (r64, r32):
         o = r["obs"]
-        tol = 1e-12 if r is r64 else 1e-6
+        tol = 1e-12 if r is r64 else 1e-8
+        assert abs(o["mass"] - o["mass0"]) <= tol * o["mass0"]
+
+
+def test_fp32_shifted_slab_against_fp64_run_averages_at_deep_quench(slabs):
+    """G/G_c = 1.6: the flat state keeps moving (see the module docstring), so FP32 and FP64 are
+    compared on averages over observations every 10 steps of the whole 20000-step run."""
+    a64 = slabs[1.6, lbm.LBM_SC_FP64]["avg"]
+    a32 = slabs[1.6, lbm.LBM_SC_FP32_SHIFTED]["avg"]
+    rel = {k: abs(a32[k] - a64[k]) / abs(a64[k]) for k in a64}
+    say("G/Gc=1.6 run averages FP64 " + ", ".join(f"{k} {v:.8f}" for k, v in a64.items()) +
+        "; FP32 relative differences " + ", ".join(f"{k} {v:.2e}" for k, v in rel.items()))
+    # three times the measured differences (1.5e-4, 1.0e-3, 4.0e-4, 1.0e-3)
+    bounds = {"n_l": 5e-4, "n_g": 3e-3, "sigma0": 1.2e-3, "p0": 3e-3}
+    for k, bound in bounds.items():
+        assert rel[k] <= bound, k
+    for prec in (lbm.LBM_SC_FP64, lbm.LBM_SC_FP32_SHIFTED):
+        o = slabs[1.6, prec]["obs"]
+        tol = 1e-12 if prec == lbm.LBM_SC_FP64 else 1e-8
         assert abs(o["mass"] - o["mass0"]) <= tol * o["mass0"]
