@@ -125,6 +125,19 @@ constexpr int OBS_BLOCKS = 512;
 // sbuf: index (0 or 1) of the source buffer, which selects the dither seed b.tick[sbuf].
 hipError_t launch_step(bool fp32, bool math64, const BoxDesc& b, const StepShape& s, int sbuf,
                        const void* src, void* dst, hipStream_t st);
+// The same per precision (step_f32.hip: FP32 storage and arithmetic; step_m64.hip: FP32 storage,
+// FP64 arithmetic; step_f64.hip: FP64), called by launch_step / launch_step_group after the shape
+// check.
+#define LBM_STEP_DECL(tag)                                                                          \
+    hipError_t launch_step_##tag(const BoxDesc& b, const StepShape& s, int sbuf, const void* src,  \
+                                 void* dst, hipStream_t st);                                       \
+    hipError_t launch_group_##tag(const StepShape& s, const GroupBox* boxes, int nbox,             \
+                                  unsigned nitems, int parity, int persistent, unsigned workers,   \
+                                  QueueState* q, hipStream_t st);
+LBM_STEP_DECL(f32)
+LBM_STEP_DECL(m64)
+LBM_STEP_DECL(f64)
+#undef LBM_STEP_DECL
 // Multi-box step. nitems work items; persistent: grid of `workers` workgroups over the queues.
 hipError_t launch_step_group(bool fp32, bool math64, const StepShape& s, const GroupBox* boxes, int nbox,
                              unsigned nitems, int parity, int persistent, unsigned workers,

@@ -1,0 +1,19 @@
+// Fused step kernels instantiated for FP32 storage and arithmetic.
+#include "step_kernels.hpp"
+
+namespace lbm {
+
+hipError_t launch_step_f32(const BoxDesc& b, const StepShape& s, int sbuf, const void* src,
+                           void* dst, hipStream_t st)
+{
+    return launch_step_impl<float, float>(b, s, sbuf, src, dst, st);
+}
+
+hipError_t launch_group_f32(const StepShape& s, const GroupBox* boxes, int nbox, unsigned nitems,
+                            int parity, int persistent, unsigned workers, QueueState* q,
+                            hipStream_t st)
+{
+    return launch_group_shape<float, float>(s, boxes, nbox, nitems, parity, persistent, workers, q, st);
+}
+
+}  // namespace lbm
