@@ -27,12 +27,17 @@ METRIC = ("MLUPS + % of HBM roofline (1 GPU); batched droplets/hour and p50/p99 
           "time-to-equilibrium")
 HBM_PEAK_GBPS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step_droplet256_fp32.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_2105_08772_amd", "csrc", "kernels.hip")
+KERNEL_SRC = [os.path.join(ROOT, "paper_2105_08772_amd", "csrc", n)
+              for n in ("step_kernels.hpp", "kernels.hpp", "d3q19.hpp")]
 
 
 def kernel_hash():
-    with open(KERNEL_SRC, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+    """Hash of the sources of the step kernels (their template code, layout and constants)."""
+    h = hashlib.sha256()
+    for p in KERNEL_SRC:
+        with open(p, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(nodes, prec, launch):
@@ -250,7 +255,9 @@ def run_served(args, torch, lbm, log, capacity_mlups=None):
         journal.close()
     summ = srv.summary()
     log("served: FP64 single-box path, one request at a time")
-    srv64, recs64, _ = serve_all(serve.GpuBackend(prec=lbm.LBM_SC_FP64, single=True), max_active=1)
+    # the FP64 boxes must also keep their mass to 1e-12 (the served configuration's mass gate)
+    srv64, recs64, _ = serve_all(serve.GpuBackend(prec=lbm.LBM_SC_FP64, single=True), max_active=1,
+                                 mass_tol=1e-12)
     summ64 = srv64.summary()
     errs = []
     for a, b in zip(recs, recs64):
@@ -301,8 +308,12 @@ def run_tolman(args, torch, lbm, log):
                        "{41,47,55,61,67,77,87,103,123,157,201,251} x {droplet,bubble}, R=L/4, tanh width "
                        "1, served together until |dP change|/dP < 1e-5 per 2048 steps; "
                        "FP32-shifted and FP64 sweeps"}
-    for name, psi in (("exp", lbm.LBM_SC_PSI_EXP), ("oneminus", lbm.LBM_SC_PSI_ONEMINUS)):
+    names = [n for n in ("exp", "oneminus") if args.tolman_psi in ("both", n)]
+    for name in names:
+        psi = lbm.LBM_SC_PSI_EXP if name == "exp" else lbm.LBM_SC_PSI_ONEMINUS
         out[name] = tolman_sweep(torch, lbm, log, psi)
+    if len(names) < 2:
+        return out
     pref = {}
     for name in ("exp", "oneminus"):
         pref[name] = {g: c["flat_sigma0"] / (float(g) - 1) ** 1.5
@@ -406,6 +417,52 @@ def tolman_sweep(torch, lbm, log, psi):
             out["delta_exponent"] = analysis.scaling_exponent(
                 x, [fits32[round(g, 10)]["delta"] for g in gs])["exponent"]
     return out
+
+
+def run_oneminus(args, torch, lbm, stream, steps):
+    """The same 256^3 droplet with the second pseudopotential of Sec. 4, psi = 1 - exp(-n)
+    (G/G_c = 1.3, its own flat coexistence densities), in the main run's precision and launch:
+    `steps` steps with an FP64 observation every 2048 (wall clock) and the step kernel's average
+    duration over back-to-back steps (HIP events on the library's stream)."""
+    prec = {"fp32": lbm.LBM_SC_FP32_SHIFTED, "fp32m64": lbm.LBM_SC_FP32_SHIFTED_MATH64,
+            "fp64": lbm.LBM_SC_FP64}[args.prec]
+    L = args.size
+    cfg = lbm.config(L, L, L, psi=lbm.LBM_SC_PSI_ONEMINUS, geom=lbm.LBM_SC_DROPLET, prec=prec,
+                     tau=1.0, g_over_gc=1.3, radius=args.radius, width=2.0, noise_amp=1e-6,
+                     seed=3, stream=stream.cuda_stream)
+    with lbm.Box(cfg) as box:
+        info = box.info()
+        box.step(128)
+        box.observables(profile=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        done = 0
+        while done < steps:
+            n = min(2048 - done % 2048, steps - done)
+            box.step(n)
+            done += n
+            if done % 2048 == 0:
+                box.observables(profile=False)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        box.step(1024)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t_step = e0.elapsed_time(e1) / 1e3 / 1024
+        obs, _ = box.observables(profile=False)
+    return {"workload": f"droplet {L}^3 periodic, {PREC_NAMES[args.prec]} populations, "
+                        f"psi=1-exp(-n), G/G_c=1.3, R={args.radius:g}, tanh width 2, noise 1e-6 "
+                        f"seed 3, tau=1, FP64 observables every 2048 steps",
+            "n_in": info["n_in"], "n_out": info["n_out"], "steps": steps,
+            "MLUPS": round(info["nodes"] * steps / wall / 1e6, 1),
+            "kernel_ms": round(t_step * 1e3, 5),
+            "kernel_GBps": round(info["bytes_per_step"] / t_step / 1e9, 1),
+            "kernel_frac_of_8TBps": round(info["bytes_per_step"] / t_step / 1e9 / HBM_PEAK_GBPS, 4),
+            "checks": {"finite": obs["finite"],
+                       "mass_drift_rel": abs(obs["mass"] - obs["mass0"]) / obs["mass0"],
+                       "dP": obs["dP"]}}
 
 
 def cpu_model():
@@ -518,8 +575,9 @@ def main():
     ap.add_argument("--copy-reps", type=int, default=5)
     ap.add_argument("--copy-lane", type=int, default=4, choices=[4, 8, 16],
                     help="bytes each lane of the copy kernel moves per access (--mode copy)")
-    ap.add_argument("--served-count", type=int, default=0,
-                    help="requests of the served workload to run after the main timing (0 = skip)")
+    ap.add_argument("--served-count", type=int, default=32,
+                    help="requests of the served workload to run after the main timing (0 = skip;"
+                         " default: 32)")
     ap.add_argument("--served-rate", type=float, default=1.0,
                     help="request arrival rate (1/s); the default offers about 0.8 of the batched "
                          "throughput")
@@ -530,6 +588,11 @@ def main():
                          "batched workload is not run in the same invocation")
     ap.add_argument("--tolman", action="store_true",
                     help="run the scaled droplet/bubble sweep and the Tolman analysis")
+    ap.add_argument("--tolman-psi", choices=["both", "exp", "oneminus"], default="both",
+                    help="pseudopotentials of the Tolman sweep")
+    ap.add_argument("--oneminus-steps", type=int, default=4096,
+                    help="steps of the same 256^3 droplet with psi = 1 - exp(-n) timed after the "
+                         "main run (0 = skip)")
     ap.add_argument("--batched-steps", type=int, default=20000,
                     help="steps of the batched 64-box workload measured after the main timing "
                          "(0 = skip; default: the configuration's 20000)")
@@ -677,11 +740,15 @@ def main():
             "kernel_ms": round(step_s * 1e3, 5),
             "bytes_per_launch": bytes_per_step,
             "stream_copy_GBps": copy_bw,
+            "frac_of_best_copy": round(achieved / copy_bw["best"], 4) if copy_bw else None,
         },
         "checks": {"finite": obs["finite"],
                    "mass_drift_rel": abs(obs["mass"] - obs["mass0"]) / obs["mass0"],
                    "dP": obs["dP"], "R_s": obs["R_s"]},
     }
+    if args.oneminus_steps > 0 and args.psi == "exp":
+        print("# 256^3 droplet with psi = 1 - exp(-n)", file=sys.stderr, flush=True)
+        out["psi_oneminus"] = run_oneminus(args, torch, lbm, stream, args.oneminus_steps)
     if args.batched_steps > 0:
         out["batched"] = run_batched(args, torch, lbm, stream, args.batched_steps,
                                      lambda m: print(m, file=sys.stderr, flush=True))
