@@ -119,8 +119,9 @@ typedef struct {
  * unknown enums, radius/width <= 0 for DROPLET/BUBBLE/SLAB, g_over_gc <= 1 when the densities must
  * come from lbm_sc_coexistence; also for boxes of more than 2^31 nodes or whose z-planes are so
  * large that the 19 populations of one plane exceed 4 GiB, i.e. beyond about 53 M (FP32 storage)
- * or 26 M (FP64) nodes per plane), allocates two population buffers and the observation scratch on
- * the current HIP device (LBM_SC_ENOMEM), and builds the initial state on the device: the tanh
+ * or 26 M (FP64) nodes per plane), allocates two population buffers and the box's small
+ * observation buffers (among them the last observed velocity, 24 bytes per node) on the current
+ * HIP device (LBM_SC_ENOMEM), and builds the initial state on the device: the tanh
  * profile plus noise, psi, the force of Eq. (SCForce), and f = f_eq(n, u = -F/(2n)) so that the
  * physical velocity (sum xi f + F/2)/n is zero. Returns after the work is enqueued and *out set.
  * On failure *out is NULL and nothing is leaked. */
@@ -131,8 +132,8 @@ int lbm_sc_create(const lbm_sc_config* cfg, lbm_sc** out);
  * the current device, 256-byte aligned, not overlapping, each with at least
  * lbm_sc_population_bytes(cfg) bytes (`bytes`) inside its allocation. The library uses them in
  * place, never frees them, and does not keep them beyond lbm_sc_destroy; the caller keeps them
- * alive until then. The observation scratch is still allocated by the library (device_bytes of
- * lbm_sc_get_info counts only that). Work of other streams on a or b must have finished before
+ * alive until then. The observation buffers are still allocated by the library (device_bytes of
+ * lbm_sc_get_info counts only those). Work of other streams on a or b must have finished before
  * this call (the initial state is written on the box's stream, unordered with other streams).
  * LBM_SC_EINVAL, with nothing allocated, if a buffer is NULL, misaligned, too small, not device
  * memory of the current device, or the two overlap. */
@@ -321,9 +322,18 @@ const char* lbm_sc_last_error(void);
  * for an unknown psi. Host only. */
 double lbm_sc_gc(int32_t psi);
 
-/* Device memory a box with this configuration will hold (populations, observation scratch and
- * small buffers), in bytes, without allocating anything; used to admit work by free HBM. Returns
- * a negative lbm_sc_status if cfg is invalid. Host only. */
+/* Bytes per node of the observation workspace shared by the boxes of one device (below). */
+#define LBM_SC_OBS_WORKSPACE_BYTES_PER_NODE 40
+
+/* Device memory a box with this configuration will hold (populations, the last observed velocity
+ * and small buffers), in bytes, without allocating anything; used to admit work by free HBM.
+ * Not counted: the observation workspace that the boxes of one device share (density, psi and
+ * momentum of every node, LBM_SC_OBS_WORKSPACE_BYTES_PER_NODE per node of the largest box
+ * observed, created with the first
+ * box, get or set that needs it and freed with the device's last box); calls that use it
+ * (create, observables, get and set populations) on boxes of one device take turns, each holding
+ * it until its own stream has drained. Returns a negative lbm_sc_status if cfg is invalid. Host
+ * only. */
 int64_t lbm_sc_device_bytes(const lbm_sc_config* cfg);
 
 /* Flat-interface coexistence densities and pressure for G = g_over_gc * G_c (the "equilibrium

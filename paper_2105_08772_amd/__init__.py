@@ -389,6 +389,7 @@ def lbm_sc_group_destroy(g):
 
 
 LBM_SC_NOALLOC_MAX_BOXES = 1024
+LBM_SC_OBS_WORKSPACE_BYTES_PER_NODE = 40
 
 
 def lbm_sc_step_boxes_noalloc(handles, nsteps, **launch):

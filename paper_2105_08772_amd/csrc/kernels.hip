@@ -209,10 +209,13 @@ __device__ __forceinline__ double com_offset(int v, int L)
     return (2 * d == L || 2 * d == -L) ? 0.0 : (double)d;
 }
 
+// Force, physical velocity and the FP64 reductions of one observation. dj holds the momentum
+// sum_i xi_i f_i (from k_obs_pull); uprev holds the velocity of the previous observation and is
+// overwritten, node by node, with this one's (each node is read and written by one thread).
 __global__ __launch_bounds__(256) void k_obs_reduce(BoxDesc b, const double* __restrict__ dn,
                                                     const double* __restrict__ dpsi,
-                                                    double* __restrict__ du,
-                                                    const double* __restrict__ duprev,
+                                                    const double* __restrict__ dj,
+                                                    double* __restrict__ uprev,
                                                     int has_prev, double* __restrict__ parts)
 {
     double acc[OBS_PARTS];
@@ -231,11 +234,8 @@ __global__ __launch_bounds__(256) void k_obs_reduce(BoxDesc b, const double* __r
         const double g = -b.G * dpsi[k];
         const double Fx = g * Sx, Fy = g * Sy, Fz = g * Sz;
         const double n = dn[k];
-        const double px = du[k] + 0.5 * Fx, py = du[N + k] + 0.5 * Fy, pz = du[2 * N + k] + 0.5 * Fz;
+        const double px = dj[k] + 0.5 * Fx, py = dj[N + k] + 0.5 * Fy, pz = dj[2 * N + k] + 0.5 * Fz;
         const double ux = px / n, uy = py / n, uz = pz / n;
-        du[k] = ux;
-        du[N + k] = uy;
-        du[2 * N + k] = uz;
         acc[P_MASS] += n;
         acc[P_MX] += px;
         acc[P_MY] += py;
@@ -244,11 +244,14 @@ __global__ __launch_bounds__(256) void k_obs_reduce(BoxDesc b, const double* __r
         acc[P_CY] += n * com_offset(y, b.ny);
         acc[P_CZ] += n * com_offset(z, b.nz);
         if (has_prev) {
-            const double ex = fabs(ux - duprev[k]), ey = fabs(uy - duprev[N + k]),
-                         ez = fabs(uz - duprev[2 * N + k]);
+            const double ex = fabs(ux - uprev[k]), ey = fabs(uy - uprev[N + k]),
+                         ez = fabs(uz - uprev[2 * N + k]);
             acc[P_DU] += ex + ey + ez;
             acc[P_DMAX] = fmax(acc[P_DMAX], fmax(ex, fmax(ey, ez)));
         }
+        uprev[k] = ux;
+        uprev[N + k] = uy;
+        uprev[2 * N + k] = uz;
         const bool ok = (n > 0.0) && isfinite(n) && isfinite(ux) && isfinite(uy) && isfinite(uz);
         if (!ok) acc[P_BAD] += 1.0;
         acc[P_NMIN] = fmin(acc[P_NMIN], n);
@@ -543,20 +546,20 @@ hipError_t launch_set(bool fp32, const BoxDesc& b, int i, const double* in, void
 }
 
 hipError_t launch_observe(bool fp32, const BoxDesc& b, const void* src, double* dn, double* dpsi,
-                          double* du, const double* duprev, int has_prev, double* parts,
+                          double* dj, double* uprev, int has_prev, double* parts,
                           double* scal, hipStream_t st)
 {
     const unsigned g = blocks_for(b.n, 256) < 4096u ? blocks_for(b.n, 256) : 4096u;
     if (fp32)
         hipLaunchKernelGGL(k_obs_pull<float>, dim3(g), dim3(256), 0, st, b, (const float*)src, dn,
-                           dpsi, du);
+                           dpsi, dj);
     else
         hipLaunchKernelGGL(k_obs_pull<double>, dim3(g), dim3(256), 0, st, b, (const double*)src,
-                           dn, dpsi, du);
+                           dn, dpsi, dj);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_obs_reduce, dim3(OBS_BLOCKS), dim3(256), 0, st, b, (const double*)dn,
-                       (const double*)dpsi, du, duprev, has_prev, parts);
+                       (const double*)dpsi, (const double*)dj, uprev, has_prev, parts);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_obs_final, dim3(1), dim3(64), 0, st, (const double*)parts, OBS_BLOCKS,

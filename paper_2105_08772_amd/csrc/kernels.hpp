@@ -148,9 +148,11 @@ hipError_t launch_get(bool fp32, const BoxDesc& b, int i, const void* src, doubl
                       hipStream_t st);
 hipError_t launch_set(bool fp32, const BoxDesc& b, int i, const double* in, void* dst,
                       hipStream_t st);
-// Observation: pull moments, then force/velocity/reductions, then line or plane profiles.
+// Observation: pull moments (dn, dpsi, dj: N, N and 3N doubles of workspace), then force,
+// velocity and reductions; uprev (3N doubles, the box's own) holds the previous observation's
+// velocity on entry and this one's on return.
 hipError_t launch_observe(bool fp32, const BoxDesc& b, const void* src, double* dn, double* dpsi,
-                          double* du, const double* duprev, int has_prev, double* parts,
+                          double* dj, double* uprev, int has_prev, double* parts,
                           double* scal, hipStream_t st);
 hipError_t launch_profile_line(const BoxDesc& b, const double* dn, const double* dpsi,
                                double* prof, double* probes, hipStream_t st);

@@ -8,6 +8,7 @@
 #include <cstdint>
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -188,10 +189,8 @@ struct lbm_sc {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     bool own_pop = true;       // false: the population buffers belong to the caller
-    double* d_n = nullptr;     // N doubles: density, also the staging buffer of get/set
-    double* d_psi = nullptr;   // N doubles
-    double* d_u = nullptr;     // 3N doubles: momentum, then velocity
-    double* d_uprev = nullptr; // 3N doubles
+    int dev = 0;               // HIP device of the box (its observation workspace)
+    double* d_uprev = nullptr; // 3N doubles: velocity of the last observation
     double* d_parts = nullptr; // OBS_BLOCKS * OBS_PARTS
     double* d_small = nullptr; // scalars (OBS_PARTS) + probes (4) + dither step counts (2 x u32)
     double* d_prof = nullptr;  // 4 * Lmax
@@ -290,6 +289,46 @@ int refuse_in_capture(hipStream_t s, const char* what)
     return LBM_SC_OK;
 }
 
+// Observation workspace, shared by the boxes of one device: density, psi and momentum of every
+// node (5 doubles per node) while an observation (or a get/set staging copy, or the initial
+// state) is computed. Every user holds the device's lock from the first launch that touches the
+// workspace until its stream has drained, so the work of two boxes never overlaps in it. It grows
+// to the largest box used and is freed when the last box of the device is destroyed. Only the
+// previous observation's velocity (3 doubles per node) stays with each box.
+struct Workspace {
+    std::mutex mu;
+    double* ptr = nullptr;
+    size_t nodes = 0;    // capacity in nodes
+    int boxes = 0;       // live boxes of the device
+};
+constexpr int MAX_DEVICES = 64;
+Workspace g_ws[MAX_DEVICES];
+
+// Make the (locked) workspace w of device dev hold n nodes: dn (n), dpsi (n), dj (3n).
+int ws_reserve(Workspace& w, int dev, size_t n)
+{
+    if (w.nodes >= n) return LBM_SC_OK;
+    int cur = dev;
+    if (hipGetDevice(&cur) != hipSuccess) cur = dev;
+    if (cur != dev && hipSetDevice(dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(LBM_SC_EDEVICE, "hipSetDevice for the observation workspace failed");
+    }
+    if (w.ptr) (void)hipFree(w.ptr);   // its previous users have drained their streams
+    w.ptr = nullptr;
+    w.nodes = 0;
+    hipError_t e = hipMalloc((void**)&w.ptr, 5 * n * sizeof(double));
+    if (cur != dev) (void)hipSetDevice(cur);
+    if (e != hipSuccess) {
+        w.ptr = nullptr;
+        (void)hipGetLastError();
+        return fail(LBM_SC_ENOMEM, "observation workspace of " + std::to_string(5 * n * 8) +
+                                       " bytes: " + hipGetErrorString(e));
+    }
+    w.nodes = n;
+    return LBM_SC_OK;
+}
+
 void release(lbm_sc* h)
 {
     if (!h) return;
@@ -299,10 +338,19 @@ void release(lbm_sc* h)
         for (void* p : h->pop)
             if (p) (void)hipFree(p);
     }
-    void* bufs[] = {h->d_n, h->d_psi, h->d_u, h->d_uprev, h->d_parts, h->d_small, h->d_prof};
+    void* bufs[] = {h->d_uprev, h->d_parts, h->d_small, h->d_prof};
     for (void* p : bufs)
         if (p) (void)hipFree(p);
     if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+    {
+        Workspace& w = g_ws[h->dev];
+        std::lock_guard<std::mutex> lock(w.mu);
+        if (--w.boxes == 0 && w.ptr) {
+            (void)hipFree(w.ptr);
+            w.ptr = nullptr;
+            w.nodes = 0;
+        }
+    }
     delete h;
 }
 
@@ -326,28 +374,38 @@ int profile_len(const lbm_sc* h)
     return h->box.nx;
 }
 
-// Run the observation kernels and assemble lbm_sc_obs on the host (synchronises).
+// Run the observation kernels and assemble lbm_sc_obs on the host (synchronises). The caller
+// holds the lock of the box's device workspace.
 int observe(lbm_sc* h, lbm_sc_obs* o, double* prof_out)
 {
     const lbm::BoxDesc& b = h->box;
-    HIP_TRY(lbm::launch_observe(h->fp32, b, h->pop[h->cur], h->d_n, h->d_psi, h->d_u, h->d_uprev,
-                                h->has_prev, h->d_parts, h->d_small, h->stream));
+    Workspace& w = g_ws[h->dev];
+    if (int rc = ws_reserve(w, h->dev, b.n)) return rc;
+    double* dn = w.ptr;
+    double* dpsi = w.ptr + b.n;
+    double* dj = w.ptr + 2 * (size_t)b.n;
+    hipError_t le = lbm::launch_observe(h->fp32, b, h->pop[h->cur], dn, dpsi, dj, h->d_uprev,
+                                        h->has_prev, h->d_parts, h->d_small, h->stream);
     const int L = profile_len(h);
-    if (h->cfg.geom == LBM_SC_SLAB)
-        HIP_TRY(lbm::launch_profile_planes(b, h->cfg.slab_axis, h->d_n, h->d_psi, h->d_prof,
-                                           h->d_small + lbm::OBS_PARTS, h->stream));
-    else
-        HIP_TRY(lbm::launch_profile_line(b, h->d_n, h->d_psi, h->d_prof,
-                                         h->d_small + lbm::OBS_PARTS, h->stream));
+    if (le == hipSuccess) {
+        if (h->cfg.geom == LBM_SC_SLAB)
+            le = lbm::launch_profile_planes(b, h->cfg.slab_axis, dn, dpsi, h->d_prof,
+                                            h->d_small + lbm::OBS_PARTS, h->stream);
+        else
+            le = lbm::launch_profile_line(b, dn, dpsi, h->d_prof, h->d_small + lbm::OBS_PARTS,
+                                          h->stream);
+    }
+    if (le != hipSuccess) {
+        // nothing may still use the workspace once the lock is released
+        (void)hipStreamSynchronize(h->stream);
+        return fail_hip("observation launch", le);
+    }
     double small[lbm::OBS_PARTS + 4];
     std::vector<double> prof(4 * (size_t)L);
     hipError_t e = hipMemcpyAsync(small, h->d_small, sizeof(small), hipMemcpyDeviceToHost, h->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(prof.data(), h->d_prof, prof.size() * sizeof(double),
                            hipMemcpyDeviceToHost, h->stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(h->d_uprev, h->d_u, 3 * (size_t)b.n * sizeof(double),
-                           hipMemcpyDeviceToDevice, h->stream);
     // wait also when an enqueue failed: no copy may still write into small or prof after return
     const hipError_t se = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) return fail_hip("hipMemcpyAsync", e);
@@ -486,9 +544,10 @@ void default_shape(lbm_sc* h)
     h->shape.z_chunk = best;
 }
 
+// What one box holds itself; the observation workspace (5 doubles per node) is shared per device.
 struct Sizes {
-    size_t popbytes, n8, n24, parts, small, prof;
-    size_t total() const { return 2 * popbytes + 2 * n8 + 2 * n24 + parts + small + prof; }
+    size_t popbytes, n24, parts, small, prof;
+    size_t total() const { return 2 * popbytes + n24 + parts + small + prof; }
 };
 
 Sizes sizes_for(const lbm_sc_config* c)
@@ -499,7 +558,6 @@ Sizes sizes_for(const lbm_sc_config* c)
     const int Lmax = std::max(c->nx, std::max(c->ny, c->nz));
     Sizes s;
     s.popbytes = (size_t)c->nz * 19 * population_pitch(pxy, elem) * elem;
-    s.n8 = (size_t)n * 8;
     s.n24 = 3 * (size_t)n * 8;
     s.parts = (size_t)lbm::OBS_BLOCKS * lbm::OBS_PARTS * 8;
     s.small = (lbm::OBS_PARTS + 4 + 1) * 8;   // scalars, probes, the two dither step counts
@@ -589,8 +647,19 @@ int create_box(const lbm_sc_config* cfg, void* buf_a, void* buf_b, size_t buf_by
     *out = nullptr;
     int rc = validate(cfg);
     if (rc) return rc;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) {
+        (void)hipGetLastError();
+        return fail(LBM_SC_EDEVICE, "no usable current HIP device");
+    }
     lbm_sc* h = new (std::nothrow) lbm_sc();
     if (!h) return fail(LBM_SC_ENOMEM, "host allocation failed");
+    h->dev = dev;
+    {
+        Workspace& w = g_ws[dev];
+        std::lock_guard<std::mutex> lock(w.mu);
+        ++w.boxes;   // from here release() accounts for the box
+    }
     h->cfg = *cfg;
     h->fp32 = cfg->prec != LBM_SC_FP64;
     h->math64 = cfg->prec == LBM_SC_FP32_SHIFTED_MATH64;
@@ -671,8 +740,7 @@ int create_box(const lbm_sc_config* cfg, void* buf_a, void* buf_b, size_t buf_by
         release(h);
         return fail(rc, msg);
     }
-    if ((rc = alloc(h, (void**)&h->d_n, sz.n8)) || (rc = alloc(h, (void**)&h->d_psi, sz.n8)) ||
-        (rc = alloc(h, (void**)&h->d_u, sz.n24)) || (rc = alloc(h, (void**)&h->d_uprev, sz.n24)) ||
+    if ((rc = alloc(h, (void**)&h->d_uprev, sz.n24)) ||
         (rc = alloc(h, (void**)&h->d_parts, sz.parts)) ||
         (rc = alloc(h, (void**)&h->d_small, sz.small)) ||
         (rc = alloc(h, (void**)&h->d_prof, sz.prof))) {
@@ -702,19 +770,27 @@ int create_box(const lbm_sc_config* cfg, void* buf_a, void* buf_b, size_t buf_by
         d.n_out = n_out;
         d.noise_amp = cfg->noise_amp;
         d.seed = cfg->seed;
-        hipError_t e = lbm::launch_init(h->fp32, b, d, h->d_n, h->d_psi, h->pop[0], h->stream);
-        if (e != hipSuccess) {
-            release(h);
-            return fail_hip("launch_init", e);
+        {
+            Workspace& w = g_ws[h->dev];
+            std::lock_guard<std::mutex> lock(w.mu);
+            rc = ws_reserve(w, h->dev, b.n);
+            if (!rc) {
+                hipError_t e = lbm::launch_init(h->fp32, b, d, w.ptr, w.ptr + b.n, h->pop[0],
+                                                h->stream);
+                if (e != hipSuccess) {
+                    (void)hipStreamSynchronize(h->stream);
+                    rc = fail_hip("launch_init", e);
+                }
+            }
+            lbm_sc_obs o;
+            if (!rc) rc = observe(h, &o, nullptr);
+            if (!rc) h->mass0 = o.mass;
         }
-        lbm_sc_obs o;
-        rc = observe(h, &o, nullptr);
         if (rc) {
             std::string msg = g_err;
             release(h);
             return fail(rc, msg);
         }
-        h->mass0 = o.mass;
     } else {
         hipError_t e = hipMemsetAsync(h->pop[0], 0, popbytes, h->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
@@ -820,6 +896,8 @@ int lbm_sc_observables(lbm_sc* h, lbm_sc_obs* out, double* prof, size_t prof_len
     if (prof && prof_len != 4 * (size_t)profile_len(h))
         return fail(LBM_SC_EINVAL, "prof_len must be 4 * " + std::to_string(profile_len(h)));
     if (int rc = refuse_in_capture(h->stream, "lbm_sc_observables")) return rc;
+    Workspace& w = g_ws[h->dev];
+    std::lock_guard<std::mutex> lock(w.mu);
     int rc = observe(h, out, prof);
     if (rc) return rc;
     if (!out->finite) return fail(LBM_SC_EUNSTABLE, "non-finite value or n <= 0 in the state");
@@ -832,10 +910,17 @@ int lbm_sc_get_populations(lbm_sc* h, double* f, size_t len)
     const size_t N = h->box.n;
     if (len != 19 * N) return fail(LBM_SC_EINVAL, "len must be 19*nx*ny*nz");
     if (int rc = refuse_in_capture(h->stream, "lbm_sc_get_populations")) return rc;
+    Workspace& w = g_ws[h->dev];
+    std::lock_guard<std::mutex> lock(w.mu);
+    if (int rc = ws_reserve(w, h->dev, N)) return rc;
     for (int i = 0; i < 19; ++i) {
-        HIP_TRY(lbm::launch_get(h->fp32, h->box, i, h->pop[h->cur], h->d_n, h->stream));
-        HIP_TRY(hipMemcpyAsync(f + (size_t)i * N, h->d_n, N * 8, hipMemcpyDeviceToHost, h->stream));
-        HIP_TRY(hipStreamSynchronize(h->stream));
+        hipError_t e = lbm::launch_get(h->fp32, h->box, i, h->pop[h->cur], w.ptr, h->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(f + (size_t)i * N, w.ptr, N * 8, hipMemcpyDeviceToHost, h->stream);
+        // wait also when an enqueue failed: the workspace is free again once the lock is released
+        const hipError_t se = hipStreamSynchronize(h->stream);
+        if (e != hipSuccess) return fail_hip("population read-back", e);
+        if (se != hipSuccess) return fail_hip("hipStreamSynchronize", se);
     }
     return LBM_SC_OK;
 }
@@ -848,12 +933,16 @@ int lbm_sc_set_populations(lbm_sc* h, const double* f, size_t len)
     if (int rc = refuse_in_capture(h->stream, "lbm_sc_set_populations")) return rc;
     // a set state starts again at step 0 (the dither sequence restarts with it)
     HIP_TRY(hipMemsetAsync(h->box.tick, 0, 2 * sizeof(unsigned), h->stream));
+    Workspace& w = g_ws[h->dev];
+    std::lock_guard<std::mutex> lock(w.mu);
+    if (int rc = ws_reserve(w, h->dev, N)) return rc;
     for (int i = 0; i < 19; ++i) {
-        HIP_TRY(hipMemcpyAsync(h->d_n, f + (size_t)i * N, N * 8, hipMemcpyHostToDevice, h->stream));
-        const hipError_t e = lbm::launch_set(h->fp32, h->box, i, h->d_n, h->pop[h->cur], h->stream);
-        // wait also when the launch failed: the copy must be done with f before returning
+        hipError_t e = hipMemcpyAsync(w.ptr, f + (size_t)i * N, N * 8, hipMemcpyHostToDevice, h->stream);
+        if (e == hipSuccess) e = lbm::launch_set(h->fp32, h->box, i, w.ptr, h->pop[h->cur], h->stream);
+        // wait also when an enqueue failed: the copy must be done with f, and the workspace free,
+        // before returning
         const hipError_t se = hipStreamSynchronize(h->stream);
-        if (e != hipSuccess) return fail_hip("launch_set", e);
+        if (e != hipSuccess) return fail_hip("population upload", e);
         if (se != hipSuccess) return fail_hip("hipStreamSynchronize", se);
     }
     h->step = 0;

@@ -84,8 +84,9 @@ class GpuBackend:
         import torch
 
         from . import (LBM_SC_BUBBLE, LBM_SC_DROPLET, LBM_SC_FP32_SHIFTED, Box, Group, LbmScError,
-                       config, lbm_sc_device_bytes)
+                       LBM_SC_OBS_WORKSPACE_BYTES_PER_NODE, config, lbm_sc_device_bytes)
         self._torch = torch
+        self._ws = LBM_SC_OBS_WORKSPACE_BYTES_PER_NODE
         self.stream = stream or torch.cuda.Stream()
         self.prec = LBM_SC_FP32_SHIFTED if prec is None else prec
         self._Box, self._Group, self._config = Box, Group, config
@@ -107,7 +108,10 @@ class GpuBackend:
                             stream=self.stream.cuda_stream)
 
     def bytes_needed(self, r):
-        return int(self._bytes(self.config(r)))
+        # the box's own memory plus a device observation workspace of its size: the boxes share
+        # one workspace as large as the largest of them, so this sum over admitted boxes bounds
+        # what they use
+        return int(self._bytes(self.config(r))) + self._ws * r.L ** 3
 
     def free_bytes(self):
         free, _total = self._torch.cuda.mem_get_info()
