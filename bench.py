@@ -55,6 +55,89 @@ def measured_traffic(nodes, prec, launch):
     return t.get("bytes_per_launch")
 
 
+def counter_per_dispatch(run_dir, counter, kernel_prefix, last=None):
+    """Median and count of one rocprofv3 counter (`--pmc COUNTER --output-format csv`) over the
+    dispatches of kernels whose name starts with kernel_prefix (rows of one dispatch summed);
+    `last`: only the last that many dispatches."""
+    import csv
+    import glob
+    files = glob.glob(os.path.join(run_dir, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise SystemExit(f"no counter_collection.csv under {run_dir}")
+    per = {}
+    for fn in files:
+        with open(fn, newline="") as fh:
+            for row in csv.DictReader(fh):
+                if row["Counter_Name"] != counter or not row["Kernel_Name"].startswith(kernel_prefix):
+                    continue
+                key = (fn, int(row["Dispatch_Id"]))
+                per[key] = per.get(key, 0.0) + float(row["Counter_Value"])
+    vals = [v for _, v in sorted(per.items())]
+    if last:
+        vals = vals[-last:]
+    if not vals:
+        raise SystemExit(f"no {counter} rows for {kernel_prefix} under {run_dir}")
+    mid = sorted(vals)
+    n = len(mid)
+    med = mid[n // 2] if n % 2 else 0.5 * (mid[n // 2 - 1] + mid[n // 2])
+    return float(med), n
+
+
+def traffic_summary(prof_dir, bench_log, out_path):
+    """HBM bytes per launch of the single-box step from four counter runs under prof_dir
+    (pmc_FETCH_SIZE_step, pmc_WRITE_SIZE_step: the benchmark's step; pmc_FETCH_SIZE_copy,
+    pmc_WRITE_SIZE_copy: the library's dword streaming copy of 1 GiB each way). Each counter is
+    scaled by what it reads for the copy, whose bytes are known; the record carries the hash of
+    the step kernels' sources and the launch shape, so the benchmark uses it only for that
+    kernel. bench_log: the step run's output, whose last line is its JSON result."""
+    with open(bench_log) as fh:
+        res = json.loads([ln for ln in fh if ln.startswith("{")][-1])
+    copy_bytes = 1 << 30
+    cf, ncf = counter_per_dispatch(os.path.join(prof_dir, "pmc_FETCH_SIZE_copy"), "FETCH_SIZE",
+                                   "void lbm::(anonymous namespace)::k_stream_copy<")
+    cw, ncw = counter_per_dispatch(os.path.join(prof_dir, "pmc_WRITE_SIZE_copy"), "WRITE_SIZE",
+                                   "void lbm::(anonymous namespace)::k_stream_copy<")
+    sf, nsf = counter_per_dispatch(os.path.join(prof_dir, "pmc_FETCH_SIZE_step"), "FETCH_SIZE",
+                                   "void lbm::(anonymous namespace)::k_step<")
+    sw, nsw = counter_per_dispatch(os.path.join(prof_dir, "pmc_WRITE_SIZE_step"), "WRITE_SIZE",
+                                   "void lbm::(anonymous namespace)::k_step<")
+    fscale, wscale = copy_bytes / (cf * 1024), copy_bytes / (cw * 1024)
+    fb, wb = sf * 1024 * fscale, sw * 1024 * wscale
+    launch = {k: v for k, v in res["config"]["launch"].items()
+              if k not in ("graph_steps", "block", "tuned")}
+    rec = {"kernel": "single-box fused step, 256^3 FP32-shifted droplet, default launch shape",
+           "nodes": res["config"]["nodes"], "prec": "fp32", "launch": launch,
+           "kernel_sha256_16": kernel_hash(),
+           "FETCH_SIZE_KiB_per_dispatch": round(sf, 1), "WRITE_SIZE_KiB_per_dispatch": round(sw, 1),
+           "copy_FETCH_SIZE_KiB_per_1GiB": round(cf, 1), "copy_WRITE_SIZE_KiB_per_1GiB": round(cw, 1),
+           "fetch_scale": round(fscale, 5), "write_scale": round(wscale, 5),
+           "fetch_bytes_per_launch": int(fb), "write_bytes_per_launch": int(wb),
+           "bytes_per_launch": int(fb + wb),
+           "algorithmic_bytes_per_launch": res["roofline"]["bytes_per_launch"],
+           "dispatches": {"step_fetch": nsf, "step_write": nsw, "copy_fetch": ncf,
+                          "copy_write": ncw}}
+    with open(out_path, "w") as fh:
+        json.dump(rec, fh, indent=1)
+        fh.write("\n")
+    alg = rec["algorithmic_bytes_per_launch"] / 2
+    print(json.dumps(rec, indent=1))
+    print(f"reads {fb / alg:.4f} x, writes {wb / alg:.4f} x the algorithmic bytes")
+
+
+def group_traffic(prof_dir, last=256):
+    """The same scaling for the multi-box step's counter runs (pmc_FETCH_SIZE_group,
+    pmc_WRITE_SIZE_group), over its last `last` dispatches; printed, not stored."""
+    with open(TRAFFIC_FILE) as fh:
+        t = json.load(fh)
+    out = {}
+    for counter, scale in (("FETCH_SIZE", t["fetch_scale"]), ("WRITE_SIZE", t["write_scale"])):
+        v, n = counter_per_dispatch(os.path.join(prof_dir, f"pmc_{counter}_group"), counter,
+                                    "void lbm::(anonymous namespace)::k_step_group<", last)
+        out[counter] = {"KiB_per_dispatch": round(v, 1), "bytes_per_launch": int(v * 1024 * scale),
+                        "dispatches": n}
+    print(json.dumps(out, indent=1))
+
+
 def stream_copy_gbps(torch, lbm, stream, nbytes=2 << 30, reps=20):
     """Achievable HBM bandwidth: the library's streaming copy of a 2 GiB buffer with 4-, 8- and
     16-byte lanes, counted as read + write bytes, and torch's device-to-device copy for
@@ -596,7 +679,18 @@ def main():
     ap.add_argument("--batched-steps", type=int, default=20000,
                     help="steps of the batched 64-box workload measured after the main timing "
                          "(0 = skip; default: the configuration's 20000)")
+    ap.add_argument("--traffic-from", default=None,
+                    help="CPU only: turn the rocprofv3 counter runs under this directory into the "
+                         "traffic record the benchmark reads (see traffic_summary)")
+    ap.add_argument("--traffic-bench-log", default=None,
+                    help="with --traffic-from: output of the counted step run")
     args = ap.parse_args()
+    if args.traffic_from:
+        if args.traffic_bench_log:
+            traffic_summary(args.traffic_from, args.traffic_bench_log, TRAFFIC_FILE)
+        else:
+            group_traffic(args.traffic_from)
+        return
     if args.gpus != 1:
         print("bench.py: the library runs on one GPU only (there is no multi-GPU path); use --gpus 1",
               file=sys.stderr)

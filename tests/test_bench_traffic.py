@@ -1,0 +1,90 @@
+"""The counter summary of bench.py (CPU only): rocprofv3 counter tables in, HBM bytes per launch
+out. Synthetic tables with known values check the per-dispatch sum over rows, the median, the
+kernel filter and the scaling by the copy calibration; the committed traffic record must be the
+one bench.py accepts for the current step-kernel sources."""
+import csv
+import importlib.util
+import json
+import os
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+FIELDS = ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"]
+STEP = "void lbm::(anonymous namespace)::k_step<float, float, 0, true, 2, false, 8, 64>(...)"
+COPY = "void lbm::(anonymous namespace)::k_stream_copy<float>(float const*, float*, unsigned long)"
+
+
+def bench():
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(ROOT, "bench.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def write_run(d, counter, rows):
+    os.makedirs(d)
+    with open(os.path.join(d, "run_counter_collection.csv"), "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=FIELDS)
+        w.writeheader()
+        for disp, name, val in rows:
+            w.writerow({"Dispatch_Id": disp, "Kernel_Name": name, "Counter_Name": counter,
+                        "Counter_Value": val})
+
+
+def test_counter_median_sums_rows_of_a_dispatch_and_filters_kernels(tmp_path):
+    b = bench()
+    d = str(tmp_path / "run")
+    # dispatch 2 reported in two rows (e.g. per XCD): 30 + 10; another kernel is ignored
+    write_run(d, "FETCH_SIZE", [(1, STEP, 10.0), (2, STEP, 30.0), (2, STEP, 10.0), (3, COPY, 1e9),
+                                (4, STEP, 20.0), (5, STEP, 100.0)])
+    med, n = b.counter_per_dispatch(d, "FETCH_SIZE", "void lbm::(anonymous namespace)::k_step<")
+    assert (med, n) == (30.0, 4)          # median of 10, 40, 20, 100
+    med, n = b.counter_per_dispatch(d, "FETCH_SIZE", "void lbm::(anonymous namespace)::k_step<",
+                                    last=2)
+    assert (med, n) == (60.0, 2)          # 20 and 100
+    with pytest.raises(SystemExit):
+        b.counter_per_dispatch(d, "WRITE_SIZE", "void lbm::(anonymous namespace)::k_step<")
+
+
+def test_traffic_summary_scales_by_the_copy(tmp_path):
+    b = bench()
+    p = str(tmp_path)
+    gib_kib = (1 << 30) / 1024
+    # the copy's FETCH_SIZE reads half its bytes, WRITE_SIZE all of them
+    write_run(os.path.join(p, "pmc_FETCH_SIZE_copy"), "FETCH_SIZE", [(1, COPY, gib_kib / 2)] * 1)
+    write_run(os.path.join(p, "pmc_WRITE_SIZE_copy"), "WRITE_SIZE", [(1, COPY, gib_kib)])
+    write_run(os.path.join(p, "pmc_FETCH_SIZE_step"), "FETCH_SIZE", [(7, STEP, 600.0)])
+    write_run(os.path.join(p, "pmc_WRITE_SIZE_step"), "WRITE_SIZE", [(7, STEP, 1000.0)])
+    log = os.path.join(p, "bench.log")
+    res = {"config": {"nodes": 8, "launch": {"rows": 2, "z_chunk": 64, "xcd_remap": 1,
+                                             "prefetch": 0, "waves": 8, "tile_x": 64,
+                                             "graph_steps": 64, "block": [64, 16],
+                                             "tuned": False}},
+           "roofline": {"bytes_per_launch": 2 * 1000 * 1024}}
+    with open(log, "w") as fh:
+        fh.write("# some stderr line\n" + json.dumps(res) + "\nrocprofv3 finalization\n")
+    out = os.path.join(p, "traffic.json")
+    b.traffic_summary(p, log, out)
+    t = json.load(open(out))
+    assert t["fetch_scale"] == 2.0 and t["write_scale"] == 1.0
+    assert t["fetch_bytes_per_launch"] == 1200 * 1024
+    assert t["write_bytes_per_launch"] == 1000 * 1024
+    assert t["bytes_per_launch"] == 2200 * 1024
+    assert t["launch"] == {"rows": 2, "z_chunk": 64, "xcd_remap": 1, "prefetch": 0, "waves": 8,
+                           "tile_x": 64}
+    assert t["kernel_sha256_16"] == b.kernel_hash()
+
+
+def test_committed_traffic_record_matches_the_current_step_kernels():
+    b = bench()
+    with open(b.TRAFFIC_FILE) as fh:
+        t = json.load(fh)
+    assert t["kernel_sha256_16"] == b.kernel_hash(), \
+        "step kernel sources changed since the counters were taken: profile again"
+    launch = dict(t["launch"], graph_steps=64)
+    assert b.measured_traffic(t["nodes"], t["prec"], launch) == t["bytes_per_launch"]
+    # reads at least the algorithmic bytes, writes about them
+    alg = t["algorithmic_bytes_per_launch"] / 2
+    assert 1.0 <= t["fetch_bytes_per_launch"] / alg < 1.2
+    assert 0.99 < t["write_bytes_per_launch"] / alg < 1.01
