@@ -67,7 +67,10 @@ typedef struct {
     int32_t geom;            /* LBM_SC_DROPLET / BUBBLE / SLAB / FROM_HOST */
     int32_t prec;            /* LBM_SC_FP64 / LBM_SC_FP32_SHIFTED / LBM_SC_FP32_SHIFTED_MATH64 */
     int32_t slab_axis;       /* slab normal: 0 = x, 1 = y, 2 = z */
-    int32_t reserved0;       /* must be 0 */
+    int32_t packed_rows;     /* 0: rows of the stored populations padded to whole 128-byte lines
+                                (for the default x-y tiles); 1: rows packed at pitch nx, for
+                                full-row tiles (lbm_sc_launch / lbm_sc_group_launch tile_x 0),
+                                which then leave no lanes idle over padding. Results are the same */
     double tau;              /* BGK relaxation time, > 0.5 */
     double g_over_gc;        /* coupling G = g_over_gc * G_c(psi); G_c < 0, so > 1 separates phases */
     double radius;           /* droplet/bubble radius R of the tanh profile (Sec. 4), > 0 */

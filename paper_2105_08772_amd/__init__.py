@@ -26,7 +26,7 @@ _i32, _i64, _u64, _f64, _vp = (ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, 
 
 class LbmScConfig(ctypes.Structure):
     _fields_ = [("nx", _i32), ("ny", _i32), ("nz", _i32), ("psi", _i32), ("geom", _i32),
-                ("prec", _i32), ("slab_axis", _i32), ("reserved0", _i32), ("tau", _f64),
+                ("prec", _i32), ("slab_axis", _i32), ("packed_rows", _i32), ("tau", _f64),
                 ("g_over_gc", _f64), ("radius", _f64), ("width", _f64), ("slab_thickness", _f64),
                 ("n_in", _f64), ("n_out", _f64), ("noise_amp", _f64), ("seed", _u64),
                 ("rho_ref", _f64), ("stream", _vp)]
@@ -151,11 +151,12 @@ def _check(rc):
 
 def config(nx, ny=None, nz=None, *, psi=LBM_SC_PSI_EXP, geom=LBM_SC_DROPLET, prec=LBM_SC_FP64,
            slab_axis=2, tau=1.0, g_over_gc=1.3, radius=0.0, width=2.0, slab_thickness=0.0,
-           n_in=0.0, n_out=0.0, noise_amp=0.0, seed=0, rho_ref=0.0, stream=None):
+           n_in=0.0, n_out=0.0, noise_amp=0.0, seed=0, rho_ref=0.0, stream=None, packed_rows=0):
     """Build an lbm_sc_config (fields as documented in include/lbm_sc.h)."""
     ny = nx if ny is None else ny
     nz = nx if nz is None else nz
-    return LbmScConfig(nx, ny, nz, psi, geom, prec, slab_axis, 0, tau, g_over_gc, radius, width,
+    return LbmScConfig(nx, ny, nz, psi, geom, prec, slab_axis, packed_rows, tau, g_over_gc,
+                       radius, width,
                        slab_thickness, n_in, n_out, noise_amp, seed & (2**64 - 1), rho_ref,
                        stream)
 

@@ -56,10 +56,13 @@ inline bool shape_supported(const StepShape& s)
 inline int tile_height(const StepShape& s) { return s.waves * s.rows * (64 / s.tile_x); }
 
 // Interior rows of a full-row tile for row pitch px: the tile pulls by + 2 rows of px nodes into
-// rows * 64 * waves thread slots (< 1: the rows are too long for full-row tiles).
+// rows * 64 * waves thread slots, less up to 31 slots that align the lane window with the line
+// grid when the pitch is not a whole number of 128-byte lines (packed rows; a line holds 32 FP32
+// or 16 FP64 values, so 31 covers both). < 1: the rows are too long for full-row tiles.
 inline int row_tile_rows(const StepShape& s, unsigned px)
 {
-    return (int)((unsigned)(s.rows * 64 * s.waves) / px) - 2;
+    const unsigned slack = px % 32u ? 31u : 0u;
+    return (int)((unsigned)(s.rows * 64 * s.waves - slack) / px) - 2;
 }
 
 // One box of a multi-box step.

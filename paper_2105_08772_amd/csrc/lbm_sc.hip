@@ -207,11 +207,14 @@ struct lbm_sc {
 
 namespace {
 
-// Row pitch of the stored populations: nx rounded up to whole 128-byte lines, so that every row
-// starts on a line and the step kernel writes complete lines (it fills the padding of the last
-// line of each row, which nothing reads).
-unsigned row_pitch(int nx, size_t elem)
+// Row pitch of the stored populations. Padded rows (the default): nx rounded up to whole 128-byte
+// lines, so that every row starts on a line and the step kernel writes complete lines (it fills
+// the padding of the last line of each row, which nothing reads); x-y tiles need this. Packed
+// rows: pitch nx, for full-row tiles, whose lane window the kernel aligns with the line grid
+// itself, so that no lanes idle over padding.
+unsigned row_pitch(int nx, size_t elem, int packed)
 {
+    if (packed) return (unsigned)nx;
     const unsigned per_line = (unsigned)(128 / elem);
     return ((unsigned)nx + per_line - 1) / per_line * per_line;
 }
@@ -242,7 +245,7 @@ int validate(const lbm_sc_config* c)
     if (c->prec != LBM_SC_FP64 && c->prec != LBM_SC_FP32_SHIFTED && c->prec != LBM_SC_FP32_SHIFTED_MATH64)
         return fail(LBM_SC_EINVAL,
                     "prec must be LBM_SC_FP64, LBM_SC_FP32_SHIFTED or LBM_SC_FP32_SHIFTED_MATH64");
-    if (c->reserved0 != 0) return fail(LBM_SC_EINVAL, "reserved0 must be 0");
+    if (c->packed_rows != 0 && c->packed_rows != 1) return fail(LBM_SC_EINVAL, "packed_rows must be 0 or 1");
     if (!(c->tau > 0.5) || !std::isfinite(c->tau)) return fail(LBM_SC_EINVAL, "tau must be > 0.5");
     if (!std::isfinite(c->g_over_gc)) return fail(LBM_SC_EINVAL, "g_over_gc must be finite");
     if (c->geom != LBM_SC_FROM_HOST) {
@@ -264,7 +267,7 @@ int validate(const lbm_sc_config* c)
     // the step kernel addresses the 19 populations of one z-plane through one buffer resource of
     // at most 4 GiB
     const size_t elem = c->prec == LBM_SC_FP64 ? 8 : 4;
-    const unsigned long long pxy = (unsigned long long)row_pitch(c->nx, elem) * c->ny;
+    const unsigned long long pxy = (unsigned long long)row_pitch(c->nx, elem, c->packed_rows) * c->ny;
     if (19ull * population_pitch(pxy, elem) * elem >= (1ull << 32))
         return fail(LBM_SC_EINVAL, "box too large: the 19 populations of one z-plane must fit in 4 GiB");
     return LBM_SC_OK;
@@ -554,7 +557,7 @@ Sizes sizes_for(const lbm_sc_config* c)
 {
     const size_t elem = c->prec == LBM_SC_FP64 ? 8 : 4;
     const unsigned long long n = (unsigned long long)c->nx * c->ny * c->nz;
-    const unsigned long long pxy = (unsigned long long)row_pitch(c->nx, elem) * c->ny;
+    const unsigned long long pxy = (unsigned long long)row_pitch(c->nx, elem, c->packed_rows) * c->ny;
     const int Lmax = std::max(c->nx, std::max(c->ny, c->nz));
     Sizes s;
     s.popbytes = (size_t)c->nz * 19 * population_pitch(pxy, elem) * elem;
@@ -693,7 +696,7 @@ int create_box(const lbm_sc_config* cfg, void* buf_a, void* buf_b, size_t buf_by
     b.nz = cfg->nz;
     b.nxy = (unsigned)cfg->nx * (unsigned)cfg->ny;
     b.n = b.nxy * (unsigned)cfg->nz;
-    b.px = row_pitch(cfg->nx, h->elem);
+    b.px = row_pitch(cfg->nx, h->elem, cfg->packed_rows);
     const unsigned long long pxy = (unsigned long long)b.px * (unsigned)cfg->ny;
     b.pxy = (unsigned)pxy;   // < 2^32: validate bounds the plane
     b.pp = (unsigned)population_pitch(pxy, h->elem);   // 19 * pp * elem < 2^32 (validate)

@@ -204,14 +204,16 @@ __device__ __forceinline__ void moments(const T (&f)[Q], double& dn, C& jx, C& j
 // hold the same value - the bulk of each phase - and the bias adds up coherently once the state
 // is quasi-static (measured: mass drift growing by about 3e-10 per step at 256^3). The value is
 // therefore rounded after adding a dither in [-1/2, 1/2) ulp, u = frac((k + s) phi) - 1/2, k the
-// node's stored index and phi the golden-ratio fraction (a Weyl sequence over the nodes): over
+// node's index (z ny + y) nx + x in the box (not its storage offset, so that the result does not
+// depend on the row pitch) and phi the golden-ratio fraction (a Weyl sequence over the nodes): over
 // the nodes of one step the dither is spread evenly, so the stored value is unbiased over a
 // region. The offset s is a hash of the box's step count, so the pattern moves to an unrelated
 // position every step: the rounding errors of a quasi-static state neither repeat (which makes
 // the mass drift linearly) nor follow the previous step's pattern (a regular shift, e.g. a second
 // Weyl sequence in time, correlates the dither with the state it produced and biases the
 // rounding; measured 10x more drift than a fixed pattern). The caller passes key = k + s. The
-// result is deterministic and depends neither on the launch shape nor on grouping.
+// result is deterministic and depends neither on the launch shape, the row layout nor on
+// grouping.
 template <typename T>
 __device__ __forceinline__ T round_rest(double v, unsigned key)
 {
@@ -343,7 +345,6 @@ __device__ __forceinline__ void step_tile(const BoxDesc& bd, const T* __restrict
     auto& ring = rg.v;
 
     const int nx = bd.nx, ny = bd.ny, nz = bd.nz;
-    const unsigned pxy = bd.pxy;
     const PopBuf sbuf = make_popbuf(src, bd.pp);
     const PopBuf dbuf = make_popbuf(dst, bd.pp);
     const unsigned popb = sbuf.pop_bytes;
@@ -484,7 +485,7 @@ __device__ __forceinline__ void step_tile(const BoxDesc& bd, const T* __restrict
             const C(*pp)[LX] = ring[k & 3];
             // plane q = p - 1 lies in [z0, z1): its resource needs no wrap
             const Rsrc qr = plane_rsrc(dbuf, p - 1);
-            const unsigned qkey = (unsigned)(p - 1) * pxy + seed;   // scalar: plane index + offset
+            const unsigned qkey = (unsigned)(p - 1) * bd.nxy + seed;   // scalar: plane base + offset
             const int lx = lc + 1;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
@@ -510,7 +511,9 @@ __device__ __forceinline__ void step_tile(const BoxDesc& bd, const T* __restrict
                              w2 * ((p_e - m_e) + (p_w - m_w) + (p_n - m_n) + (p_s - m_s));
                 const C gp = -G * psi0;
                 const unsigned off = yo[r][1] + xso;
-                const unsigned key = qkey + off / E;
+                // stored rows lie inside the box (yg < ny): no wrap
+                const unsigned yrow = (unsigned)(y0 + (wv * R + r) * SUB + ls);
+                const unsigned key = qkey + yrow * (unsigned)nx + (unsigned)xg;
                 if constexpr (TAU1) {
                     collide_store<T, C, true>(qr, popb, off, key, rho_ref, pdn[r], pjx[r], pjy[r],
                                               pjz[r], gp * Sx, gp * Sy, gp * Sz, inv_tau, guo_pref,
@@ -538,10 +541,14 @@ __device__ __forceinline__ void step_tile(const BoxDesc& bd, const T* __restrict
 
 // Full-row tiles (for boxes whose rows are short): the workgroup owns rows [y0, y0 + by) of the
 // whole x extent, z planes [z0, z1). Per plane it pulls by + 2 rows (one halo row on each side,
-// wrapped) flattened over the row pitch: node m of the list is (m % px, m / px), thread t holds
-// nodes t + k NT, k < NPT. There is no x halo (x neighbours wrap inside the LDS row), and only
-// the row padding leaves lanes idle; those lanes store values nobody reads, so that each row's
-// last 128-byte line is written whole. The host chooses by so that px (by + 2) <= NPT NT.
+// wrapped) flattened over the row pitch: node m of the list is (m % px, m / px). There is no x
+// halo (x neighbours wrap inside the LDS row). Thread t holds list nodes t + k NT - al, k < NPT,
+// where al = (y0 - 1) px mod (elements per 128-byte line) puts the lane window on the line grid:
+// every wave's loads and stores of the interior rows cover whole lines, whether the rows are
+// padded to whole lines (al = 0; the padding lanes store values nobody reads, so that each row's
+// last line is written whole) or packed (pitch nx: no idle lanes over padding, and only the two
+// lines at the ends of the tile's rows are shared with the neighbouring tiles). The host chooses
+// by so that px (by + 2) + al <= NPT NT (row_tile_rows).
 template <typename T, typename C, int PSI, bool TAU1, int NPT, int WAVES>
 __device__ __forceinline__ void step_rows(const BoxDesc& bd, const T* __restrict__ src,
                                           T* __restrict__ dst, int by, int tiy, int z0, int z1,
@@ -552,7 +559,6 @@ __device__ __forceinline__ void step_rows(const BoxDesc& bd, const T* __restrict
     auto& ring = rg.v;
     const int nx = bd.nx, ny = bd.ny, nz = bd.nz;
     const int px = (int)bd.px;
-    const unsigned pxy = bd.pxy;
     const PopBuf sbuf = make_popbuf(src, bd.pp);
     const PopBuf dbuf = make_popbuf(dst, bd.pp);
     const unsigned popb = sbuf.pop_bytes;
@@ -564,14 +570,16 @@ __device__ __forceinline__ void step_rows(const BoxDesc& bd, const T* __restrict
     const unsigned rowb = bd.px * E;
     const int y0 = tiy * by;
     const int M = px * (by + 2);
+    constexpr int LINE = 128 / (int)sizeof(T);
+    const int al = (((y0 - 1) * px) % LINE + LINE) % LINE;
 
     // the thread's nodes: LDS position (lx, ly), box coordinates (x, y), load and store flags
     int lxk[NPT], lyk[NPT], xk[NPT], yk[NPT];
     bool ldk[NPT], stk[NPT];
 #pragma unroll
     for (int k = 0; k < NPT; ++k) {
-        const int m = (int)threadIdx.x + k * NT;
-        const bool valid = m < M;
+        const int m = (int)threadIdx.x + k * NT - al;
+        const bool valid = m >= 0 && m < M;
         const int lx = valid ? m % px : 0;
         const int ly = valid ? m / px : 0;
         const int yg = y0 - 1 + ly;
@@ -638,7 +646,7 @@ __device__ __forceinline__ void step_rows(const BoxDesc& bd, const T* __restrict
             const C* pp = ring[kp & 3];
             // plane q = p - 1 lies in [z0, z1): its resource needs no wrap
             const Rsrc qr = plane_rsrc(dbuf, p - 1);
-            const unsigned qkey = (unsigned)(p - 1) * pxy + seed;   // scalar: plane index + offset
+            const unsigned qkey = (unsigned)(p - 1) * bd.nxy + seed;   // scalar: plane base + offset
 #pragma unroll
             for (int k = 0; k < NPT; ++k) {
                 if (!stk[k]) continue;
@@ -666,7 +674,7 @@ __device__ __forceinline__ void step_rows(const BoxDesc& bd, const T* __restrict
                 unsigned xo[3], yo[3];
                 node_offsets(k, xo, yo);
                 const unsigned off = yo[1] + (unsigned)xk[k] * E;
-                const unsigned key = qkey + off / E;
+                const unsigned key = qkey + (unsigned)yk[k] * (unsigned)nx + (unsigned)xk[k];
                 if constexpr (TAU1) {
                     collide_store<T, C, true>(qr, popb, off, key, rho_ref, pdn[k], pjx[k], pjy[k],
                                               pjz[k], gp * Sx, gp * Sy, gp * Sz, inv_tau, guo_pref,

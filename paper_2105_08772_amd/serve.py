@@ -80,7 +80,8 @@ class GpuBackend:
     boxes are stepped one by one through the plain single-box path (lbm_sc_step) instead of one
     multi-box launch: the baseline the batched server is compared with."""
 
-    def __init__(self, prec=None, stream=None, tau=1.0, width=2.0, noise_amp=1e-6, single=False):
+    def __init__(self, prec=None, stream=None, tau=1.0, width=2.0, noise_amp=1e-6, single=False,
+                 packed_rows=None):
         import torch
 
         from . import (LBM_SC_BUBBLE, LBM_SC_DROPLET, LBM_SC_FP32_SHIFTED, Box, Group, LbmScError,
@@ -97,6 +98,9 @@ class GpuBackend:
         self.group = Group(self.stream.cuda_stream)
         self.launch = None
         self.single = single
+        # multi-box launches use full-row tiles, for which rows are best stored packed (pitch nx);
+        # the single-box path keeps x-y tiles on rows padded to whole lines
+        self.packed_rows = (not single) if packed_rows is None else bool(packed_rows)
         self.active = []
         self.fallen_back = None    # the launch shape replaced by FALLBACK, while it is replaced
 
@@ -105,7 +109,7 @@ class GpuBackend:
                             prec=self.prec, tau=self.tau, g_over_gc=r.g_over_gc,
                             radius=r.radius, width=self.width, noise_amp=self.noise_amp,
                             seed=r.seed, n_in=r.n_in, n_out=r.n_out,
-                            stream=self.stream.cuda_stream)
+                            stream=self.stream.cuda_stream, packed_rows=int(self.packed_rows))
 
     def bytes_needed(self, r):
         # the box's own memory plus a device observation workspace of its size: the boxes share

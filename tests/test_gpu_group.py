@@ -95,6 +95,34 @@ def test_group_equals_boxes_alone(prec, li):
         b.close()
 
 
+@pytest.mark.parametrize("prec", [lbm.LBM_SC_FP32_SHIFTED, lbm.LBM_SC_FP64,
+                                  lbm.LBM_SC_FP32_SHIFTED_MATH64])
+@pytest.mark.parametrize("li", [7, 8, 9, 10, 11, 4])
+def test_packed_rows_in_a_group_equal_padded_boxes_alone(prec, li):
+    """Boxes with packed rows (pitch nx) mixed with padded ones in one group: every box ends
+    bitwise equal to the same box with padded rows stepped alone, under full-row tiles (whose
+    lane window is then aligned to the line grid per tile) and under x-y tiles."""
+    import torch
+    launch = LAUNCHES[li]
+    say(f"packed rows in a group prec={prec} launch={launch}")
+    s = torch.cuda.Stream()
+    cfgs = box_configs(prec, s.cuda_stream)
+    want = alone(cfgs, 11)
+    for k, c in enumerate(cfgs):
+        c.packed_rows = k % 2 == 0 or c.nx % 32 != 0
+    boxes = [lbm.Box(c) for c in cfgs]
+    with lbm.Group(s.cuda_stream) as g:
+        g.set_launch(**launch)
+        g.set(boxes)
+        g.step(3)
+        g.step(8)
+        got = [b.get() for b in boxes]
+    for k, (a, b) in enumerate(zip(got, want)):
+        assert np.array_equal(a, b), f"box {k} (packed {cfgs[k].packed_rows}) differs"
+    for b in boxes:
+        b.close()
+
+
 def test_group_full_row_tiles_8_nodes_per_thread():
     """8 nodes per thread (FP32 arithmetic only): bitwise equal to the boxes stepped alone;
     groups of FP64 boxes or of boxes with FP64 arithmetic reject the shape."""

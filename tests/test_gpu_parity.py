@@ -46,10 +46,10 @@ def fp32_representable(f, rho_ref):
 
 
 def make_box(dims, prec=lbm.LBM_SC_FP64, psi=lbm.LBM_SC_PSI_EXP, ratio=1.3, tau=1.0,
-             rho_ref=0.0):
+             rho_ref=0.0, packed=0):
     nx, ny, nz = dims
     cfg = lbm.config(nx, ny, nz, psi=psi, geom=lbm.LBM_SC_FROM_HOST, prec=prec, tau=tau,
-                     g_over_gc=ratio, rho_ref=rho_ref if rho_ref else 1.0)
+                     g_over_gc=ratio, rho_ref=rho_ref if rho_ref else 1.0, packed_rows=packed)
     return lbm.Box(cfg)
 
 
@@ -267,29 +267,34 @@ def test_steps_recorded_into_a_caller_graph():
             assert np.array_equal(b.get(), ref.get())
 
 
-@pytest.mark.parametrize("dims", SHAPES + [(100, 37, 9), (129, 5, 4)])
+@pytest.mark.parametrize("dims", SHAPES + [(100, 37, 9), (129, 5, 4), (101, 45, 7)])
 @pytest.mark.parametrize("prec", [lbm.LBM_SC_FP64, lbm.LBM_SC_FP32_SHIFTED])
 def test_full_row_tiles_one_step(dims, prec):
     """Full-row tiles (tile_x 0) against the oracle (FP64, 1e-11) and bitwise against the default
-    x-y tiles (FP32) after one and three steps, on tiny, ragged and multi-tile boxes."""
+    x-y tiles (FP32) after one and three steps, on tiny, ragged and multi-tile boxes, with rows
+    padded to whole lines and with packed rows (pitch nx; the default x-y tiles run on those too)."""
     say(f"full-row tiles dims={dims} prec={prec}")
     rho_ref = 1.5
     f = fp32_representable(inputs.random_populations(dims, 5 + sum(dims), W * 1.5, amp=0.3), rho_ref)
     G = 1.3 * lbm.lbm_sc_gc(0)
     outs = []
-    for launch in (None, (4, 3, 1, 0, 8, 0), (2, 3, 1, 0, 8, 0), (4, 2, 0, 0, 4, 0)) + (((8, 2, 0, 0, 8, 0),)
-                                                 if prec == lbm.LBM_SC_FP32_SHIFTED else ()):
-        with make_box(dims, prec=prec, rho_ref=rho_ref) as b:
-            b.set(f)
-            if launch:
-                b.set_launch(*launch)
-            b.step(1)
-            g1 = b.get()
-            b.step(2)
-            outs.append((g1, b.get()))
+    launches = (None, (4, 3, 1, 0, 8, 0), (2, 3, 1, 0, 8, 0), (4, 2, 0, 0, 4, 0))
+    if prec == lbm.LBM_SC_FP32_SHIFTED:
+        launches += ((8, 2, 0, 0, 8, 0),)
+    for packed in (0, 1):
+        for launch in launches:
+            with make_box(dims, prec=prec, rho_ref=rho_ref, packed=packed) as b:
+                b.set(f)
+                if launch:
+                    b.set_launch(*launch)
+                b.step(1)
+                g1 = b.get()
+                b.step(2)
+                outs.append((g1, b.get()))
     if prec == lbm.LBM_SC_FP64:
         ref = core.step(f, G, 1.0, 0)
         assert rel_err(outs[1][0], ref) <= TOL64
+        assert rel_err(outs[len(launches) + 1][0], ref) <= TOL64
     for g1, g3 in outs[1:]:
         assert np.array_equal(g1, outs[0][0]) and np.array_equal(g3, outs[0][1])
 
@@ -379,6 +384,38 @@ def test_droplet32_observables(droplet32_run):
     # for droplets, Sec. 4); sigma_0 = 0.0495 is the flat lattice value at G/G_c = 1.3
     assert obs["n_center"] > 2.0 and obs["n_far"] < 0.6 and obs["dP"] > 0
     assert obs["C"] > 0 and 0 < obs["R_s"] < obs["R_e"] and 0 < obs["sigma_s"] < 0.0495
+
+
+@pytest.mark.parametrize("prec", [lbm.LBM_SC_FP64, lbm.LBM_SC_FP32_SHIFTED])
+def test_packed_rows_equal_padded_rows(prec):
+    """Initial state, 20 steps (default x-y tiles and full-row tiles), observables and profiles of
+    a droplet and a slab with packed rows (pitch nx) are bitwise those of the padded box: the
+    layout changes addresses only, the observation reductions run in canonical node order."""
+    for dims, geom in (((45, 37, 21), lbm.LBM_SC_DROPLET), ((33, 20, 50), lbm.LBM_SC_SLAB)):
+        say(f"packed rows prec={prec} dims={dims}")
+        res = []
+        for packed in (0, 1):
+            cfg = lbm.config(*dims, psi=0, geom=geom, prec=prec, g_over_gc=1.4, radius=7.0,
+                             slab_thickness=16.0, width=2.0, noise_amp=1e-6, seed=4,
+                             packed_rows=packed)
+            with lbm.Box(cfg) as b:
+                f0 = b.get()
+                b.step(10)
+                o1, p1 = b.observables()
+                b.set_launch(4, 5, 1, 0, 8, 0)
+                b.step(10)
+                o2, p2 = b.observables()
+                res.append((f0, b.get(), o1, p1, o2, p2))
+        a, c = res
+        assert np.array_equal(a[0], c[0]) and np.array_equal(a[1], c[1])
+        for oa, oc in ((a[2], c[2]), (a[4], c[4])):
+            for k, v in oa.items():
+                w = oc[k]
+                if isinstance(v, float) and np.isnan(v):
+                    assert np.isnan(w), k
+                else:
+                    assert np.array_equal(np.asarray(v), np.asarray(w)), k
+        assert np.array_equal(a[3], c[3]) and np.array_equal(a[5], c[5])
 
 
 def test_du_against_previous_call():

@@ -53,7 +53,8 @@ BAD = [
     dict(nx=0), dict(tau=0.5), dict(psi=2), dict(geom=9), dict(prec=3), dict(radius=0.0),
     dict(width=0.0), dict(g_over_gc=0.95), dict(n_in=1.0, n_out=0.0), dict(noise_amp=-1.0),
     dict(geom=lbm.LBM_SC_SLAB, slab_thickness=0.0, slab_axis=2),
-    dict(geom=lbm.LBM_SC_SLAB, slab_thickness=4.0, slab_axis=3),
+    dict(geom=lbm.LBM_SC_SLAB, slab_thickness=4.0, slab_axis=3), dict(packed_rows=2),
+    dict(packed_rows=-1),
 ]
 
 
@@ -94,6 +95,25 @@ def test_population_bytes_is_one_buffer_of_the_device_bytes():
         assert pb % 256 == 0
     with pytest.raises(lbm.LbmScError):
         lbm.lbm_sc_population_bytes(lbm.config(0, 4, 4))
+
+
+def test_packed_rows_use_pitch_nx():
+    """Packed rows store each z-plane's rows at pitch nx: the population buffer shrinks by the
+    row padding (none when nx fills whole 128-byte lines)."""
+    for prec, line in ((lbm.LBM_SC_FP32_SHIFTED, 32), (lbm.LBM_SC_FP64, 16)):
+        for nx in (37, 64, 100, 129):
+            pad = lbm.lbm_sc_population_bytes(lbm.config(nx, 20, 6, prec=prec, radius=3.0))
+            pk = lbm.lbm_sc_population_bytes(lbm.config(nx, 20, 6, prec=prec, radius=3.0,
+                                                        packed_rows=1))
+            px = -(-nx // line) * line
+            if nx % line == 0:
+                assert pk == pad
+            else:
+                assert pk < pad
+                # one z-plane's population planes: 19 x (pitch x ny rounded up to 64 elements)
+                elem = 8 if prec == lbm.LBM_SC_FP64 else 4
+                assert pk == 6 * 19 * (-(-(nx * 20) // 64) * 64) * elem
+                assert pad == 6 * 19 * (-(-(px * 20) // 64) * 64) * elem
 
 
 def test_sizes_of_the_largest_z_plane():

@@ -8,6 +8,9 @@ slip at an untested size would show only as wrong results; this test looks for i
   the row's pitch), and every LDS index inside the ring;
 - each node of the box is stored exactly once per plane, and nothing is stored beyond the row
   pitch;
+- in full-row tiles, every interior store lands at an address congruent to its thread slot
+  modulo the 128-byte line (the lane window is aligned with the line grid), for rows padded to
+  whole lines and for packed rows (pitch nx) alike;
 - for each stored node, the 18 neighbours it reads from the LDS ring hold psi of the right
   (periodically wrapped) nodes, written by some thread of the workgroup;
 - the pull sources of every population of a stored node are its upwind neighbours (wrapped).
@@ -26,7 +29,9 @@ CY = [0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1]
 NEIGH = [(dx, dy) for dx in (-1, 0, 1) for dy in (-1, 0, 1)]
 
 
-def row_pitch(nx, elem):
+def row_pitch(nx, elem, packed=False):
+    if packed:
+        return nx
     per_line = 128 // elem
     return (nx + per_line - 1) // per_line * per_line
 
@@ -46,9 +51,9 @@ def wrap(v, L):
 class Plane:
     """Accesses of one workgroup to one z-plane: psi written into the LDS ring, loads, stores."""
 
-    def __init__(self, nx, ny, elem, lds_shape):
+    def __init__(self, nx, ny, elem, lds_shape, packed=False):
         self.nx, self.ny, self.elem = nx, ny, elem
-        self.px = row_pitch(nx, elem)
+        self.px = row_pitch(nx, elem, packed)
         self.pp = pop_pitch(self.px * ny, elem)
         self.lds = {}
         self.lds_shape = lds_shape
@@ -82,14 +87,14 @@ def check_neighbours(pl, x, y, lds_of):
         assert pl.lds[idx] == (wrap(x + dx, pl.nx), wrap(y + dy, pl.ny)), (x, y, dx, dy)
 
 
-def xy_tile(nx, ny, elem, R, waves, bxt, tix, tiy, stored):
+def xy_tile(nx, ny, elem, R, waves, bxt, tix, tiy, stored, packed=False):
     """step_tile: tile (tix, tiy) of a BXT-wide x-y tiling."""
     sub = 64 // bxt
     by = waves * R * sub
     LX, LY = bxt + 2, by + 2
     NH = 2 * LX + 2 * by
     assert NH <= 64 * waves
-    pl = Plane(nx, ny, elem, (LY, LX))
+    pl = Plane(nx, ny, elem, (LY, LX), packed)
     px, E = pl.px, elem
     x0, y0 = tix * bxt, tiy * by
     todo = []
@@ -137,22 +142,31 @@ def xy_tile(nx, ny, elem, R, waves, bxt, tix, tiy, stored):
     stored.extend(pl.stores)
 
 
-def row_tile(nx, ny, elem, npt, waves, tiy, stored):
+def row_tile_rows(npt, waves, px):
+    """Interior rows of a full-row tile (kernels.hpp row_tile_rows): 31 slots are kept free to
+    align the lane window when the pitch is not a whole number of 32-element lines."""
+    slack = 31 if px % 32 else 0
+    return (npt * 64 * waves - slack) // px - 2
+
+
+def row_tile(nx, ny, elem, npt, waves, tiy, stored, packed=False):
     """step_rows: full-row tiles of by rows, npt nodes per thread."""
     NT = 64 * waves
-    px = row_pitch(nx, elem)
-    by = npt * NT // px - 2
+    px = row_pitch(nx, elem, packed)
+    by = row_tile_rows(npt, waves, px)
     assert by >= 1
     M = px * (by + 2)
     cap = npt * NT
-    pl = Plane(nx, ny, elem, (cap,))
+    pl = Plane(nx, ny, elem, (cap,), packed)
     E = elem
+    line = 128 // elem
     y0 = tiy * by
+    al = ((y0 - 1) * px) % line      # Python's % is already non-negative
     todo = []
     for t in range(NT):
         for k in range(npt):
-            m = t + k * NT
-            valid = m < M
+            m = t + k * NT - al
+            valid = 0 <= m < M
             lx, ly = (m % px, m // px) if valid else (0, 0)
             yg = y0 - 1 + ly
             lxk, xk, yk = min(lx, nx - 1), lx, wrap(yg, ny)
@@ -169,6 +183,8 @@ def row_tile(nx, ny, elem, npt, waves, tiy, stored):
             if stk:
                 off = yo[1] + xk * E
                 assert xk < px
+                # aligned lane window: the slot and the stored element agree modulo the line
+                assert (off // E - (t + k * NT)) % line == 0, (t, k)
                 pl.stores.append(pl.node_of(pl.load(off, E)))
                 if xk < nx:
                     todo.append((xk, yg, ly, lxk))
@@ -204,26 +220,29 @@ XY_SHAPES = [(R, waves, bxt) for (R, waves, bxt) in itertools.product((1, 2, 4),
 @pytest.mark.parametrize("nx,ny", [s for s in SIZES if s[0] <= 130])
 @pytest.mark.parametrize("R,waves,bxt", XY_SHAPES)
 @pytest.mark.parametrize("elem", [4, 8])
-def test_xy_tile_index_map(nx, ny, R, waves, bxt, elem):
+@pytest.mark.parametrize("packed", [False, True])
+def test_xy_tile_index_map(nx, ny, R, waves, bxt, elem, packed):
     by = waves * R * (64 // bxt)
     stored = []
     for tix in range((nx + bxt - 1) // bxt):
         for tiy in range((ny + by - 1) // by):
-            xy_tile(nx, ny, elem, R, waves, bxt, tix, tiy, stored)
-    check_coverage(stored, nx, ny, row_pitch(nx, elem))
+            xy_tile(nx, ny, elem, R, waves, bxt, tix, tiy, stored, packed)
+    check_coverage(stored, nx, ny, row_pitch(nx, elem, packed))
 
 
-@pytest.mark.parametrize("nx,ny", [s for s in SIZES if s[0] <= 130] + [(160, 11), (300, 4)])
+@pytest.mark.parametrize("nx,ny", [s for s in SIZES if s[0] <= 130] + [(160, 11), (300, 4),
+                                                                         (101, 37), (77, 50)])
 @pytest.mark.parametrize("npt,waves", [(2, 8), (4, 8), (8, 8), (4, 4)])
 @pytest.mark.parametrize("elem", [4, 8])
-def test_row_tile_index_map(nx, ny, npt, waves, elem):
-    px = row_pitch(nx, elem)
-    by = npt * 64 * waves // px - 2
+@pytest.mark.parametrize("packed", [False, True])
+def test_row_tile_index_map(nx, ny, npt, waves, elem, packed):
+    px = row_pitch(nx, elem, packed)
+    by = row_tile_rows(npt, waves, px)
     if by < 1:
         pytest.skip("rows too long for this shape (the library refuses it)")
     stored = []
     for tiy in range((ny + by - 1) // by):
-        row_tile(nx, ny, elem, npt, waves, tiy, stored)
+        row_tile(nx, ny, elem, npt, waves, tiy, stored, packed)
     check_coverage(stored, nx, ny, px)
 
 
