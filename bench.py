@@ -97,16 +97,19 @@ def traffic_summary(prof_dir, bench_log, out_path):
                                    "void lbm::(anonymous namespace)::k_stream_copy<")
     cw, ncw = counter_per_dispatch(os.path.join(prof_dir, "pmc_WRITE_SIZE_copy"), "WRITE_SIZE",
                                    "void lbm::(anonymous namespace)::k_stream_copy<")
+    spp = res["config"]["launch"].get("steps_per_pass", 1)
+    kernel = "void lbm::(anonymous namespace)::" + ("k_step2<" if spp == 2 else "k_step<")
     sf, nsf = counter_per_dispatch(os.path.join(prof_dir, "pmc_FETCH_SIZE_step"), "FETCH_SIZE",
-                                   "void lbm::(anonymous namespace)::k_step<")
+                                   kernel)
     sw, nsw = counter_per_dispatch(os.path.join(prof_dir, "pmc_WRITE_SIZE_step"), "WRITE_SIZE",
-                                   "void lbm::(anonymous namespace)::k_step<")
+                                   kernel)
     fscale, wscale = copy_bytes / (cf * 1024), copy_bytes / (cw * 1024)
     fb, wb = sf * 1024 * fscale, sw * 1024 * wscale
     launch = {k: v for k, v in res["config"]["launch"].items()
               if k not in ("graph_steps", "block", "tuned")}
     rec = {"kernel": "single-box fused step, 256^3 FP32-shifted droplet, default launch shape",
            "nodes": res["config"]["nodes"], "prec": "fp32", "launch": launch,
+           "steps_per_launch": spp,
            "kernel_sha256_16": kernel_hash(),
            "FETCH_SIZE_KiB_per_dispatch": round(sf, 1), "WRITE_SIZE_KiB_per_dispatch": round(sw, 1),
            "copy_FETCH_SIZE_KiB_per_1GiB": round(cf, 1), "copy_WRITE_SIZE_KiB_per_1GiB": round(cw, 1),
@@ -121,7 +124,8 @@ def traffic_summary(prof_dir, bench_log, out_path):
         fh.write("\n")
     alg = rec["algorithmic_bytes_per_launch"] / 2
     print(json.dumps(rec, indent=1))
-    print(f"reads {fb / alg:.4f} x, writes {wb / alg:.4f} x the algorithmic bytes")
+    print(f"reads {fb / alg:.4f} x, writes {wb / alg:.4f} x the algorithmic bytes "
+          f"({spp} step(s) per launch)")
 
 
 def group_traffic(prof_dir, last=256):
@@ -652,6 +656,8 @@ def main():
     ap.add_argument("--prefetch", type=int, default=-1)
     ap.add_argument("--waves", type=int, default=0)
     ap.add_argument("--tile-x", type=int, default=-1, help="64, 32, or 0 for full-row tiles")
+    ap.add_argument("--steps-per-pass", type=int, default=0,
+                    help="1 or 2 time steps per kernel pass (0: the library's default)")
     ap.add_argument("--tune", action="store_true", help="sweep launch shapes, keep the fastest")
     ap.add_argument("--cpu-steps", type=int, default=25)
     ap.add_argument("--no-cpu", action="store_true")
@@ -749,7 +755,7 @@ def main():
         for c in tune.box_candidates(L):
             try:
                 box.set_launch(c["rows"], c["z_chunk"], c["xcd_remap"], c["prefetch"], c["waves"],
-                               c["tile_x"])
+                               c["tile_x"], 64, c.get("steps_per_pass", 1))
             except lbm.LbmScError:
                 continue
             box.step(8)
@@ -760,14 +766,15 @@ def main():
                 best = (t, c)
         tuned = best[1]
         box.set_launch(tuned["rows"], tuned["z_chunk"], tuned["xcd_remap"], tuned["prefetch"],
-                       tuned["waves"], tuned["tile_x"])
+                       tuned["waves"], tuned["tile_x"], 64, tuned.get("steps_per_pass", 1))
     if (args.rows or args.zchunk or args.remap >= 0 or args.prefetch >= 0 or args.waves
-            or args.tile_x >= 0):
+            or args.tile_x >= 0 or args.steps_per_pass):
         lc = box.launch()
         box.set_launch(args.rows or lc["rows"], args.zchunk or lc["z_chunk"],
                        args.remap if args.remap >= 0 else lc["xcd_remap"],
                        args.prefetch if args.prefetch >= 0 else lc["prefetch"],
-                       args.waves or lc["waves"], args.tile_x if args.tile_x >= 0 else lc["tile_x"])
+                       args.waves or lc["waves"], args.tile_x if args.tile_x >= 0 else lc["tile_x"],
+                       64, args.steps_per_pass or lc["steps_per_pass"])
     info = box.info()
     launch = box.launch()
 
@@ -796,7 +803,9 @@ def main():
     mlups = nodes * K / wall / 1e6
     print(f"# timed {K} steps: {mlups:.0f} MLUPS", file=sys.stderr, flush=True)
 
-    # the dominant kernel alone: average launch duration over back-to-back steps
+    # the dominant kernel alone: average launch duration over back-to-back steps (a launch
+    # advances the box by steps_per_pass steps)
+    spp = launch["steps_per_pass"]
     k_steps = min(K, 2048)
     step_s = time_steps(k_steps)
     achieved = bytes_per_step / step_s / 1e9
@@ -835,8 +844,9 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBPS, 4),
             "traffic": traffic,
-            "kernel_ms": round(step_s * 1e3, 5),
-            "bytes_per_launch": bytes_per_step,
+            "kernel_ms": round(step_s * spp * 1e3, 5),
+            "steps_per_launch": spp,
+            "bytes_per_launch": bytes_per_step * spp,
             "stream_copy_GBps": copy_bw,
             "frac_of_best_copy": round(achieved / copy_bw["best"], 4) if copy_bw else None,
         },

@@ -149,12 +149,15 @@ int64_t lbm_sc_population_bytes(const lbm_sc_config* cfg);
 
 /* Enqueue nsteps (>= 0) time steps of Eq. (lbm) on the handle's stream: fused pull streaming,
  * density and psi, Shan-Chen force, Guo equilibrium velocity, BGK collision with the Guo term.
- * Runs of graph_steps steps (lbm_sc_launch) are replayed from a hipGraph the handle captures on
- * first use. While the caller is capturing the stream the call records plain launches into the
- * caller's graph: nsteps must then be even (LBM_SC_EINVAL otherwise, nothing recorded), every
- * replay advances the box by nsteps, and the host step counter advances once, at the capture
- * (lbm_sc_set_step corrects it after replays). Returns after enqueueing (asynchronous);
- * LBM_SC_EDEVICE if a launch fails. */
+ * With two steps per pass (lbm_sc_launch.steps_per_pass, the default for FP32 storage and
+ * arithmetic at tau = 1) pairs of steps run as one launch and an odd last step as a single one;
+ * the results are bitwise those of single steps. Runs of graph_steps steps are replayed from a
+ * hipGraph the handle captures on first use. While the caller is capturing the stream the call
+ * records plain launches into the caller's graph: nsteps must then be even (LBM_SC_EINVAL
+ * otherwise, nothing recorded; with two steps per pass a count that is not a multiple of 4 is
+ * recorded as single steps), every replay advances the box by nsteps, and the host step counter
+ * advances once, at the capture (lbm_sc_set_step corrects it after replays). Returns after
+ * enqueueing (asynchronous); LBM_SC_EDEVICE if a launch fails. */
 int lbm_sc_step(lbm_sc* h, int64_t nsteps);
 
 /* Wait until all work enqueued on the handle's stream has finished. This call, and every other
@@ -196,8 +199,12 @@ int lbm_sc_set_step(lbm_sc* h, int64_t step);
  * with rows 1 or 2 and prefetch 0. tile_x = 0 selects full-row tiles for boxes with short rows:
  * the workgroup (prefetch 0) owns whole rows, `rows` is the number of nodes each thread holds per
  * plane (waves 8: 2, 4, or 8 with FP32 arithmetic; waves 4: 4), and a tile has
- * rows*64*waves/px - 2 rows, px being nx rounded up to whole 128-byte lines (LBM_SC_EINVAL if
- * that is below 1). */
+ * rows*64*waves/px - 2 rows, px being the row pitch (less up to 31 slots that align packed rows
+ * with the line grid; LBM_SC_EINVAL if that is below 1). steps_per_pass = 2 selects the
+ * two-steps-per-pass kernel instead (FP32 storage and arithmetic, tau = 1), whose shapes are
+ * tile_x 64 with rows 1 and waves 8 (64 x 8 tiles, either prefetch setting) or rows 2 and waves
+ * 16 (64 x 16 tiles, prefetch 0); it is the default for those boxes (64 x 8, prefetch 1), and
+ * lbm_sc_get_launch reports the shape of the kernel in use. */
 typedef struct {
     int32_t rows;       /* tile rows per wave: 1, 2 or 4 (full-row tiles: nodes per thread, 2, 4, 8) */
     int32_t z_chunk;    /* planes per workgroup, >= 1 (clamped to nz) */
@@ -205,9 +212,14 @@ typedef struct {
     int32_t prefetch;   /* 1: issue the next plane's loads before the collision of the current one */
     int32_t waves;      /* wave64s per workgroup: 4 or 8 */
     int32_t tile_x;     /* tile width: 64 or 32; 0 for full-row tiles */
-    int32_t graph_steps;/* lbm_sc_step replays a hipGraph of this many launches (even, <= 4096;
+    int32_t graph_steps;/* lbm_sc_step replays a hipGraph of this many steps (even, <= 4096;
                            0: plain launches; default 64; plain launches inside a caller's
                            stream capture) */
+    int32_t steps_per_pass; /* 1, or 2: two time steps per kernel pass (FP32 storage and
+                           arithmetic, tau = 1 only; the fields above then give its shape, and
+                           an odd last step runs in the last single-step shape set, or the
+                           default one). The box streams through HBM once per two steps; the
+                           results are bitwise those of single steps */
 } lbm_sc_launch;
 
 /* Set / read the launch shape. The shape changes only the schedule: every node's arithmetic and

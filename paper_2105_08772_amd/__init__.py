@@ -59,7 +59,8 @@ class LbmScInfo(ctypes.Structure):
 
 class LbmScLaunch(ctypes.Structure):
     _fields_ = [("rows", _i32), ("z_chunk", _i32), ("xcd_remap", _i32), ("prefetch", _i32),
-                ("waves", _i32), ("tile_x", _i32), ("graph_steps", _i32)]
+                ("waves", _i32), ("tile_x", _i32), ("graph_steps", _i32),
+                ("steps_per_pass", _i32)]
 
     def to_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -246,8 +247,9 @@ def lbm_sc_set_step(h, step):
 
 
 def lbm_sc_set_launch(h, rows, z_chunk, xcd_remap=1, prefetch=0, waves=4, tile_x=64,
-                      graph_steps=64):
-    l = LbmScLaunch(rows, z_chunk, xcd_remap, prefetch, waves, tile_x, graph_steps)
+                      graph_steps=64, steps_per_pass=1):
+    l = LbmScLaunch(rows, z_chunk, xcd_remap, prefetch, waves, tile_x, graph_steps,
+                    steps_per_pass)
     _check(load().lbm_sc_set_launch(h, ctypes.byref(l)))
 
 
@@ -321,8 +323,9 @@ class Box:
         lbm_sc_set_step(self.h, step)
 
     def set_launch(self, rows, z_chunk, xcd_remap=1, prefetch=0, waves=4, tile_x=64,
-                   graph_steps=64):
-        lbm_sc_set_launch(self.h, rows, z_chunk, xcd_remap, prefetch, waves, tile_x, graph_steps)
+                   graph_steps=64, steps_per_pass=1):
+        lbm_sc_set_launch(self.h, rows, z_chunk, xcd_remap, prefetch, waves, tile_x, graph_steps,
+                          steps_per_pass)
 
     def launch(self):
         return lbm_sc_get_launch(self.h)

@@ -4,14 +4,16 @@
 // so the three compile in parallel; kernels.hip includes it for the shared device helpers only.
 //
 // Population storage: plane-major, population i of node (x, y, z) at element
-// (z * 19 + i) * pp + y * px + x, with the row pitch px >= nx a whole number of 128-byte lines
-// (the padding is never read) and the population pitch pp >= px * ny. Each z-plane is one
+// (z * 19 + i) * pp + y * px + x, with the row pitch px >= nx (a whole number of 128-byte lines,
+// whose padding is never read, or nx itself for packed rows) and the population pitch
+// pp >= px * ny. Each z-plane is one
 // contiguous block of 19 population planes, so a box is not limited by 32-bit offsets.
 // The stored arrays hold the post-collision populations of the previous step, f*_i(x, t - 1), so
 // the pre-collision state of time t is the pull f_i(x, t) = f*_i(x - xi_i, t - 1) (Eq. lbm of
 // arXiv:2105.08772 read as pull streaming). FP32 storage keeps g_i = f_i - w_i rho_ref.
 //
-// Fused step (one launch per time step, Sec. 2 of the paper):
+// Fused step (one launch per time step, or two: see the two-steps-per-pass kernel below; Sec. 2
+// of the paper):
 //   pull the 19 populations -> density n and momentum j -> psi(n) -> Shan-Chen force F from the
 //   psi of the 18 neighbours (Eq. SCForce) -> u_eq = (j + F/2)/n -> BGK relaxation to the
 //   second-order equilibrium plus the Guo term -> store. psi at the neighbours is needed at the
@@ -239,19 +241,19 @@ __device__ __forceinline__ unsigned dither_shift(unsigned t)
     return t;
 }
 
-// Collide one node in the arithmetic type C and store its 19 post-collision (shifted) populations,
-// rounded to the storage type T, at in-plane byte offset off of plane resource dst; key, the
-// node's plane-by-plane index (z * ny + y) * px + x plus the dither offset of the box's step,
-// sets the rest population's dither.
+// Collide one node in the arithmetic type C and hand its 19 post-collision (shifted) populations,
+// rounded to the storage type T, to sink(integral_constant<i>, value) in the order they are
+// computed (pairs i, i + 1, then the rest population); key, the node's index (z ny + y) nx + x
+// plus the dither offset of the box's step, sets the rest population's dither.
 // dn64 = sum g (n - rho_ref, exact), j = sum xi g = sum xi f. Rest population: mass-exact
 // closure g*_0 = dn - sum_{i>0} g*_i (the stored values summed in double precision), equal to
 // the BGK value in exact arithmetic; the node's stored mass then changes only by the final
-// rounding of g*_0.
-template <typename T, typename C, bool TAU1>
-__device__ __forceinline__ void collide_store(Rsrc dst, unsigned pop_bytes, unsigned off,
-                                              unsigned key, C rho_ref,
-                                              double dn64, C jx, C jy, C jz, C Fx, C Fy, C Fz,
-                                              C inv_tau, C guo_pref, const T* fin)
+// rounding of g*_0. Every kernel collides through this routine, so that a node gets the same
+// bits whichever kernel steps it.
+template <typename T, typename C, bool TAU1, typename Sink>
+__device__ __forceinline__ void collide_emit(Sink&& sink, unsigned key, C rho_ref, double dn64,
+                                             C jx, C jy, C jz, C Fx, C Fy, C Fz, C inv_tau,
+                                             C guo_pref, const T* fin)
 {
     const C dn = (C)dn64;
     const C n = rho_ref + dn;
@@ -285,11 +287,53 @@ __device__ __forceinline__ void collide_store(Rsrc dst, unsigned pop_bytes, unsi
         }
         // the closure sums the values as stored (rounded to T)
         const T sp = (T)gp, sm = (T)gm;
-        bstore<T, i>(dst, pop_bytes, off, sp);
-        bstore<T, i + 1>(dst, pop_bytes, off, sm);
+        sink(std::integral_constant<int, i>{}, sp);
+        sink(std::integral_constant<int, i + 1>{}, sm);
         sum += (double)sp + (double)sm;
     });
-    bstore<T, 0>(dst, pop_bytes, off, round_rest<T>(dn64 - sum, key));
+    sink(std::integral_constant<int, 0>{}, round_rest<T>(dn64 - sum, key));
+}
+
+// collide_emit storing the populations at in-plane byte offset off of plane resource dst, each
+// as soon as it is computed.
+template <typename T, typename C, bool TAU1>
+__device__ __forceinline__ void collide_store(Rsrc dst, unsigned pop_bytes, unsigned off,
+                                              unsigned key, C rho_ref,
+                                              double dn64, C jx, C jy, C jz, C Fx, C Fy, C Fz,
+                                              C inv_tau, C guo_pref, const T* fin)
+{
+    collide_emit<T, C, TAU1>([&](auto I, T v) { bstore<T, decltype(I)::value>(dst, pop_bytes, off, v); },
+                             key, rho_ref, dn64, jx, jy, jz, Fx, Fy, Fz, inv_tau, guo_pref, fin);
+}
+
+// Shan-Chen force of Eq. (SCForce): F = -G c_s^2 psi(x) sum_a W_a psi(x + xi_a) xi_a
+// = -G psi(x) S with S = sum_a w_a psi(x + xi_a) xi_a, since c_s^2 W_a equals the lattice weight
+// w_a (1/18 for the six axis neighbours, 1/36 for the twelve diagonal ones). at(dx, dy, dz) returns psi of the
+// neighbour at that offset (dz = -1, 0, 1 for the planes below, at and above the node). Every
+// kernel evaluates the force through this routine (same expression, same rounding).
+template <typename C, typename At>
+__device__ __forceinline__ void sc_force(At&& at, C G, C& Fx, C& Fy, C& Fz)
+{
+    const C c_e = at(1, 0, 0), c_w = at(-1, 0, 0);
+    const C c_n = at(0, 1, 0), c_s = at(0, -1, 0);
+    const C c_ne = at(1, 1, 0), c_nw = at(-1, 1, 0);
+    const C c_se = at(1, -1, 0), c_sw = at(-1, -1, 0);
+    const C p_c = at(0, 0, 1), p_e = at(1, 0, 1), p_w = at(-1, 0, 1);
+    const C p_n = at(0, 1, 1), p_s = at(0, -1, 1);
+    const C m_c = at(0, 0, -1), m_e = at(1, 0, -1), m_w = at(-1, 0, -1);
+    const C m_n = at(0, 1, -1), m_s = at(0, -1, -1);
+    const C psi0 = at(0, 0, 0);
+    const C w1 = (C)W1, w2 = (C)W2;
+    const C Sx = w1 * (c_e - c_w) +
+                 w2 * ((c_ne - c_nw) + (c_se - c_sw) + (p_e - p_w) + (m_e - m_w));
+    const C Sy = w1 * (c_n - c_s) +
+                 w2 * ((c_ne - c_se) + (c_nw - c_sw) + (p_n - p_s) + (m_n - m_s));
+    const C Sz = w1 * (p_c - m_c) +
+                 w2 * ((p_e - m_e) + (p_w - m_w) + (p_n - m_n) + (p_s - m_s));
+    const C gp = -G * psi0;
+    Fx = gp * Sx;
+    Fy = gp * Sy;
+    Fz = gp * Sz;
 }
 
 // Tile of a workgroup of WAVES wave64s: BXT (64 or 32) nodes wide; each wave covers R rows of
@@ -491,40 +535,24 @@ __device__ __forceinline__ void step_tile(const BoxDesc& bd, const T* __restrict
             for (int r = 0; r < R; ++r) {
                 if (!(xstore && yin[r])) continue;
                 const int ly = (wv * R + r) * SUB + ls + 1;
-                const C c_e = pc[ly][lx + 1], c_w = pc[ly][lx - 1];
-                const C c_n = pc[ly + 1][lx], c_s = pc[ly - 1][lx];
-                const C c_ne = pc[ly + 1][lx + 1], c_nw = pc[ly + 1][lx - 1];
-                const C c_se = pc[ly - 1][lx + 1], c_sw = pc[ly - 1][lx - 1];
-                const C p_c = pp[ly][lx], p_e = pp[ly][lx + 1], p_w = pp[ly][lx - 1];
-                const C p_n = pp[ly + 1][lx], p_s = pp[ly - 1][lx];
-                const C m_c = pm[ly][lx], m_e = pm[ly][lx + 1], m_w = pm[ly][lx - 1];
-                const C m_n = pm[ly + 1][lx], m_s = pm[ly - 1][lx];
-                const C psi0 = pc[ly][lx];
-                const C w1 = (C)W1, w2 = (C)W2;
-                // S = sum_a w_a psi(x + xi_a) xi_a; F = -G c_s^2 psi(x) sum_a W_a psi xi_a
-                //   = -G psi(x) S   (Eq. SCForce with c_s^2 W_a = w_a)
-                const C Sx = w1 * (c_e - c_w) +
-                             w2 * ((c_ne - c_nw) + (c_se - c_sw) + (p_e - p_w) + (m_e - m_w));
-                const C Sy = w1 * (c_n - c_s) +
-                             w2 * ((c_ne - c_se) + (c_nw - c_sw) + (p_n - p_s) + (m_n - m_s));
-                const C Sz = w1 * (p_c - m_c) +
-                             w2 * ((p_e - m_e) + (p_w - m_w) + (p_n - m_n) + (p_s - m_s));
-                const C gp = -G * psi0;
+                C Fx, Fy, Fz;
+                sc_force<C>([&](int dx, int dy, int dz) {
+                    return (dz < 0 ? pm : dz > 0 ? pp : pc)[ly + dy][lx + dx];
+                }, G, Fx, Fy, Fz);
                 const unsigned off = yo[r][1] + xso;
                 // stored rows lie inside the box (yg < ny): no wrap
                 const unsigned yrow = (unsigned)(y0 + (wv * R + r) * SUB + ls);
                 const unsigned key = qkey + yrow * (unsigned)nx + (unsigned)xg;
                 if constexpr (TAU1) {
                     collide_store<T, C, true>(qr, popb, off, key, rho_ref, pdn[r], pjx[r], pjy[r],
-                                              pjz[r], gp * Sx, gp * Sy, gp * Sz, inv_tau, guo_pref,
+                                              pjz[r], Fx, Fy, Fz, inv_tau, guo_pref,
                                               (const T*)nullptr);
                 } else {
                     // the pre-collision populations of plane q, pulled again
                     T fin[Q];
                     load_node(planes(p - 1), popb, yo[r], xo, fin);
                     collide_store<T, C, false>(qr, popb, off, key, rho_ref, pdn[r], pjx[r], pjy[r],
-                                               pjz[r], gp * Sx, gp * Sy, gp * Sz, inv_tau, guo_pref,
-                                               fin);
+                                               pjz[r], Fx, Fy, Fz, inv_tau, guo_pref, fin);
                 }
             }
         }
@@ -652,40 +680,26 @@ __device__ __forceinline__ void step_rows(const BoxDesc& bd, const T* __restrict
                 if (!stk[k]) continue;
                 const int lx = lxk[k];
                 const int xw = lx == 0 ? nx - 1 : lx - 1, xe = lx == nx - 1 ? 0 : lx + 1;
-                const int r0 = (lyk[k] - 1) * nx, r1 = lyk[k] * nx, r2 = (lyk[k] + 1) * nx;
-                const C c_e = pc[r1 + xe], c_w = pc[r1 + xw];
-                const C c_n = pc[r2 + lx], c_s = pc[r0 + lx];
-                const C c_ne = pc[r2 + xe], c_nw = pc[r2 + xw];
-                const C c_se = pc[r0 + xe], c_sw = pc[r0 + xw];
-                const C p_c = pp[r1 + lx], p_e = pp[r1 + xe], p_w = pp[r1 + xw];
-                const C p_n = pp[r2 + lx], p_s = pp[r0 + lx];
-                const C m_c = pm[r1 + lx], m_e = pm[r1 + xe], m_w = pm[r1 + xw];
-                const C m_n = pm[r2 + lx], m_s = pm[r0 + lx];
-                const C psi0 = pc[r1 + lx];
-                const C w1 = (C)W1, w2 = (C)W2;
-                // S = sum_a w_a psi(x + xi_a) xi_a; F = -G psi(x) S (Eq. SCForce, c_s^2 W_a = w_a)
-                const C Sx = w1 * (c_e - c_w) +
-                             w2 * ((c_ne - c_nw) + (c_se - c_sw) + (p_e - p_w) + (m_e - m_w));
-                const C Sy = w1 * (c_n - c_s) +
-                             w2 * ((c_ne - c_se) + (c_nw - c_sw) + (p_n - p_s) + (m_n - m_s));
-                const C Sz = w1 * (p_c - m_c) +
-                             w2 * ((p_e - m_e) + (p_w - m_w) + (p_n - m_n) + (p_s - m_s));
-                const C gp = -G * psi0;
+                const int r1 = lyk[k] * nx;
+                const int xs[3] = {xw, lx, xe};
+                C Fx, Fy, Fz;
+                sc_force<C>([&](int dx, int dy, int dz) {
+                    return (dz < 0 ? pm : dz > 0 ? pp : pc)[r1 + dy * nx + xs[dx + 1]];
+                }, G, Fx, Fy, Fz);
                 unsigned xo[3], yo[3];
                 node_offsets(k, xo, yo);
                 const unsigned off = yo[1] + (unsigned)xk[k] * E;
                 const unsigned key = qkey + (unsigned)yk[k] * (unsigned)nx + (unsigned)xk[k];
                 if constexpr (TAU1) {
                     collide_store<T, C, true>(qr, popb, off, key, rho_ref, pdn[k], pjx[k], pjy[k],
-                                              pjz[k], gp * Sx, gp * Sy, gp * Sz, inv_tau, guo_pref,
+                                              pjz[k], Fx, Fy, Fz, inv_tau, guo_pref,
                                               (const T*)nullptr);
                 } else {
                     // the pre-collision populations of plane q, pulled again
                     T fin[Q];
                     load_node(planes(p - 1), popb, yo, xo, fin);
                     collide_store<T, C, false>(qr, popb, off, key, rho_ref, pdn[k], pjx[k], pjy[k],
-                                               pjz[k], gp * Sx, gp * Sy, gp * Sz, inv_tau, guo_pref,
-                                               fin);
+                                               pjz[k], Fx, Fy, Fz, inv_tau, guo_pref, fin);
                 }
             }
         }
@@ -719,6 +733,325 @@ __global__ __launch_bounds__(64 * WAVES) void k_step(StepArgs a, const T* __rest
     unsigned* tout = logical == 0 ? a.b.tick + (1 - a.s) : nullptr;
     if constexpr (BXT == 0) step_rows<T, C, PSI, TAU1, R, WAVES>(a.b, src, dst, a.by, tiy, z0, z1, tin, tout, ring);
     else step_tile<T, C, PSI, TAU1, R, PF, WAVES, BXT>(a.b, src, dst, tix, tiy, z0, z1, tin, tout, ring);
+}
+
+// ------------------------------------------------------------------------------------------
+// Two time steps per pass (FP32 storage and arithmetic, tau = 1). A single step streams every
+// population in and out of HBM once; here a workgroup keeps the first step's post-collision
+// populations of its region in LDS and applies the second step to them, so the box streams
+// through HBM once per two steps. The workgroup owns a 64 x 8 tile of the second step's output
+// and marches a z chunk. Per plane p it
+//   1. pulls the populations of the tile plus a 3-node ring (70 x 14 nodes) from memory (loaded
+//      during the previous plane's work): their density and momentum, and psi(t) into an LDS
+//      ring of four planes;
+//   2. collides plane p - 1 for the tile plus a 2-node ring (68 x 12): the first step, written
+//      to LDS (one plane of 19 populations);
+//   3. gathers from that plane the populations each node of the tile plus a 1-node ring
+//      (66 x 10) pulls: f_i(x, t + 1) = f*_i(x - xi_i, t) comes from plane z - cz_i, so a node of
+//      plane p - 2 is complete now (its cz = +1 populations were gathered two planes ago and its
+//      cz = 0 ones one plane ago, held in registers), giving density, momentum and psi(t + 1);
+//   4. collides plane p - 3 of the tile (the second step) and stores it.
+// A chunk of planes [z0, z1) therefore pulls planes z0 - 3 .. z1 + 2. Both steps collide through
+// the same routines as the single-step kernels (sc_force, collide_emit) on the same inputs, and
+// the first step's values are rounded to FP32 exactly as they would be stored, so two steps here
+// give the same bits as two single steps.
+// ------------------------------------------------------------------------------------------
+// Geometry of a two-step tile BY rows high (64 wide) worked by WAVES waves: each thread owns
+// BY / WAVES nodes of the second step's tile.
+template <int BY, int WAVES>
+struct T2Geom {
+    static constexpr int BX = 64, NT = 64 * WAVES;
+    static constexpr int NO = BY / WAVES;                   // own nodes per thread
+    static constexpr int LX = BX + 6, LY = BY + 6;          // pulled from memory: tile + 3
+    static constexpr int AX = BX + 4, AY = BY + 4;          // first step: tile + 2
+    static constexpr int GX = BX + 2, GY = BY + 2;          // second step's densities: tile + 1
+    static constexpr int NL = LX * LY;
+    static constexpr int NSA = (NL + NT - 1) / NT;          // pulled-node slots per thread
+    static constexpr int NHR = 2 * GX + 2 * BY;             // ring nodes of the second step
+    static constexpr int NSH = (NHR + NT - 1) / NT;         // ring slots per thread
+    static constexpr int NB = NO + NSH;                     // gather slots per thread
+    static_assert(NO * WAVES == BY, "the tile height must be a multiple of the waves");
+};
+
+template <int BY, int WAVES>
+struct Ring2 {
+    using G = T2Geom<BY, WAVES>;
+    float psa[4][G::LY][G::LX];   // psi(t) of the pulled nodes, planes p - 3 .. p (mod 4)
+    float fs[Q][G::AY][G::AX];    // first step's populations of plane p - 1
+    float psb[4][G::GY][G::GX];   // psi(t + 1) of the tile plus one, planes p - 5 .. p - 2
+};
+
+template <int PSI, int BY, int WAVES, bool PF>
+__device__ __forceinline__ void step_tile2(const BoxDesc& bd, const float* __restrict__ src,
+                                           float* __restrict__ dst, int tix, int tiy, int z0,
+                                           int z1, const unsigned* tick_in, unsigned* tick_out,
+                                           Ring2<BY, WAVES>& rg)
+{
+    using T = float;
+    using C = float;
+    using Gm = T2Geom<BY, WAVES>;
+    constexpr int NT = Gm::NT, NSA = Gm::NSA, NO = Gm::NO, NB = Gm::NB;
+    constexpr int LX = Gm::LX, AX = Gm::AX, AY = Gm::AY, BCX = Gm::GX;
+    constexpr unsigned E = sizeof(T);
+    const int nx = bd.nx, ny = bd.ny, nz = bd.nz;
+    const PopBuf sbuf = make_popbuf(src, bd.pp);
+    const PopBuf dbuf = make_popbuf(dst, bd.pp);
+    const unsigned popb = sbuf.pop_bytes;
+    const C rho_ref = (C)bd.rho_ref;
+    const C G = (C)bd.G;
+    const unsigned rowb = bd.px * E;
+    const unsigned nxy = bd.nxy;
+    const int x0 = tix * Gm::BX, y0 = tiy * BY;
+    const int t = threadIdx.x;
+
+    // pulled nodes: slot k of thread t is node s = t + k NT of the (BX + 6) x (BY + 6) region, at
+    // LDS position (ly, lx) of psa; nodes of the (BX + 4) x (BY + 4) region inside it also
+    // collide (first step)
+    int sx[NSA], sy[NSA];
+    bool sin_[NSA], sa[NSA];
+    unsigned sxo[NSA][3], syo[NSA][3], skey[NSA];
+#pragma unroll
+    for (int k = 0; k < NSA; ++k) {
+        const int sidx = t + k * NT;
+        sin_[k] = sidx < Gm::NL;
+        const int lx = sin_[k] ? sidx % LX : 0, ly = sin_[k] ? sidx / LX : 0;
+        sx[k] = lx;
+        sy[k] = ly;
+        sa[k] = sin_[k] && lx >= 1 && lx <= AX && ly >= 1 && ly <= AY;
+        const int x = wrapi(x0 - 3 + lx, nx), y = wrapi(y0 - 3 + ly, ny);
+        sxo[k][0] = (unsigned)wrapi(x - 1, nx) * E;
+        sxo[k][1] = (unsigned)x * E;
+        sxo[k][2] = (unsigned)wrapi(x + 1, nx) * E;
+        syo[k][0] = (unsigned)wrapi(y - 1, ny) * rowb;
+        syo[k][1] = (unsigned)y * rowb;
+        syo[k][2] = (unsigned)wrapi(y + 1, ny) * rowb;
+        skey[k] = (unsigned)y * (unsigned)nx + (unsigned)x;   // the node's index in its plane
+    }
+    // second step: slots j < NO are the thread's own nodes (lane, wave + j WAVES) of the tile,
+    // slots NO + h nodes of the ring around it (ring node t + h NT); (bx, by) tile coordinates
+    const int lane = t & 63, wv = t >> 6;
+    int bx[NB], by[NB];
+    bool bon[NB];
+#pragma unroll
+    for (int j = 0; j < NO; ++j) {
+        bx[j] = lane;
+        by[j] = wv + j * WAVES;
+        bon[j] = true;
+    }
+#pragma unroll
+    for (int h = 0; h < Gm::NSH; ++h) {
+        const int r = t + h * NT;
+        bon[NO + h] = r < Gm::NHR;
+        int hx = 0, hy = 0;
+        if (r < BCX) {
+            hx = r - 1;
+            hy = -1;
+        } else if (r < 2 * BCX) {
+            hx = r - BCX - 1;
+            hy = BY;
+        } else if (r < 2 * BCX + BY) {
+            hx = -1;
+            hy = r - 2 * BCX;
+        } else if (r < Gm::NHR) {
+            hx = Gm::BX;
+            hy = r - 2 * BCX - BY;
+        }
+        bx[NO + h] = hx;
+        by[NO + h] = hy;
+    }
+    // own nodes are stored if they lie in the box (lanes over row padding store values nobody
+    // reads, so that every line is written whole)
+    const int xg = x0 + lane;
+    bool ost[NO];
+    unsigned ooff[NO], okey[NO];
+#pragma unroll
+    for (int j = 0; j < NO; ++j) {
+        const int yg = y0 + by[j];
+        ost[j] = xg < (int)bd.px && yg < ny;
+        ooff[j] = (unsigned)(ost[j] ? yg : 0) * rowb + (unsigned)(ost[j] ? xg : 0) * E;
+        okey[j] = (unsigned)(ost[j] ? yg : 0) * (unsigned)nx + (unsigned)(ost[j] ? xg : 0);
+    }
+
+    auto planes = [&](int p) {
+        return Planes{plane_rsrc(sbuf, wrapi(p - 1, nz)), plane_rsrc(sbuf, wrapi(p, nz)),
+                      plane_rsrc(sbuf, wrapi(p + 1, nz))};
+    };
+
+    double pdn[NSA];                           // pulled nodes: moments of the previous plane
+    C pjx[NSA], pjy[NSA], pjz[NSA];
+#pragma unroll
+    for (int k = 0; k < NSA; ++k) {
+        pdn[k] = 0.0;
+        pjx[k] = pjy[k] = pjz[k] = C(0);
+    }
+    T stz[NB][Q] = {}, st1[NB][Q] = {}, st2[NB][Q] = {};   // gathered cz = 0 / cz = +1 values
+    double bdn[NO];                            // own nodes: moments of the last completed plane
+    C bjx[NO], bjy[NO], bjz[NO];
+#pragma unroll
+    for (int j = 0; j < NO; ++j) {
+        bdn[j] = 0.0;
+        bjx[j] = bjy[j] = bjz[j] = C(0);
+    }
+    unsigned tkv = 0u, tk = 0u, seed_a = 0u, seed_b = 0u;
+    const int nk = (z1 - z0) + 6;
+    // PF: the populations of the next plane are loaded one iteration ahead, so that the loads are
+    // in flight while the two collisions of the current iteration run
+    T fnx[NSA][Q];
+    if constexpr (PF) {
+        const Planes zr = planes(z0 - 3);
+#pragma unroll
+        for (int k = 0; k < NSA; ++k)
+            if (sin_[k]) load_node(zr, popb, syo[k], sxo[k], fnx[k]);
+    }
+    for (int kp = 0; kp < nk; ++kp) {
+        const int p = z0 - 3 + kp;
+        if (kp == 1) {
+            tk = __builtin_amdgcn_readfirstlane(tkv);
+            seed_a = dither_shift(tk);
+            seed_b = dither_shift(tk + 1u);
+        }
+        // 1. plane p: moments and psi(t) of the pulled nodes, then the loads of plane p + 1
+        double cdn[NSA];
+        C cjx[NSA], cjy[NSA], cjz[NSA];
+        {
+            float(*ps)[LX] = rg.psa[p & 3];
+            const Planes zc = planes(p);
+#pragma unroll
+            for (int k = 0; k < NSA; ++k) {
+                cdn[k] = 0.0;
+                cjx[k] = cjy[k] = cjz[k] = C(0);
+                if (sin_[k]) {
+                    if constexpr (!PF) load_node(zc, popb, syo[k], sxo[k], fnx[k]);
+                    moments(fnx[k], cdn[k], cjx[k], cjy[k], cjz[k]);
+                    ps[sy[k]][sx[k]] = psi_of<C, PSI>(rho_ref + (C)cdn[k]);
+                }
+            }
+            if (PF && kp + 1 < nk) {
+                const Planes zr = planes(p + 1);
+#pragma unroll
+                for (int k = 0; k < NSA; ++k)
+                    if (sin_[k]) load_node(zr, popb, syo[k], sxo[k], fnx[k]);
+            }
+        }
+        tkv = __hip_atomic_load(tick_in, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        __syncthreads();
+        // 2. first step on plane q = p - 1
+        if (kp >= 2) {
+            const float(*am)[LX] = rg.psa[(p - 2) & 3];
+            const float(*ac)[LX] = rg.psa[(p - 1) & 3];
+            const float(*ap)[LX] = rg.psa[p & 3];
+            const unsigned qkey = (unsigned)wrapi(p - 1, nz) * nxy + seed_a;
+#pragma unroll
+            for (int k = 0; k < NSA; ++k) {
+                if (!sa[k]) continue;
+                const int lx = sx[k], ly = sy[k];
+                C Fx, Fy, Fz;
+                sc_force<C>([&](int dx, int dy, int dz) {
+                    return (dz < 0 ? am : dz > 0 ? ap : ac)[ly + dy][lx + dx];
+                }, G, Fx, Fy, Fz);
+                collide_emit<T, C, true>(
+                    [&](auto I, T v) { rg.fs[decltype(I)::value][ly - 1][lx - 1] = v; },
+                    qkey + skey[k], rho_ref, pdn[k], pjx[k], pjy[k], pjz[k], Fx, Fy, Fz, C(1),
+                    C(0.5), (const T*)nullptr);
+            }
+        }
+        __syncthreads();
+        // 3. gather from plane p - 1; plane c = p - 2 of the second step is then complete
+        double ndn[NO];
+        C njx[NO], njy[NO], njz[NO];
+#pragma unroll
+        for (int j = 0; j < NO; ++j) {
+            ndn[j] = 0.0;
+            njx[j] = njy[j] = njz[j] = C(0);
+        }
+        if (kp >= 2) {
+            float(*pb)[BCX] = rg.psb[(p - 2) & 3];
+#pragma unroll
+            for (int k = 0; k < NB; ++k) {
+                if (!bon[k]) continue;
+                const int gx = bx[k] + 2, gy = by[k] + 2;   // fs coordinates of the node
+                T cur[Q];
+                static_for<0, Q>([&](auto I) {
+                    constexpr int i = decltype(I)::value;
+                    const T v = rg.fs[i][gy - CY[i]][gx - CX[i]];
+                    if constexpr (CZ[i] < 0) {
+                        cur[i] = v;
+                    } else if constexpr (CZ[i] == 0) {
+                        cur[i] = stz[k][i];
+                        stz[k][i] = v;
+                    } else {
+                        cur[i] = st2[k][i];
+                        st2[k][i] = st1[k][i];
+                        st1[k][i] = v;
+                    }
+                });
+                double dn;
+                C jx, jy, jz;
+                moments(cur, dn, jx, jy, jz);
+                pb[by[k] + 1][bx[k] + 1] = psi_of<C, PSI>(rho_ref + (C)dn);
+                if (k < NO) {
+                    ndn[k] = dn;
+                    njx[k] = jx;
+                    njy[k] = jy;
+                    njz[k] = jz;
+                }
+            }
+        }
+        __syncthreads();
+        // 4. second step on plane r = p - 3, stored
+        if (kp >= 6) {
+            const float(*bm)[BCX] = rg.psb[(p - 4) & 3];
+            const float(*bc)[BCX] = rg.psb[(p - 3) & 3];
+            const float(*bp)[BCX] = rg.psb[(p - 2) & 3];
+            const int r = p - 3;   // in [z0, z1): no wrap
+            const Rsrc rr = plane_rsrc(dbuf, r);
+            const unsigned rkey = (unsigned)r * nxy + seed_b;
+#pragma unroll
+            for (int j = 0; j < NO; ++j) {
+                if (!ost[j]) continue;
+                const int lx = bx[j] + 1, ly = by[j] + 1;
+                C Fx, Fy, Fz;
+                sc_force<C>([&](int dx, int dy, int dz) {
+                    return (dz < 0 ? bm : dz > 0 ? bp : bc)[ly + dy][lx + dx];
+                }, G, Fx, Fy, Fz);
+                collide_store<T, C, true>(rr, popb, ooff[j], rkey + okey[j], rho_ref, bdn[j],
+                                          bjx[j], bjy[j], bjz[j], Fx, Fy, Fz, C(1), C(0.5),
+                                          (const T*)nullptr);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < NO; ++j) {
+            bdn[j] = ndn[j];
+            bjx[j] = njx[j];
+            bjy[j] = njy[j];
+            bjz[j] = njz[j];
+        }
+#pragma unroll
+        for (int k = 0; k < NSA; ++k) {
+            pdn[k] = cdn[k];
+            pjx[k] = cjx[k];
+            pjy[k] = cjy[k];
+            pjz[k] = cjz[k];
+        }
+    }
+    if (tick_out && t == 0) *tick_out = tk + 2u;
+}
+
+template <int PSI, int BY, int WAVES, bool PF>
+__global__ __launch_bounds__(64 * WAVES) void k_step2(StepArgs a, const float* __restrict__ src,
+                                                      float* __restrict__ dst)
+{
+    __shared__ Ring2<BY, WAVES> ring;
+    const unsigned logical = a.remap ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
+    const int tix = (int)(logical % (unsigned)a.tiles_x);
+    const unsigned t2 = logical / (unsigned)a.tiles_x;
+    const int tiy = (int)(t2 % (unsigned)a.tiles_y);
+    const int ch = (int)(t2 / (unsigned)a.tiles_y);
+    const int z0 = ch * a.zc;
+    const int z1 = min(z0 + a.zc, a.b.nz);
+    const unsigned* tin = a.b.tick + a.s;
+    unsigned* tout = logical == 0 ? a.b.tick + (1 - a.s) : nullptr;
+    step_tile2<PSI, BY, WAVES, PF>(a.b, src, dst, tix, tiy, z0, z1, tin, tout, ring);
 }
 
 // ------------------------------------------------------------------------------------------

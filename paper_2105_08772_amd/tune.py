@@ -18,6 +18,9 @@ SHAPES = [dict(waves=4, rows=r, prefetch=pf, tile_x=64) for r in (1, 2, 4) for p
          [dict(waves=8, rows=r, prefetch=0, tile_x=bx) for r in (1, 2) for bx in (64, 32)] + \
          [dict(waves=8, rows=r, prefetch=0, tile_x=0) for r in (2, 4, 8)] + \
          [dict(waves=4, rows=4, prefetch=0, tile_x=0)]   # full-row tiles
+# two steps per pass (single boxes, FP32 storage and arithmetic, tau = 1)
+SHAPES2 = [dict(waves=8, rows=1, prefetch=pf, tile_x=64) for pf in (0, 1)] + \
+          [dict(waves=16, rows=2, prefetch=0, tile_x=64)]
 
 
 def group_candidates():
@@ -61,11 +64,17 @@ def tune_group(group, steps=8, candidates=None, log=None):
     return dict(best[1], seconds_per_step=best[0])
 
 
-def box_candidates(nz):
+def box_candidates(nz, two_step=True):
+    """Single-step shapes, and (two_step: FP32 boxes at tau = 1) the two-steps-per-pass shapes,
+    each with z chunks of 8..128 planes and the XCD remap on or off."""
     out = []
     for shape, zc, remap in itertools.product(SHAPES, (8, 16, 32, 64, 128), (0, 1)):
         if zc <= max(nz, 8):
-            out.append(dict(shape, z_chunk=zc, xcd_remap=remap))
+            out.append(dict(shape, z_chunk=zc, xcd_remap=remap, steps_per_pass=1))
+    if two_step:
+        for shape, zc, remap in itertools.product(SHAPES2, (8, 16, 32, 64, 128), (0, 1)):
+            if zc <= max(nz, 8):
+                out.append(dict(shape, z_chunk=zc, xcd_remap=remap, steps_per_pass=2))
     return out
 
 
@@ -76,7 +85,7 @@ def tune_box(box, steps=16, candidates=None, log=None):
     for cand in candidates or box_candidates(box.dims[2]):
         try:
             box.set_launch(cand["rows"], cand["z_chunk"], cand["xcd_remap"], cand["prefetch"],
-                           cand["waves"], cand["tile_x"])
+                           cand["waves"], cand["tile_x"], 64, cand.get("steps_per_pass", 1))
         except LbmScError:
             continue
         box.step(2)
@@ -93,5 +102,5 @@ def tune_box(box, steps=16, candidates=None, log=None):
         raise ValueError("no candidate launch shape fits this box")
     c = best[1]
     box.set_launch(c["rows"], c["z_chunk"], c["xcd_remap"], c["prefetch"], c["waves"],
-                   c["tile_x"])
+                   c["tile_x"], 64, c.get("steps_per_pass", 1))
     return dict(c, seconds_per_step=best[0])

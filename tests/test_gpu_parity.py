@@ -81,10 +81,8 @@ def test_one_step_fp32_shifted(dims, tau, prefetch):
     G = 1.3 * lbm.lbm_sc_gc(0)
     with make_box(dims, prec=lbm.LBM_SC_FP32_SHIFTED, tau=tau, rho_ref=rho_ref) as b:
         b.set(f)
-        lc = b.launch()
-        # prefetch is compiled for 4-wave workgroups
-        b.set_launch(lc["rows"], lc["z_chunk"], lc["xcd_remap"], prefetch,
-                     4 if prefetch else lc["waves"], lc["tile_x"])
+        # the single-step kernel in its default tile (prefetch is compiled for 4-wave workgroups)
+        b.set_launch(2, dims[2], 1, prefetch, 4 if prefetch else 8, 64)
         b.step(1)
         g = b.get()
     ref = core.step(f, G, tau, 0)
@@ -152,7 +150,7 @@ def test_launch_shapes_are_bitwise_identical(prec):
             b.set(f)
             b.set_launch(rows, zc, remap, pf, waves, tx)
             assert b.launch() == dict(rows=rows, z_chunk=min(zc, 33), xcd_remap=remap, prefetch=pf,
-                                      waves=waves, tile_x=tx, graph_steps=64)
+                                      waves=waves, tile_x=tx, graph_steps=64, steps_per_pass=1)
             b.step(3)
             outs.append(b.get())
     for o in outs[1:]:
@@ -185,10 +183,8 @@ def test_graph_replay_equals_plain_launches():
     runs = {}
     for K in (0, 2, 6):
         with make_box(dims, prec=lbm.LBM_SC_FP32_SHIFTED, rho_ref=rho_ref) as b:
-            lc = b.launch()
             b.set(f)
-            b.set_launch(lc["rows"], lc["z_chunk"], lc["xcd_remap"], lc["prefetch"], lc["waves"],
-                         lc["tile_x"], K)
+            b.set_launch(2, dims[2], 1, 0, 8, 64, K)   # single steps (two-step graphs: their own test)
             out = []
             for n in (1, 6, 7, 13, 2):
                 b.step(n)
