@@ -62,8 +62,8 @@ def run(dims, f, counts, psi=0, packed=0, two=False, zc=None, graph_steps=64, sh
         return out
 
 
-DIMS = [(4, 4, 4), (1, 1, 8), (3, 5, 7), (37, 29, 11), (64, 8, 9), (65, 9, 10), (130, 17, 13),
-        (100, 37, 21), (200, 3, 5)]
+DIMS = [(4, 4, 4), (1, 1, 8), (3, 5, 7), (5, 4, 1), (9, 7, 2), (37, 29, 11), (64, 8, 9),
+        (65, 9, 10), (130, 17, 13), (100, 37, 21), (200, 3, 5)]
 
 
 @pytest.mark.parametrize("dims", DIMS)
