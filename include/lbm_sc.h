@@ -202,9 +202,11 @@ int lbm_sc_set_step(lbm_sc* h, int64_t step);
  * rows*64*waves/px - 2 rows, px being the row pitch (less up to 31 slots that align packed rows
  * with the line grid; LBM_SC_EINVAL if that is below 1). steps_per_pass = 2 selects the
  * two-steps-per-pass kernel instead (FP32 storage and arithmetic, tau = 1), whose shapes are
- * tile_x 64 with rows 1 and waves 8 (64 x 8 tiles, either prefetch setting) or rows 2 and waves
- * 16 (64 x 16 tiles, prefetch 0); it is the default for those boxes (64 x 8, prefetch 1), and
- * lbm_sc_get_launch reports the shape of the kernel in use. */
+ * tile_x 64 with rows 1 and waves 8 (64 x 8 tiles, either prefetch setting), tile_x 32 with rows
+ * 2 and waves 8 (32 x 16 tiles, either prefetch setting) or tile_x 64 with rows 2 and waves 16
+ * (64 x 16 tiles, prefetch 0); it is the default for those boxes (32 x 16 without prefetch from
+ * 3 M nodes, 64 x 8 with prefetch below), and lbm_sc_get_launch reports the shape of the kernel
+ * in use. */
 typedef struct {
     int32_t rows;       /* tile rows per wave: 1, 2 or 4 (full-row tiles: nodes per thread, 2, 4, 8) */
     int32_t z_chunk;    /* planes per workgroup, >= 1 (clamped to nz) */

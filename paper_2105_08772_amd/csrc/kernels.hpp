@@ -55,12 +55,15 @@ inline bool shape_supported(const StepShape& s)
 
 inline int tile_height(const StepShape& s) { return s.waves * s.rows * (64 / s.tile_x); }
 
-// Shapes of the two-steps-per-pass kernel (tile_x 64): 64 x 8 tiles of 8 waves (rows 1), with or
-// without the next plane prefetched, or 64 x 16 tiles of 16 waves (rows 2, no prefetch).
+// Shapes of the two-steps-per-pass kernel: tiles tile_x wide and 8 * rows high with one node of
+// the second step per thread, i.e. waves = tile_x * 8 * rows / 64: 64 x 8 (rows 1, waves 8) or
+// 32 x 16 (rows 2, waves 8), either prefetch setting, or 64 x 16 (rows 2, waves 16, prefetch 0).
 inline bool step2_shape_supported(const StepShape& s)
 {
-    if (s.z_chunk < 1 || (s.xcd_remap & ~1) || (s.prefetch & ~1) || s.tile_x != 64) return false;
-    return (s.rows == 1 && s.waves == 8) || (s.rows == 2 && s.waves == 16 && s.prefetch == 0);
+    if (s.z_chunk < 1 || (s.xcd_remap & ~1) || (s.prefetch & ~1)) return false;
+    return (s.tile_x == 64 && s.rows == 1 && s.waves == 8) ||
+           (s.tile_x == 32 && s.rows == 2 && s.waves == 8) ||
+           (s.tile_x == 64 && s.rows == 2 && s.waves == 16 && s.prefetch == 0);
 }
 
 // Interior rows of a full-row tile for row pitch px: the tile pulls by + 2 rows of px nodes into
@@ -149,10 +152,10 @@ LBM_STEP_DECL(f32)
 LBM_STEP_DECL(m64)
 LBM_STEP_DECL(f64)
 #undef LBM_STEP_DECL
-// Two time steps per pass for FP32 storage and arithmetic at tau = 1 (64 x 8 tiles, z chunks of
-// zc planes): the state in src after t steps becomes the state in dst after t + 2.
-hipError_t launch_step2_f32(const BoxDesc& b, int rows, int waves, int prefetch, int zc, int remap,
-                            int sbuf, const void* src, void* dst, hipStream_t st);
+// Two time steps per pass for FP32 storage and arithmetic at tau = 1 (shape s, see
+// step2_shape_supported): the state in src after t steps becomes the state in dst after t + 2.
+hipError_t launch_step2_f32(const BoxDesc& b, const StepShape& s, int sbuf, const void* src,
+                            void* dst, hipStream_t st);
 // Multi-box step. nitems work items; persistent: grid of `workers` workgroups over the queues.
 hipError_t launch_step_group(bool fp32, bool math64, const StepShape& s, const GroupBox* boxes, int nbox,
                              unsigned nitems, int parity, int persistent, unsigned workers,

@@ -26,8 +26,8 @@ const char* const SHAPE_MSG =
     "prefetch; tile_x 32: rows 1, 2 (waves 8: no prefetch); tile_x 0: no prefetch, waves 8 with rows 2, 4 or 8, or waves 4 with rows 4)";
 
 const char* const SHAPE2_MSG =
-    "unsupported two-step launch shape (tile_x 64 with rows 1 and waves 8, or rows 2 and waves 16 "
-    "without prefetch)";
+    "unsupported two-step launch shape (tile_x 64 with rows 1 and waves 8, tile_x 32 with rows 2 and "
+    "waves 8, or tile_x 64 with rows 2 and waves 16 without prefetch)";
 
 int fail(int code, const char* msg)
 {
@@ -559,16 +559,20 @@ void default_shape(lbm_sc* h)
     // latency; with prefetch, or eight waves in one workgroup, one workgroup per CU suffices
     const int slots = cus * (h->shape.prefetch ? 1 : std::max(1, 8 / h->shape.waves));
     h->shape.z_chunk = z_chunk_for(h->box, h->shape.tile_x, lbm::tile_height(h->shape), slots, 2);
-    // FP32 storage and arithmetic at tau = 1: two steps per pass, 64 x 8 tiles of 8 waves with the
-    // next plane prefetched (one workgroup per CU: 88 KB of LDS), each chunk pulling 6 planes more
-    // than it steps; measured 1.11-1.22x the single-step rate for boxes of 128^3 to 384^3, equal at
-    // 96^3, and faster on small boxes
-    h->shape2.rows = 1;
+    // FP32 storage and arithmetic at tau = 1: two steps per pass, each chunk pulling 6 planes more
+    // than it steps. Boxes of 3 M nodes or more: 32 x 16 tiles of 8 waves without prefetch (78 KB
+    // of LDS and 128 VGPRs: two workgroups per CU); smaller ones: 64 x 8 tiles of 8 waves with the
+    // next plane prefetched (one workgroup per CU). Measured against the 64 x 8 tiles: 3-13 %
+    // faster from 160^3 to 384^3, 4 % at 96^3, 3 % slower at 128^3 and 24-29 % slower at 48^3 and
+    // 64^3; the two-step kernel runs 1.11-1.22x the single-step rate for boxes of 128^3 to 384^3
+    // in 64 x 8 tiles
+    const bool big = (double)h->box.n >= 3.0e6;
+    h->shape2.rows = big ? 2 : 1;
     h->shape2.waves = 8;
-    h->shape2.prefetch = 1;
-    h->shape2.tile_x = 64;
+    h->shape2.prefetch = big ? 0 : 1;
+    h->shape2.tile_x = big ? 32 : 64;
     h->shape2.xcd_remap = 1;
-    h->shape2.z_chunk = z_chunk_for(h->box, 64, 8, cus, 6);
+    h->shape2.z_chunk = big ? z_chunk_for(h->box, 32, 16, 2 * cus, 6) : z_chunk_for(h->box, 64, 8, cus, 6);
     h->spp = (h->fp32 && !h->math64 && h->box.tau == 1.0) ? 2 : 1;
 }
 
@@ -859,9 +863,7 @@ int lbm_sc_step(lbm_sc* h, int64_t nsteps)
     // other buffer
     auto launch = [&](int c, int steps) -> hipError_t {
         if (steps == 2)
-            return lbm::launch_step2_f32(h->box, h->shape2.rows, h->shape2.waves, h->shape2.prefetch,
-                                         h->shape2.z_chunk, h->shape2.xcd_remap, c, h->pop[c],
-                                         h->pop[1 - c], h->stream);
+            return lbm::launch_step2_f32(h->box, h->shape2, c, h->pop[c], h->pop[1 - c], h->stream);
         return lbm::launch_step(h->fp32, h->math64, h->box, h->shape, c, h->pop[c], h->pop[1 - c],
                                 h->stream);
     };
@@ -1020,7 +1022,7 @@ int lbm_sc_get_info(lbm_sc* h, lbm_sc_info* out)
     out->bytes_per_step = (int64_t)2 * 19 * (int64_t)h->elem * (int64_t)h->box.n;
     int bx, by;
     if (h->spp == 2) {
-        bx = 64;
+        bx = h->shape2.tile_x;
         by = 8 * h->shape2.rows;
     } else {
         tile_dims(h->shape, h->box, bx, by);

@@ -9,10 +9,11 @@ hipError_t launch_step_f32(const BoxDesc& b, const StepShape& s, int sbuf, const
     return launch_step_impl<float, float>(b, s, sbuf, src, dst, st);
 }
 
-// Two time steps per pass (FP32 storage and arithmetic, tau = 1): 64-wide tiles of rows x 8 rows
-// worked by waves wave64s (rows 1 with waves 8, either prefetch setting; rows 2 with waves 16), z
+// Two time steps per pass (FP32 storage and arithmetic, tau = 1): tiles tile_x wide and 8 * rows
+// high, worked by tile_x * 8 * rows / 64 waves (one node of the second step per thread): 64 x 8
+// with 8 waves or 32 x 16 with 8 waves, either prefetch setting, or 64 x 16 with 16 waves; z
 // chunks of zc planes (clamped to nz).
-template <int BY, int WAVES, bool PF>
+template <int BX, int BY, int WAVES, bool PF, int MINW = 1>
 hipError_t launch_step2_t(const BoxDesc& b, int zc, int remap, int sbuf, const void* src, void* dst,
                           hipStream_t st)
 {
@@ -20,7 +21,7 @@ hipError_t launch_step2_t(const BoxDesc& b, int zc, int remap, int sbuf, const v
     a.b = b;
     a.s = sbuf;
     a.by = 0;
-    a.tiles_x = (b.nx + 63) / 64;
+    a.tiles_x = (b.nx + BX - 1) / BX;
     a.tiles_y = (b.ny + BY - 1) / BY;
     a.zc = zc < b.nz ? zc : b.nz;
     if (a.zc < 1) return hipErrorInvalidValue;
@@ -28,22 +29,26 @@ hipError_t launch_step2_t(const BoxDesc& b, int zc, int remap, int sbuf, const v
     a.remap = remap;
     const unsigned grid = (unsigned)(a.tiles_x * a.tiles_y * a.nchunks);
     if (b.psi == 0)
-        hipLaunchKernelGGL((k_step2<0, BY, WAVES, PF>), dim3(grid), dim3(64 * WAVES), 0, st, a,
+        hipLaunchKernelGGL((k_step2<0, BX, BY, WAVES, PF, MINW>), dim3(grid), dim3(64 * WAVES), 0, st, a,
                            (const float*)src, (float*)dst);
     else
-        hipLaunchKernelGGL((k_step2<1, BY, WAVES, PF>), dim3(grid), dim3(64 * WAVES), 0, st, a,
+        hipLaunchKernelGGL((k_step2<1, BX, BY, WAVES, PF, MINW>), dim3(grid), dim3(64 * WAVES), 0, st, a,
                            (const float*)src, (float*)dst);
     return hipGetLastError();
 }
 
-hipError_t launch_step2_f32(const BoxDesc& b, int rows, int waves, int prefetch, int zc, int remap,
-                            int sbuf, const void* src, void* dst, hipStream_t st)
+hipError_t launch_step2_f32(const BoxDesc& b, const StepShape& s, int sbuf, const void* src,
+                            void* dst, hipStream_t st)
 {
-    if (rows == 1 && waves == 8)
-        return prefetch ? launch_step2_t<8, 8, true>(b, zc, remap, sbuf, src, dst, st)
-                        : launch_step2_t<8, 8, false>(b, zc, remap, sbuf, src, dst, st);
-    if (rows == 2 && waves == 16 && !prefetch)
-        return launch_step2_t<16, 16, false>(b, zc, remap, sbuf, src, dst, st);
+    const int zc = s.z_chunk, remap = s.xcd_remap;
+    if (s.tile_x == 64 && s.rows == 1 && s.waves == 8)
+        return s.prefetch ? launch_step2_t<64, 8, 8, true>(b, zc, remap, sbuf, src, dst, st)
+                          : launch_step2_t<64, 8, 8, false>(b, zc, remap, sbuf, src, dst, st);
+    if (s.tile_x == 32 && s.rows == 2 && s.waves == 8)
+        return s.prefetch ? launch_step2_t<32, 16, 8, true>(b, zc, remap, sbuf, src, dst, st)
+                          : launch_step2_t<32, 16, 8, false, 4>(b, zc, remap, sbuf, src, dst, st);
+    if (s.tile_x == 64 && s.rows == 2 && s.waves == 16 && !s.prefetch)
+        return launch_step2_t<64, 16, 16, false>(b, zc, remap, sbuf, src, dst, st);
     return hipErrorInvalidValue;
 }
 

@@ -756,12 +756,12 @@ __global__ __launch_bounds__(64 * WAVES) void k_step(StepArgs a, const T* __rest
 // the first step's values are rounded to FP32 exactly as they would be stored, so two steps here
 // give the same bits as two single steps.
 // ------------------------------------------------------------------------------------------
-// Geometry of a two-step tile BY rows high (64 wide) worked by WAVES waves: each thread owns
-// BY / WAVES nodes of the second step's tile.
-template <int BY, int WAVES>
+// Geometry of a two-step tile BX wide and BY rows high worked by WAVES waves: each thread owns
+// BX BY / (64 WAVES) nodes of the second step's tile.
+template <int BX_, int BY, int WAVES>
 struct T2Geom {
-    static constexpr int BX = 64, NT = 64 * WAVES;
-    static constexpr int NO = BY / WAVES;                   // own nodes per thread
+    static constexpr int BX = BX_, NT = 64 * WAVES;
+    static constexpr int NO = BX * BY / NT;                 // own nodes per thread
     static constexpr int LX = BX + 6, LY = BY + 6;          // pulled from memory: tile + 3
     static constexpr int AX = BX + 4, AY = BY + 4;          // first step: tile + 2
     static constexpr int GX = BX + 2, GY = BY + 2;          // second step's densities: tile + 1
@@ -770,26 +770,26 @@ struct T2Geom {
     static constexpr int NHR = 2 * GX + 2 * BY;             // ring nodes of the second step
     static constexpr int NSH = (NHR + NT - 1) / NT;         // ring slots per thread
     static constexpr int NB = NO + NSH;                     // gather slots per thread
-    static_assert(NO * WAVES == BY, "the tile height must be a multiple of the waves");
+    static_assert(NO * NT == BX * BY, "the tile must be a whole number of nodes per thread");
 };
 
-template <int BY, int WAVES>
+template <int BX, int BY, int WAVES>
 struct Ring2 {
-    using G = T2Geom<BY, WAVES>;
+    using G = T2Geom<BX, BY, WAVES>;
     float psa[4][G::LY][G::LX];   // psi(t) of the pulled nodes, planes p - 3 .. p (mod 4)
     float fs[Q][G::AY][G::AX];    // first step's populations of plane p - 1
     float psb[4][G::GY][G::GX];   // psi(t + 1) of the tile plus one, planes p - 5 .. p - 2
 };
 
-template <int PSI, int BY, int WAVES, bool PF>
+template <int PSI, int BX, int BY, int WAVES, bool PF>
 __device__ __forceinline__ void step_tile2(const BoxDesc& bd, const float* __restrict__ src,
                                            float* __restrict__ dst, int tix, int tiy, int z0,
                                            int z1, const unsigned* tick_in, unsigned* tick_out,
-                                           Ring2<BY, WAVES>& rg)
+                                           Ring2<BX, BY, WAVES>& rg)
 {
     using T = float;
     using C = float;
-    using Gm = T2Geom<BY, WAVES>;
+    using Gm = T2Geom<BX, BY, WAVES>;
     constexpr int NT = Gm::NT, NSA = Gm::NSA, NO = Gm::NO, NB = Gm::NB;
     constexpr int LX = Gm::LX, AX = Gm::AX, AY = Gm::AY, BCX = Gm::GX;
     constexpr unsigned E = sizeof(T);
@@ -827,15 +827,16 @@ __device__ __forceinline__ void step_tile2(const BoxDesc& bd, const float* __res
         syo[k][2] = (unsigned)wrapi(y + 1, ny) * rowb;
         skey[k] = (unsigned)y * (unsigned)nx + (unsigned)x;   // the node's index in its plane
     }
-    // second step: slots j < NO are the thread's own nodes (lane, wave + j WAVES) of the tile,
-    // slots NO + h nodes of the ring around it (ring node t + h NT); (bx, by) tile coordinates
-    const int lane = t & 63, wv = t >> 6;
+    // second step: slots j < NO are the thread's own nodes o = t + j NT of the tile, at
+    // (o mod BX, o / BX), slots NO + h nodes of the ring around it (ring node t + h NT); (bx, by)
+    // are tile coordinates
     int bx[NB], by[NB];
     bool bon[NB];
 #pragma unroll
     for (int j = 0; j < NO; ++j) {
-        bx[j] = lane;
-        by[j] = wv + j * WAVES;
+        const int o = t + j * NT;
+        bx[j] = o % BX;
+        by[j] = o / BX;
         bon[j] = true;
     }
 #pragma unroll
@@ -861,12 +862,11 @@ __device__ __forceinline__ void step_tile2(const BoxDesc& bd, const float* __res
     }
     // own nodes are stored if they lie in the box (lanes over row padding store values nobody
     // reads, so that every line is written whole)
-    const int xg = x0 + lane;
     bool ost[NO];
     unsigned ooff[NO], okey[NO];
 #pragma unroll
     for (int j = 0; j < NO; ++j) {
-        const int yg = y0 + by[j];
+        const int xg = x0 + bx[j], yg = y0 + by[j];
         ost[j] = xg < (int)bd.px && yg < ny;
         ooff[j] = (unsigned)(ost[j] ? yg : 0) * rowb + (unsigned)(ost[j] ? xg : 0) * E;
         okey[j] = (unsigned)(ost[j] ? yg : 0) * (unsigned)nx + (unsigned)(ost[j] ? xg : 0);
@@ -1037,11 +1037,13 @@ __device__ __forceinline__ void step_tile2(const BoxDesc& bd, const float* __res
     if (tick_out && t == 0) *tick_out = tk + 2u;
 }
 
-template <int PSI, int BY, int WAVES, bool PF>
-__global__ __launch_bounds__(64 * WAVES) void k_step2(StepArgs a, const float* __restrict__ src,
-                                                      float* __restrict__ dst)
+// MINW: waves per SIMD the register allocation must allow (4: two 8-wave workgroups per CU, at
+// most 128 VGPRs).
+template <int PSI, int BX, int BY, int WAVES, bool PF, int MINW>
+__global__ __launch_bounds__(64 * WAVES, MINW) void k_step2(StepArgs a, const float* __restrict__ src,
+                                                            float* __restrict__ dst)
 {
-    __shared__ Ring2<BY, WAVES> ring;
+    __shared__ Ring2<BX, BY, WAVES> ring;
     const unsigned logical = a.remap ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
     const int tix = (int)(logical % (unsigned)a.tiles_x);
     const unsigned t2 = logical / (unsigned)a.tiles_x;
@@ -1051,7 +1053,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_step2(StepArgs a, const float* _
     const int z1 = min(z0 + a.zc, a.b.nz);
     const unsigned* tin = a.b.tick + a.s;
     unsigned* tout = logical == 0 ? a.b.tick + (1 - a.s) : nullptr;
-    step_tile2<PSI, BY, WAVES, PF>(a.b, src, dst, tix, tiy, z0, z1, tin, tout, ring);
+    step_tile2<PSI, BX, BY, WAVES, PF>(a.b, src, dst, tix, tiy, z0, z1, tin, tout, ring);
 }
 
 // ------------------------------------------------------------------------------------------

@@ -84,9 +84,13 @@ def test_committed_traffic_record_matches_the_current_step_kernels():
         "step kernel sources changed since the counters were taken: profile again"
     launch = dict(t["launch"], graph_steps=64)
     assert b.measured_traffic(t["nodes"], t["prec"], launch) == t["bytes_per_launch"]
-    # per step: reads at least the algorithmic bytes over the steps one launch keeps on chip,
-    # writes about them (a launch of two steps reads and writes the state once)
+    # per launch: reads at least one pass over the state (a launch of two steps reads and writes
+    # it once), at most that times the planes a z chunk pulls over the planes it steps (one more
+    # on each side for one step, three for two) and 20 % of halo re-reads in x and y; writes one
+    # pass
     spp = t.get("steps_per_launch", 1)
     alg = t["algorithmic_bytes_per_launch"] / 2 / spp
-    assert 1.0 <= t["fetch_bytes_per_launch"] / alg < 1.2
+    zc = t["launch"]["z_chunk"]
+    chunk = (zc + 2 * (2 * spp - 1)) / zc
+    assert 1.0 <= t["fetch_bytes_per_launch"] / alg < 1.2 * chunk
     assert 0.99 < t["write_bytes_per_launch"] / alg < 1.01

@@ -40,15 +40,15 @@ def box(dims, psi=0, packed=0, prec=lbm.LBM_SC_FP32_SHIFTED, tau=1.0):
 
 
 # two-step shapes (rows, waves, prefetch)
-SHAPES2 = [(1, 8, 1), (1, 8, 0), (2, 16, 0)]
+SHAPES2 = [(1, 8, 1, 64), (1, 8, 0, 64), (2, 16, 0, 64), (2, 8, 0, 32), (2, 8, 1, 32)]
 
 
-def set_two(b, shape=(1, 8, 1), zc=None, graph_steps=64):
-    rows, waves, pf = shape
-    b.set_launch(rows, zc or b.dims[2], 1, pf, waves, 64, graph_steps, 2)
+def set_two(b, shape=(1, 8, 1, 64), zc=None, graph_steps=64):
+    rows, waves, pf, tx = shape
+    b.set_launch(rows, zc or b.dims[2], 1, pf, waves, tx, graph_steps, 2)
 
 
-def run(dims, f, counts, psi=0, packed=0, two=False, zc=None, graph_steps=64, shape=(1, 8, 1)):
+def run(dims, f, counts, psi=0, packed=0, two=False, zc=None, graph_steps=64, shape=(1, 8, 1, 64)):
     with box(dims, psi, packed) as b:
         b.set(f)
         if two:
@@ -118,7 +118,7 @@ def test_two_steps_per_pass_droplet_observables_and_dither():
         else:
             assert np.array_equal(np.asarray(v), np.asarray(w)), k
     with lbm.Box(lbm.config(48, 40, 44, **cfg)) as b:
-        set_two(b, (2, 16, 0), zc=11)
+        set_two(b, (2, 8, 0, 32), zc=11)
         b.set(f1)
         b.set_step(2050)
         b.step(7)
@@ -162,9 +162,10 @@ def test_two_steps_per_pass_is_refused_where_it_does_not_apply():
             with pytest.raises(lbm.LbmScError):
                 b.set_launch(1, 16, 1, 1, 8, 64, 64, 3)
     with box((16, 16, 16)) as b:
-        for bad in ((2, 8, 1), (1, 4, 0), (2, 16, 1), (4, 8, 0), (3, 12, 0)):
+        for bad in ((2, 8, 1, 64), (1, 4, 0, 64), (2, 16, 1, 64), (4, 8, 0, 64), (3, 12, 0, 64),
+                    (1, 8, 0, 32), (2, 16, 0, 32)):
             with pytest.raises(lbm.LbmScError):
                 set_two(b, bad)
-        set_two(b, (2, 16, 0), zc=5)
-        assert b.launch() == dict(rows=2, z_chunk=5, xcd_remap=1, prefetch=0, waves=16, tile_x=64,
+        set_two(b, (2, 8, 0, 32), zc=5)
+        assert b.launch() == dict(rows=2, z_chunk=5, xcd_remap=1, prefetch=0, waves=8, tile_x=32,
                                   graph_steps=64, steps_per_pass=2)
