@@ -128,17 +128,26 @@ def traffic_summary(prof_dir, bench_log, out_path):
           f"({spp} step(s) per launch)")
 
 
-def group_traffic(prof_dir, last=256):
+def group_traffic(prof_dir, bench_log=None, timed_steps=256 + 128):
     """The same scaling for the multi-box step's counter runs (pmc_FETCH_SIZE_group,
-    pmc_WRITE_SIZE_group), over its last `last` dispatches; printed, not stored."""
+    pmc_WRITE_SIZE_group), over the dispatches of the timed mix: its `timed_steps` steps (the
+    256 steps of the counted run and the 128-step kernel timing), one dispatch per step, or per
+    two steps when the tuned launch (from the counted run's bench line in bench_log) takes two
+    steps per pass; printed, not stored."""
     with open(TRAFFIC_FILE) as fh:
         t = json.load(fh)
-    out = {}
+    spp = 1
+    if bench_log:
+        with open(bench_log) as fh:
+            res = json.loads([ln for ln in fh if ln.startswith("{")][-1])
+        spp = res["batched"]["launch"].get("steps_per_pass", 1)
+    kernel = "void lbm::(anonymous namespace)::" + ("k_step2_group<" if spp == 2 else "k_step_group<")
+    out = {"kernel": kernel, "steps_per_launch": spp}
     for counter, scale in (("FETCH_SIZE", t["fetch_scale"]), ("WRITE_SIZE", t["write_scale"])):
         v, n = counter_per_dispatch(os.path.join(prof_dir, f"pmc_{counter}_group"), counter,
-                                    "void lbm::(anonymous namespace)::k_step_group<", last)
+                                    kernel, timed_steps // spp)
         out[counter] = {"KiB_per_dispatch": round(v, 1), "bytes_per_launch": int(v * 1024 * scale),
-                        "dispatches": n}
+                        "bytes_per_step": int(v * 1024 * scale / spp), "dispatches": n}
     print(json.dumps(out, indent=1))
 
 
@@ -184,9 +193,9 @@ HELD_OUT_SEED = 2106
 def run_batched(args, torch, lbm, stream, steps, log):
     """The batched workload: 64 cubic boxes (L ~ U{48..160}, R ~ U[0.15, 0.35] L, G/G_c ~
     U[1.05, 1.8], droplet or bubble, exp psi, FP32-shifted, tanh width 2, noise 1e-6), seeded
-    2105, advanced together by one multi-box launch per step with a launch shape autotuned on a
-    held-out mix of the same distribution (seed 2106), and FP64 observations of every box every
-    2048 steps. Compared with the plain single-box FP64 path on a subset of the same boxes
+    2105, advanced together by one multi-box launch per step (or per two steps) with a launch
+    shape and row layout autotuned on a held-out mix of the same distribution (seed 2106), and
+    FP64 observations of every box every 2048 steps. Compared with the plain single-box FP64 path on a subset of the same boxes
     (throughput and dP after the same number of steps)."""
     from tests import inputs
     from paper_2105_08772_amd import tune
@@ -199,28 +208,38 @@ def run_batched(args, torch, lbm, stream, steps, log):
                           width=2.0, noise_amp=1e-6, seed=b["seed"], stream=st,
                           packed_rows=packed)
 
-    # the group's boxes store their rows packed (pitch nx, no lanes idle over row padding under
-    # full-row tiles); the single-box FP64 comparison keeps the default padded rows of x-y tiles
-
-    # the launch shape is tuned on a held-out mix, so that the timed boxes are unseen by the tuner
+    # the launch shape is tuned on a held-out mix, so that the timed boxes are unseen by the tuner:
+    # the single-step shapes on boxes whose rows are packed (pitch nx, no lanes idle over row
+    # padding under full-row tiles), the two-steps-per-pass shapes (x-y tiles) on the same boxes
+    # with rows padded to whole lines; the timed boxes take the row layout of the winner. The
+    # single-box FP64 comparison keeps the default padded rows.
     held_spec = inputs.batched_boxes(seed=HELD_OUT_SEED)
-    held = [lbm.Box(cfg(b, lbm.LBM_SC_FP32_SHIFTED, stream.cuda_stream, 1)) for b in held_spec]
-    hgroup = lbm.Group(stream.cuda_stream)
-    hgroup.set(held)
-    log(f"# batched: tuning on the held-out mix (seed {HELD_OUT_SEED}, "
-        f"{hgroup.info()['nodes'] / 1e6:.1f} M nodes)")
-    best = tune.tune_group(hgroup, steps=8, log=lambda m: log("# " + m))
-    hgroup.close()
-    for b in held:
-        b.close()
-    del held
-    torch.cuda.empty_cache()
+    tuned = []
+    for packed, spp in ((1, 1), (0, 2)):
+        held = [lbm.Box(cfg(b, lbm.LBM_SC_FP32_SHIFTED, stream.cuda_stream, packed))
+                for b in held_spec]
+        hgroup = lbm.Group(stream.cuda_stream)
+        hgroup.set(held)
+        log(f"# batched: tuning {'single-step' if spp == 1 else 'two-step'} shapes on the held-out "
+            f"mix (seed {HELD_OUT_SEED}, {hgroup.info()['nodes'] / 1e6:.1f} M nodes, packed rows "
+            f"{packed})")
+        cands = [c for c in tune.group_candidates() if c["steps_per_pass"] == spp]
+        tuned.append(dict(tune.tune_group(hgroup, steps=8, candidates=cands,
+                                          log=lambda m: log("# " + m)), packed_rows=packed))
+        hgroup.close()
+        for b in held:
+            b.close()
+        del held
+        torch.cuda.empty_cache()
+    best = min(tuned, key=lambda t: t["seconds_per_step"])
     log(f"# batched: tuned {best}")
-    boxes = [lbm.Box(cfg(b, lbm.LBM_SC_FP32_SHIFTED, stream.cuda_stream, 1)) for b in spec]
+    packed = best["packed_rows"]
+    boxes = [lbm.Box(cfg(b, lbm.LBM_SC_FP32_SHIFTED, stream.cuda_stream, packed)) for b in spec]
     group = lbm.Group(stream.cuda_stream)
     group.set(boxes)
     ginfo = group.info()
-    group.set_launch(**{k: v for k, v in best.items() if k != "seconds_per_step"}, graph_steps=64)
+    launch = {k: v for k, v in best.items() if k not in ("seconds_per_step", "packed_rows")}
+    group.set_launch(**launch, graph_steps=64)
     log(f"# batched: {len(boxes)} boxes, {ginfo['nodes'] / 1e6:.1f} M nodes")
     # timed: `steps` steps of all boxes, FP64 observation of every box every 2048 steps
     for b in boxes:
@@ -284,15 +303,17 @@ def run_batched(args, torch, lbm, stream, steps, log):
     solve_steps = 20000
     return {
         "workload": "64 boxes L~U{48..160}, R~U[0.15,0.35]L, G/G_c~U[1.05,1.8], droplet/bubble, "
-                    "exp psi, FP32-shifted, seed 2105, one multi-box launch per step, FP64 "
-                    "observations every 2048 steps",
+                    "exp psi, FP32-shifted, seed 2105, one multi-box launch per step or per two "
+                    "steps (tuned), FP64 observations every 2048 steps",
         "boxes": len(boxes), "nodes": total_nodes, "steps": steps, "seconds": round(wall, 3),
         "MLUPS": round(mlups, 1),
         "droplets_per_hour": round(len(boxes) * 3600.0 / (wall * solve_steps / steps), 1),
         "kernel_ms_per_step": round(t_step * 1e3, 4),
         "kernel_GBps": round(ginfo["bytes_per_step"] / t_step / 1e9, 1),
         "kernel_frac_of_8TBps": round(ginfo["bytes_per_step"] / t_step / 1e9 / HBM_PEAK_GBPS, 4),
-        "launch": {k: v for k, v in best.items() if k != "seconds_per_step"},
+        "launch": dict(launch, packed_rows=packed),
+        "tuned_ms_per_step": {("two_step" if t["steps_per_pass"] == 2 else "single_step"):
+                              round(t["seconds_per_step"] * 1e3, 4) for t in tuned},
         "launch_tuned_on": f"held-out mix of the same distribution, seed {HELD_OUT_SEED}",
         "unstable_boxes": unstable,
         "fp64_single_path": {"boxes": len(subset), "MLUPS": round(mlups64, 1),
@@ -311,7 +332,7 @@ def run_batched(args, torch, lbm, stream, steps, log):
 def run_served(args, torch, lbm, log, capacity_mlups=None):
     """The served workload: seeded Poisson arrivals of droplet/bubble requests (L ~ U{32..192},
     radius ~ U[max(6, 0.15 L), min(60, 0.35 L)], G/G_c ~ U[1.05, 1.8], exp psi, FP32-shifted),
-    continuously batched into one multi-box launch per step, admitted by free HBM (less an 8 GiB
+    continuously batched into one multi-box launch per two steps, admitted by free HBM (less an 8 GiB
     reserve), each run until its stop rule holds (dP change < 1e-5 or max |du| < 1e-9 between
     observations 2048 steps apart; at most 100000 steps). Reports p50/p99 time to equilibrium
     and aggregate MLUPS. The same requests with the same arrivals and stop rule are then served
@@ -335,11 +356,12 @@ def run_served(args, torch, lbm, log, capacity_mlups=None):
         torch.cuda.empty_cache()
         return srv, recs, budget
 
-    be = serve.GpuBackend()
-    # full-row tiles (the fastest shape of the batched mix; the backend falls back to x-y tiles
-    # for a box whose rows are too long)
-    be.set_launch(rows=4, waves=8, tile_x=0, z_chunk=8, prefetch=0, persistent=0, workers=0,
-                  graph_steps=64)
+    # two steps per launch in 32 x 16 tiles on rows padded to whole lines, z chunks of 16 planes
+    # (a few boxes at a time: short chunks keep every CU busy); measured on this workload against
+    # full-row single-step launches on packed rows: p50 / p99 1.58 / 7.99 s against 1.71 / 9.75 s
+    be = serve.GpuBackend(packed_rows=False)
+    be.set_launch(rows=2, waves=8, tile_x=32, z_chunk=16, prefetch=0, persistent=0, workers=0,
+                  items_per_cu=0, steps_per_pass=2, graph_steps=64)
     journal = open(args.served_journal, "w") if args.served_journal else None
     srv, recs, budget = serve_all(be, journal=journal)
     if journal:
@@ -694,12 +716,15 @@ def main():
                          "traffic record the benchmark reads (see traffic_summary)")
     ap.add_argument("--traffic-bench-log", default=None,
                     help="with --traffic-from: output of the counted step run")
+    ap.add_argument("--traffic-group-log", default=None,
+                    help="with --traffic-from and no --traffic-bench-log: output of the counted "
+                         "batched run (its tuned launch names the group kernel)")
     args = ap.parse_args()
     if args.traffic_from:
         if args.traffic_bench_log:
             traffic_summary(args.traffic_from, args.traffic_bench_log, TRAFFIC_FILE)
         else:
-            group_traffic(args.traffic_from)
+            group_traffic(args.traffic_from, args.traffic_group_log)
         return
     if args.gpus != 1:
         print("bench.py: the library runs on one GPU only (there is no multi-GPU path); use --gpus 1",

@@ -257,6 +257,14 @@ typedef struct {
     int32_t waves;       /* wave64s per workgroup: 4 or 8 */
     int32_t tile_x;      /* tile width: 64 or 32; 0 for full-row tiles (FP32 boxes for rows 8) */
     int32_t items_per_cu;/* z_chunk 0: work items per CU in total (0 = 8, at most 4096) */
+    int32_t steps_per_pass; /* 0 or 1: one time step per launch; 2: two time steps per launch by
+                            the two-steps-per-pass kernel (every box with FP32 storage and
+                            arithmetic at tau = 1; the tile shapes of lbm_sc_launch with
+                            steps_per_pass 2; persistent 0). The group then reads and writes each
+                            box once per two steps; a graph holds graph_steps / 2 launches when
+                            graph_steps is a multiple of 4 (plain launches otherwise), and an odd
+                            last step runs as one single-step launch per box, in the box's own
+                            single-step shape. Results are bitwise those of single steps */
 } lbm_sc_group_launch;
 
 /* Create an empty group that enqueues on `stream` (a hipStream_t, required: the boxes of the
@@ -269,9 +277,9 @@ int lbm_sc_group_create(void* stream, lbm_sc_group** out);
  * inside a stream capture. */
 int lbm_sc_group_set(lbm_sc_group* g, lbm_sc* const* boxes, int32_t nbox);
 
-/* Enqueue nsteps (>= 0) time steps of every box of the group: one multi-box launch per step,
- * replayed from a captured hipGraph in chunks of graph_steps. Each box's step counter advances by
- * nsteps. Asynchronous. LBM_SC_EINVAL, with nothing enqueued, while the group's stream is being
+/* Enqueue nsteps (>= 0) time steps of every box of the group: one multi-box launch per step (per
+ * two steps with steps_per_pass 2), replayed from a captured hipGraph in chunks of graph_steps.
+ * Each box's step counter advances by nsteps. Asynchronous. LBM_SC_EINVAL, with nothing enqueued, while the group's stream is being
  * captured by the caller. */
 int lbm_sc_group_step(lbm_sc_group* g, int64_t nsteps);
 
@@ -302,8 +310,8 @@ void lbm_sc_group_destroy(lbm_sc_group* g);
  * LBM_SC_NOALLOC_MAX_BOXES boxes per call (LBM_SC_EINVAL beyond, nothing enqueued).
  * The boxes stay owned by the caller; every box must be non-NULL, appear once, share one
  * precision and have been created on one stream, where the work is enqueued; launch follows the
- * rules of lbm_sc_group_set_launch and must fit every box (LBM_SC_EINVAL otherwise, nothing
- * enqueued). Each box's step counter advances by nsteps. Asynchronous. Calls that overlap in time
+ * rules of lbm_sc_group_set_launch, with steps_per_pass 0 or 1, and must fit every box
+ * (LBM_SC_EINVAL otherwise, nothing enqueued). Each box's step counter advances by nsteps. Asynchronous. Calls that overlap in time
  * on one GPU (enqueued on different streams) race on the shared array; calls on one stream are
  * ordered. While the caller is capturing the stream the launches are recorded into the caller's
  * graph: nsteps must then be even, every replay advances the boxes by nsteps, and the host step

@@ -69,7 +69,7 @@ class LbmScLaunch(ctypes.Structure):
 class LbmScGroupLaunch(ctypes.Structure):
     _fields_ = [("rows", _i32), ("z_chunk", _i32), ("xcd_remap", _i32), ("prefetch", _i32),
                 ("persistent", _i32), ("workers", _i32), ("graph_steps", _i32), ("waves", _i32),
-                ("tile_x", _i32), ("items_per_cu", _i32)]
+                ("tile_x", _i32), ("items_per_cu", _i32), ("steps_per_pass", _i32)]
 
     def to_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

@@ -88,6 +88,9 @@ struct GroupBox {
     unsigned items;         // tiles_x * tiles_y * ceil(nz / zc)
 };
 
+// Empty slot of a group's item order.
+constexpr unsigned NO_ITEM = 0xFFFFFFFFu;
+
 // Work queues of the persistent multi-box kernel (device memory, zero-initialised once).
 struct QueueState {
     unsigned next[8];       // next ticket of each XCD's queue
@@ -156,6 +159,11 @@ LBM_STEP_DECL(f64)
 // step2_shape_supported): the state in src after t steps becomes the state in dst after t + 2.
 hipError_t launch_step2_f32(const BoxDesc& b, const StepShape& s, int sbuf, const void* src,
                             void* dst, hipStream_t st);
+// The same over a group's work list (tiles tile_x wide and 8 * rows high, one workgroup per item):
+// nitems workgroups taking items 0 .. nitems - 1, or, with an item order, 8 * per workgroups of
+// which workgroup w takes order[(w mod 8) * per + w / 8] (NO_ITEM: none).
+hipError_t launch_group2_f32(const StepShape& s, const GroupBox* boxes, int nbox, unsigned nitems,
+                             const unsigned* order, unsigned per, int parity, hipStream_t st);
 // Multi-box step. nitems work items; persistent: grid of `workers` workgroups over the queues.
 hipError_t launch_step_group(bool fp32, bool math64, const StepShape& s, const GroupBox* boxes, int nbox,
                              unsigned nitems, int parity, int persistent, unsigned workers,

@@ -1118,6 +1118,10 @@ struct lbm_sc_group {
     lbm::GroupBox* d_desc = nullptr;
     size_t d_desc_cap = 0;
     lbm::QueueState* d_queue = nullptr;
+    unsigned* d_order = nullptr;  // two steps per pass with XCD remap: item order, 8 runs of order_per
+    size_t d_order_cap = 0;
+    unsigned order_per = 0;
+    bool use_order = false;
     lbm_sc_group_launch launch;
     bool fp32 = false;
     bool math64 = false;          // FP32 storage with FP64 arithmetic (shared by every box)
@@ -1156,6 +1160,36 @@ lbm::StepShape group_shape(const lbm_sc_group_launch& L)
     return s;
 }
 
+int group_spp(const lbm_sc_group_launch& L) { return L.steps_per_pass == 2 ? 2 : 1; }
+
+// Tile width and height of the group's items on box b (two steps per pass: tile_x x 8 * rows).
+void group_tile_dims(const lbm_sc_group_launch& L, const lbm::BoxDesc& b, int& bx, int& by)
+{
+    if (group_spp(L) == 2) {
+        bx = L.tile_x;
+        by = 8 * L.rows;
+    } else {
+        tile_dims(group_shape(L), b, bx, by);
+    }
+}
+
+// Whether box h (the i-th of a list) can be stepped by launch L; fails with the reason if not.
+int check_group_box(const lbm_sc_group_launch& L, const lbm_sc* h, int i)
+{
+    const std::string who = "box " + std::to_string(i);
+    if (group_spp(L) == 2) {
+        if (!(h->fp32 && !h->math64 && h->box.tau == 1.0))
+            return fail(LBM_SC_EINVAL, who + ": two steps per pass need FP32 storage, FP32 arithmetic "
+                                             "and tau = 1");
+        return LBM_SC_OK;
+    }
+    if (!shape_fits(group_shape(L), h->box))
+        return fail(LBM_SC_EINVAL, who + ": rows too long for the full-row tiles of this launch");
+    if (L.tile_x == 0 && L.rows == 8 && (!h->fp32 || h->math64))
+        return fail(LBM_SC_EINVAL, "full-row tiles with 8 nodes per thread need FP32 arithmetic");
+    return LBM_SC_OK;
+}
+
 // z_chunk 0: each box is cut into z chunks of about the same work, items_per_cu items per CU in
 // total, so that small boxes march their whole height (no chunk ends pulled twice) and large
 // ones are split for balance. Returns the work (nodes) of one item, 0 for fixed z chunks.
@@ -1179,7 +1213,7 @@ lbm::GroupBox box_desc(const lbm_sc* h, const lbm_sc_group_launch& L, double ite
 {
     const lbm::StepShape shape = group_shape(L);
     int bx, by;
-    tile_dims(shape, h->box, bx, by);
+    group_tile_dims(L, h->box, bx, by);
     lbm::GroupBox d;
     std::memset(&d, 0, sizeof(d));
     d.b = h->box;
@@ -1207,7 +1241,7 @@ lbm::GroupBox box_desc(const lbm_sc* h, const lbm_sc_group_launch& L, double ite
 double item_nodes(const lbm::GroupBox& d, const lbm_sc_group_launch& L, unsigned it)
 {
     int bx, by;
-    tile_dims(group_shape(L), d.b, bx, by);
+    group_tile_dims(L, d.b, bx, by);
     const unsigned tix = it % d.tiles_x, t2 = it / d.tiles_x;
     const unsigned tiy = t2 % d.tiles_y, ch = t2 / d.tiles_y;
     const int w = std::min(bx, d.b.nx - (int)tix * bx);
@@ -1254,6 +1288,58 @@ lbm::QueueState queue_ranges(Desc desc, size_t nbox, unsigned nitems, const lbm_
     return q;
 }
 
+// Item order of the two-steps-per-pass group kernel (workgroup w on XCD w mod 8 takes entry
+// (w mod 8) * per + w / 8): the box-major list cut into 8 contiguous runs of about equal cost, one
+// per XCD, each run with its longest items first, so that the XCDs finish together and the short
+// items fill the end of the launch. The cost of an item is the number of planes its march
+// iterates: its chunk height plus the 6 planes pulled beyond it. The sort is stable, so the tiles
+// of one box and z chunk stay together (neighbours in x and y run side by side on one XCD and
+// share their halo lines in its L2). Returns false if the result is not a permutation.
+bool two_step_order(const std::vector<lbm::GroupBox>& desc, unsigned nitems, std::vector<unsigned>& order,
+                    unsigned& per)
+{
+    std::vector<double> cost(nitems);
+    double total = 0.0;
+    for (const lbm::GroupBox& d : desc) {
+        const unsigned tiles = (unsigned)d.tiles_x * (unsigned)d.tiles_y;
+        for (unsigned it = 0; it < d.items; ++it) {
+            const int ch = (int)(it / tiles);
+            const int dz = std::min(d.zc, d.b.nz - ch * d.zc);
+            cost[d.item_begin + it] = dz + 6.0;
+            total += dz + 6.0;
+        }
+    }
+    unsigned bounds[9];
+    bounds[0] = 0;
+    int x = 1;
+    double acc = 0.0;
+    for (unsigned k = 0; k < nitems && x < 8; ++k) {
+        while (x < 8 && !(acc + 0.5 * cost[k] < total * x / 8.0)) bounds[x++] = k;
+        acc += cost[k];
+    }
+    while (x < 8) bounds[x++] = nitems;
+    bounds[8] = nitems;
+    per = 1;
+    for (int r = 0; r < 8; ++r) per = std::max(per, bounds[r + 1] - bounds[r]);
+    order.assign((size_t)8 * per, lbm::NO_ITEM);
+    std::vector<unsigned> run;
+    for (int r = 0; r < 8; ++r) {
+        run.clear();
+        for (unsigned k = bounds[r]; k < bounds[r + 1]; ++k) run.push_back(k);
+        std::stable_sort(run.begin(), run.end(), [&](unsigned a, unsigned b) { return cost[a] > cost[b]; });
+        std::copy(run.begin(), run.end(), order.begin() + (size_t)r * per);
+    }
+    std::vector<char> seen(nitems, 0);
+    unsigned count = 0;
+    for (unsigned v : order) {
+        if (v == lbm::NO_ITEM) continue;
+        if (v >= nitems || seen[v]) return false;
+        seen[v] = 1;
+        ++count;
+    }
+    return count == nitems;
+}
+
 // Build the work list and queue ranges for the current boxes and launch shape, and upload them.
 // Phases align every box's current buffer with parity 0.
 int group_rebuild(lbm_sc_group* g)
@@ -1286,7 +1372,24 @@ int group_rebuild(lbm_sc_group* g)
     const lbm::QueueState q = queue_ranges([&](size_t i) { return g->desc[i]; }, g->desc.size(),
                                            g->nitems, L);
     HIP_TRY(hipMemcpyAsync(g->d_queue, &q, sizeof(q), hipMemcpyHostToDevice, g->stream));
-    // the queue state is read by later launches: keep the host copy alive until it has landed
+    std::vector<unsigned> order;
+    g->use_order = group_spp(L) == 2 && L.xcd_remap && g->nitems > 0;
+    if (g->use_order) {
+        if (!two_step_order(g->desc, g->nitems, order, g->order_per))
+            return fail(LBM_SC_EDEVICE, "internal error: the item order is not a permutation");
+        const size_t bytes = order.size() * sizeof(unsigned);
+        if (bytes > g->d_order_cap) {
+            if (g->d_order) (void)hipFree(g->d_order);
+            g->d_order = nullptr;
+            g->d_order_cap = 0;
+            hipError_t e = hipMalloc((void**)&g->d_order, bytes);
+            if (e != hipSuccess) return fail(LBM_SC_ENOMEM, "group item order allocation failed");
+            g->d_order_cap = bytes;
+        }
+        HIP_TRY(hipMemcpyAsync(g->d_order, order.data(), bytes, hipMemcpyHostToDevice, g->stream));
+    }
+    // the queue state and the order are read by later launches: keep the host copies alive until
+    // they have landed
     HIP_TRY(hipStreamSynchronize(g->stream));
     drop_graph(g);
     g->dirty = false;
@@ -1297,6 +1400,10 @@ int group_rebuild(lbm_sc_group* g)
 hipError_t group_launch(lbm_sc_group* g, int parity)
 {
     const lbm::StepShape s = group_shape(g->launch);
+    if (group_spp(g->launch) == 2)
+        return lbm::launch_group2_f32(s, g->d_desc, (int)g->desc.size(), g->nitems,
+                                      g->use_order ? g->d_order : nullptr, g->order_per, parity,
+                                      g->stream);
     const unsigned workers = g->launch.workers ? (unsigned)g->launch.workers : 256u;
     return lbm::launch_step_group(g->fp32, g->math64, s, g->d_desc, (int)g->desc.size(), g->nitems, parity,
                                   g->launch.persistent, workers, g->d_queue, g->stream);
@@ -1308,7 +1415,14 @@ int check_group_launch(const lbm_sc_group_launch* l)
     if (l->items_per_cu < 0 || l->items_per_cu > 4096)
         return fail(LBM_SC_EINVAL, "items_per_cu must be in [0, 4096]");
     if ((l->xcd_remap | l->prefetch | l->persistent) & ~1) return fail(LBM_SC_EINVAL, "flags must be 0 or 1");
-    if (!lbm::shape_supported(group_shape(*l))) return fail(LBM_SC_EINVAL, SHAPE_MSG);
+    if (l->steps_per_pass < 0 || l->steps_per_pass > 2)
+        return fail(LBM_SC_EINVAL, "steps_per_pass must be 0, 1 or 2");
+    if (l->steps_per_pass == 2) {
+        if (!lbm::step2_shape_supported(group_shape(*l))) return fail(LBM_SC_EINVAL, SHAPE2_MSG);
+        if (l->persistent) return fail(LBM_SC_EINVAL, "two steps per pass take one workgroup per item (persistent 0)");
+    } else if (!lbm::shape_supported(group_shape(*l))) {
+        return fail(LBM_SC_EINVAL, SHAPE_MSG);
+    }
     if (l->workers < 0 || l->workers % 8 || l->workers > 65536)
         return fail(LBM_SC_EINVAL, "workers must be a multiple of 8 in [0, 65536]");
     if (l->graph_steps < 0 || l->graph_steps % 2 || l->graph_steps > 4096)
@@ -1328,7 +1442,7 @@ int lbm_sc_group_create(void* stream, lbm_sc_group** out)
     lbm_sc_group* g = new (std::nothrow) lbm_sc_group();
     if (!g) return fail(LBM_SC_ENOMEM, "host allocation failed");
     g->stream = (hipStream_t)stream;
-    g->launch = {2, 32, 1, 1, 0, 0, 64, 4, 64, 0};   // rows 2, z chunk 32, 4 waves, 64-wide
+    g->launch = {2, 32, 1, 1, 0, 0, 64, 4, 64, 0, 1};   // rows 2, z chunk 32, 4 waves, 64-wide
     hipError_t e = hipMalloc((void**)&g->d_queue, sizeof(lbm::QueueState));
     if (e != hipSuccess) {
         delete g;
@@ -1358,11 +1472,7 @@ int lbm_sc_group_set(lbm_sc_group* g, lbm_sc* const* boxes, int32_t nbox)
             return fail(LBM_SC_EINVAL, "all boxes of a group must share one precision");
         for (int j = 0; j < i; ++j)
             if (boxes[j] == boxes[i]) return fail(LBM_SC_EINVAL, "a box appears twice");
-        if (!shape_fits(group_shape(g->launch), boxes[i]->box))
-            return fail(LBM_SC_EINVAL, "box " + std::to_string(i) +
-                                           ": rows too long for the group's full-row tiles");
-        if (g->launch.tile_x == 0 && g->launch.rows == 8 && (!boxes[i]->fp32 || boxes[i]->math64))
-            return fail(LBM_SC_EINVAL, "full-row tiles with 8 nodes per thread need FP32 arithmetic");
+        if (int rc = check_group_box(g->launch, boxes[i], i)) return rc;
     }
     for (lbm_sc* b : g->boxes) detach(b, g);
     g->boxes.assign(boxes, boxes + nbox);
@@ -1388,13 +1498,17 @@ int lbm_sc_group_step(lbm_sc_group* g, int64_t nsteps)
         if (rc) return rc;
     }
     const int K = g->launch.graph_steps;
-    if (K > 0 && nsteps >= K && (!g->graph || g->graph_len != K)) {
-        // capture K launches with parities 0, 1, ..., replayed whenever the parity is 0
+    // two steps per pass: a graph of K steps holds K / 2 launches, an even number only when K is
+    // a multiple of 4 (otherwise plain launches)
+    const int spp = group_spp(g->launch);
+    const int Kl = spp == 2 ? (K % 4 ? 0 : K / 2) : K;
+    if (Kl > 0 && nsteps >= K && (!g->graph || g->graph_len != K)) {
+        // capture Kl launches with parities 0, 1, ..., replayed whenever the parity is 0
         drop_graph(g);
         hipGraph_t graph = nullptr;
         HIP_TRY(hipStreamBeginCapture(g->stream, hipStreamCaptureModeThreadLocal));
         hipError_t le = hipSuccess;
-        for (int k = 0; k < K && le == hipSuccess; ++k) le = group_launch(g, k & 1);
+        for (int k = 0; k < Kl && le == hipSuccess; ++k) le = group_launch(g, k & 1);
         hipError_t ce = hipStreamEndCapture(g->stream, &graph);
         if (le != hipSuccess) {
             if (graph) (void)hipGraphDestroy(graph);
@@ -1414,10 +1528,21 @@ int lbm_sc_group_step(lbm_sc_group* g, int64_t nsteps)
         if (g->graph && g->par == 0 && nsteps - done >= g->graph_len) {
             HIP_TRY(hipGraphLaunch(g->graph, g->stream));
             done += g->graph_len;
+        } else if (spp == 2 && nsteps - done == 1) {
+            // odd last step of a two-steps-per-pass group: each box alone, in its own single-step
+            // shape (same arithmetic, so the same bits); the phases stay aligned with the parity
+            for (size_t i = 0; i < g->boxes.size(); ++i) {
+                lbm_sc* h = g->boxes[i];
+                const int c = (g->desc[i].phase + g->par) & 1;
+                HIP_TRY(lbm::launch_step(h->fp32, h->math64, h->box, h->shape, c, h->pop[c],
+                                         h->pop[1 - c], g->stream));
+            }
+            g->par ^= 1;
+            ++done;
         } else {
             HIP_TRY(group_launch(g, g->par));
             g->par ^= 1;
-            ++done;
+            done += spp;
         }
     }
     for (size_t i = 0; i < g->boxes.size(); ++i) {
@@ -1434,13 +1559,8 @@ int lbm_sc_group_set_launch(lbm_sc_group* g, const lbm_sc_group_launch* l)
     int rc = check_group_launch(l);
     if (rc) return rc;
     if ((rc = refuse_in_capture(g->stream, "lbm_sc_group_set_launch"))) return rc;
-    for (size_t i = 0; i < g->boxes.size(); ++i) {
-        if (!shape_fits(group_shape(*l), g->boxes[i]->box))
-            return fail(LBM_SC_EINVAL, "box " + std::to_string(i) +
-                                           ": rows too long for full-row tiles of this launch");
-        if (l->tile_x == 0 && l->rows == 8 && (!g->boxes[i]->fp32 || g->boxes[i]->math64))
-            return fail(LBM_SC_EINVAL, "full-row tiles with 8 nodes per thread need FP32 arithmetic");
-    }
+    for (size_t i = 0; i < g->boxes.size(); ++i)
+        if (int rc = check_group_box(*l, g->boxes[i], (int)i)) return rc;
     g->launch = *l;
     return group_rebuild(g);
 }
@@ -1475,6 +1595,7 @@ void lbm_sc_group_destroy(lbm_sc_group* g)
     drop_graph(g);
     if (g->d_desc) (void)hipFree(g->d_desc);
     if (g->d_queue) (void)hipFree(g->d_queue);
+    if (g->d_order) (void)hipFree(g->d_order);
     delete g;
 }
 
@@ -1486,6 +1607,8 @@ int lbm_sc_step_boxes_noalloc(lbm_sc* const* boxes, int32_t nbox, int64_t nsteps
         return fail(LBM_SC_EINVAL, "lbm_sc_step_boxes_noalloc takes at most 1024 boxes");
     if (nsteps < 0) return fail(LBM_SC_EINVAL, "nsteps must be >= 0");
     if (int rc = check_group_launch(launch)) return rc;
+    if (launch->steps_per_pass == 2)
+        return fail(LBM_SC_EINVAL, "lbm_sc_step_boxes_noalloc takes one step per launch (steps_per_pass 0 or 1)");
     const lbm_sc_group_launch& L = *launch;
     const lbm::StepShape shape = group_shape(L);
     for (int i = 0; i < nbox; ++i) {
@@ -1497,10 +1620,7 @@ int lbm_sc_step_boxes_noalloc(lbm_sc* const* boxes, int32_t nbox, int64_t nsteps
             return fail(LBM_SC_EINVAL, "all boxes must share one precision");
         for (int j = 0; j < i; ++j)
             if (boxes[j] == b) return fail(LBM_SC_EINVAL, "a box appears twice");
-        if (!shape_fits(shape, b->box))
-            return fail(LBM_SC_EINVAL, "a box's rows are too long for the full-row tiles of this launch");
-        if (L.tile_x == 0 && L.rows == 8 && (!b->fp32 || b->math64))
-            return fail(LBM_SC_EINVAL, "full-row tiles with 8 nodes per thread need FP32 arithmetic");
+        if (int rc = check_group_box(L, b, i)) return rc;
     }
     if (nbox == 0 || nsteps == 0) return LBM_SC_OK;
     hipStream_t st = boxes[0]->stream;

@@ -52,6 +52,32 @@ hipError_t launch_step2_f32(const BoxDesc& b, const StepShape& s, int sbuf, cons
     return hipErrorInvalidValue;
 }
 
+template <int BX, int BY, int WAVES, bool PF, int MINW = 1>
+hipError_t launch_group2_t(const GroupBox* boxes, int nbox, unsigned nitems, const unsigned* order,
+                           unsigned per, int parity, hipStream_t st)
+{
+    const unsigned grid = order ? 8u * per : nitems;
+    hipLaunchKernelGGL((k_step2_group<BX, BY, WAVES, PF, MINW>), dim3(grid), dim3(64 * WAVES), 0, st,
+                       boxes, nbox, parity, order, per);
+    return hipGetLastError();
+}
+
+// Two steps per pass over a group: the shapes of launch_step2_f32, one workgroup per work item
+// (the work list built for tiles tile_x wide and 8 * rows high).
+hipError_t launch_group2_f32(const StepShape& s, const GroupBox* boxes, int nbox, unsigned nitems,
+                             const unsigned* order, unsigned per, int parity, hipStream_t st)
+{
+#define LBM_G2(BX, BY, WV, PF, ...) \
+    launch_group2_t<BX, BY, WV, PF, ##__VA_ARGS__>(boxes, nbox, nitems, order, per, parity, st)
+    if (s.tile_x == 64 && s.rows == 1 && s.waves == 8)
+        return s.prefetch ? LBM_G2(64, 8, 8, true) : LBM_G2(64, 8, 8, false);
+    if (s.tile_x == 32 && s.rows == 2 && s.waves == 8)
+        return s.prefetch ? LBM_G2(32, 16, 8, true) : LBM_G2(32, 16, 8, false, 4);
+    if (s.tile_x == 64 && s.rows == 2 && s.waves == 16 && !s.prefetch) return LBM_G2(64, 16, 16, false);
+    return hipErrorInvalidValue;
+#undef LBM_G2
+}
+
 hipError_t launch_group_f32(const StepShape& s, const GroupBox* boxes, int nbox, unsigned nitems,
                             int parity, int persistent, unsigned workers, QueueState* q,
                             hipStream_t st)

@@ -806,7 +806,12 @@ __device__ __forceinline__ void step_tile2(const BoxDesc& bd, const float* __res
 
     // pulled nodes: slot k of thread t is node s = t + k NT of the (BX + 6) x (BY + 6) region, at
     // LDS position (ly, lx) of psa; nodes of the (BX + 4) x (BY + 4) region inside it also
-    // collide (first step)
+    // collide (first step). A tile cut by the box edge (wv x hv nodes in the box) needs only the
+    // (wv + 6) x (hv + 6) corner of the region: the slots beyond it load the corner's last column
+    // or row again (lines the wave reads anyway, instead of nodes across the periodic wrap), and
+    // what they compute reaches only tile nodes outside the box, which are not stored or land in
+    // row padding that nothing reads
+    const int wv = min(Gm::BX, nx - x0), hv = min(BY, ny - y0);
     int sx[NSA], sy[NSA];
     bool sin_[NSA], sa[NSA];
     unsigned sxo[NSA][3], syo[NSA][3], skey[NSA];
@@ -818,7 +823,7 @@ __device__ __forceinline__ void step_tile2(const BoxDesc& bd, const float* __res
         sx[k] = lx;
         sy[k] = ly;
         sa[k] = sin_[k] && lx >= 1 && lx <= AX && ly >= 1 && ly <= AY;
-        const int x = wrapi(x0 - 3 + lx, nx), y = wrapi(y0 - 3 + ly, ny);
+        const int x = wrapi(x0 - 3 + min(lx, wv + 5), nx), y = wrapi(y0 - 3 + min(ly, hv + 5), ny);
         sxo[k][0] = (unsigned)wrapi(x - 1, nx) * E;
         sxo[k][1] = (unsigned)x * E;
         sxo[k][2] = (unsigned)wrapi(x + 1, nx) * E;
@@ -1063,19 +1068,25 @@ __global__ __launch_bounds__(64 * WAVES, MINW) void k_step2(StepArgs a, const fl
 // (rows, prefetch) is shared. Box b reads pop[(phase_b + parity) & 1] and writes the other.
 // ------------------------------------------------------------------------------------------
 
-template <typename T, typename C, int R, bool PF, int WAVES, int BXT>
-__device__ __forceinline__ void group_item(const GroupBox* __restrict__ boxes, int nbox,
-                                           unsigned item, int parity,
-                                           RingOf<C, R, WAVES, BXT>& ring)
+// Box of a work item: the last box whose first item is <= item.
+__device__ __forceinline__ const GroupBox& group_box_of(const GroupBox* __restrict__ boxes, int nbox,
+                                                        unsigned item)
 {
-    // box of the item: last box whose first item is <= item
     int lo = 0, hi = nbox - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
         if (boxes[mid].item_begin <= item) lo = mid;
         else hi = mid - 1;
     }
-    const GroupBox& g = boxes[lo];
+    return boxes[lo];
+}
+
+template <typename T, typename C, int R, bool PF, int WAVES, int BXT>
+__device__ __forceinline__ void group_item(const GroupBox* __restrict__ boxes, int nbox,
+                                           unsigned item, int parity,
+                                           RingOf<C, R, WAVES, BXT>& ring)
+{
+    const GroupBox& g = group_box_of(boxes, nbox, item);
     const unsigned local = item - g.item_begin;
     const int tix = (int)(local % (unsigned)g.tiles_x);
     const unsigned t2 = local / (unsigned)g.tiles_x;
@@ -1151,6 +1162,39 @@ __global__ __launch_bounds__(64 * WAVES) void k_step_group_persistent(
             __threadfence();
         }
     }
+}
+
+// Two steps per pass over a group (FP32 storage and arithmetic, every box at tau = 1): one
+// workgroup per (box, tile, z chunk) item of the list above, each marched by the two-step tile
+// kernel's body; a launch moves every box from pop[(phase + parity) & 1] to the other buffer and
+// advances its step count by two. With an item order (order != nullptr) the grid is 8 * per
+// workgroups: workgroup w runs on XCD w mod 8 and takes order[(w mod 8) * per + w / 8], the XCD's
+// share of the items in the order the host chose (NO_ITEM: nothing to do); without it, workgroup w
+// takes item w.
+template <int BX, int BY, int WAVES, bool PF, int MINW>
+__global__ __launch_bounds__(64 * WAVES, MINW) void k_step2_group(const GroupBox* __restrict__ boxes,
+                                                                  int nbox, int parity,
+                                                                  const unsigned* __restrict__ order,
+                                                                  unsigned per)
+{
+    __shared__ Ring2<BX, BY, WAVES> ring;
+    const unsigned item = order ? order[(blockIdx.x % 8u) * per + blockIdx.x / 8u] : blockIdx.x;
+    if (item == NO_ITEM) return;
+    const GroupBox& g = group_box_of(boxes, nbox, item);
+    const unsigned local = item - g.item_begin;
+    const int tix = (int)(local % (unsigned)g.tiles_x);
+    const unsigned t2 = local / (unsigned)g.tiles_x;
+    const int tiy = (int)(t2 % (unsigned)g.tiles_y);
+    const int ch = (int)(t2 / (unsigned)g.tiles_y);
+    const int z0 = ch * g.zc;
+    const int z1 = min(z0 + g.zc, g.b.nz);
+    const int s = (g.phase + parity) & 1;
+    const float* src = (const float*)g.pop[s];
+    float* dst = (float*)g.pop[1 - s];
+    const unsigned* tin = g.b.tick + s;
+    unsigned* tout = local == 0 ? g.b.tick + (1 - s) : nullptr;
+    if (g.b.psi == 0) step_tile2<0, BX, BY, WAVES, PF>(g.b, src, dst, tix, tiy, z0, z1, tin, tout, ring);
+    else step_tile2<1, BX, BY, WAVES, PF>(g.b, src, dst, tix, tiy, z0, z1, tin, tout, ring);
 }
 
 template <typename T, typename C, int PSI, bool TAU1, int R, bool PF, int WAVES, int BXT>

@@ -125,7 +125,7 @@ class GpuBackend:
         return self._Box(self.config(r))
 
     # x-y tiles: every box size fits them (full-row tiles need rows short enough for the workgroup)
-    FALLBACK = dict(rows=2, waves=4, tile_x=64, prefetch=0)
+    FALLBACK = dict(rows=2, waves=4, tile_x=64, prefetch=0, persistent=0, steps_per_pass=1)
 
     def set_active(self, boxes):
         if self.single:

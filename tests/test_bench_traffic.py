@@ -94,3 +94,39 @@ def test_committed_traffic_record_matches_the_current_step_kernels():
     chunk = (zc + 2 * (2 * spp - 1)) / zc
     assert 1.0 <= t["fetch_bytes_per_launch"] / alg < 1.2 * chunk
     assert 0.99 < t["write_bytes_per_launch"] / alg < 1.01
+
+
+GROUP1 = "void lbm::(anonymous namespace)::k_step_group<float, float, 4, false, 8, 0>(...)"
+GROUP2 = "void lbm::(anonymous namespace)::k_step2_group<32, 16, 8, false, 4>(...)"
+
+
+def test_group_traffic_follows_the_tuned_kernel(tmp_path, capsys):
+    """The batched counter summary takes the dispatches of the tuned group kernel over the timed
+    mix only (the tuner's dispatches of every kernel come first), one per step or per two steps,
+    and reports bytes per launch and per step."""
+    b = bench()
+    p = str(tmp_path)
+    rec = json.load(open(b.TRAFFIC_FILE))
+    # tuner: both kernels; timed mix: 384 steps = 192 two-step launches of 1000 KiB read
+    tuner = [(k, GROUP1 if k % 2 else GROUP2, 5000.0) for k in range(1, 50)]
+    timed = [(100 + k, GROUP2, 1000.0) for k in range(192)]
+    write_run(os.path.join(p, "pmc_FETCH_SIZE_group"), "FETCH_SIZE", tuner + timed)
+    write_run(os.path.join(p, "pmc_WRITE_SIZE_group"), "WRITE_SIZE",
+              tuner + [(d, n, 800.0) for d, n, _ in timed])
+    log = os.path.join(p, "group.log")
+    with open(log, "w") as fh:
+        fh.write(json.dumps({"batched": {"launch": {"steps_per_pass": 2, "tile_x": 32}}}) + "\n")
+    b.group_traffic(p, log)
+    out = json.loads(capsys.readouterr().out)
+    assert out["steps_per_launch"] == 2 and out["kernel"].endswith("k_step2_group<")
+    assert out["FETCH_SIZE"]["dispatches"] == 192 and out["FETCH_SIZE"]["KiB_per_dispatch"] == 1000.0
+    assert out["FETCH_SIZE"]["bytes_per_launch"] == int(1000 * 1024 * rec["fetch_scale"])
+    assert out["FETCH_SIZE"]["bytes_per_step"] == int(1000 * 1024 * rec["fetch_scale"] / 2)
+    assert out["WRITE_SIZE"]["bytes_per_step"] == int(800 * 1024 * rec["write_scale"] / 2)
+    # a single-step launch: the last 384 dispatches of the single-step kernel
+    with open(log, "w") as fh:
+        fh.write(json.dumps({"batched": {"launch": {"steps_per_pass": 1}}}) + "\n")
+    b.group_traffic(p, log)
+    out = json.loads(capsys.readouterr().out)
+    assert out["steps_per_launch"] == 1 and out["FETCH_SIZE"]["dispatches"] == 25
+    assert out["FETCH_SIZE"]["KiB_per_dispatch"] == 5000.0

@@ -206,7 +206,8 @@ def test_backend_leaves_the_xy_tile_fallback_when_the_wide_box_leaves():
 
     class FakeGroup:
         def __init__(self):
-            self.shape = dict(tile_x=0, rows=4, waves=8, z_chunk=8, prefetch=0)
+            self.shape = dict(tile_x=0, rows=4, waves=8, z_chunk=8, prefetch=0, persistent=0,
+                              steps_per_pass=1)
             self.boxes = []
 
         def set(self, boxes):

@@ -258,3 +258,120 @@ def test_z_chunks_cover_every_plane_once(nz, zc):
         for p in range(z0 - 1, z1 + 1):
             assert 0 <= wrap(p - 1, nz) < nz and 0 <= wrap(p + 1, nz) < nz
     assert sorted(planes) == list(range(nz))
+
+
+# ------------------------------------------------------------------------------------------
+# Two steps per pass (k_step2 / k_step2_group: step_tile2). A workgroup of 64 * WAVES threads owns
+# a BX x BY tile of the second step. Slot k of thread t pulls node s = t + k * NT of the
+# (BX + 6) x (BY + 6) region (LDS position (s // LX, s % LX) of psa, global node x0 - 3 + lx,
+# y0 - 3 + ly wrapped); in a tile cut by the box edge (wv x hv nodes inside) the slots beyond the
+# (wv + 6) x (hv + 6) corner pull the corner's last column or row again. Pulled slots inside 1 <= lx <= BX + 4, 1 <= ly <= BY + 4 collide
+# the first step into fs[.][ly - 1][lx - 1]. Own slot j of thread t is tile node o = t + j * NT at
+# (o % BX, o // BX); ring slot h is ring node r = t + h * NT of the 2 (BX + 2) + 2 BY nodes
+# around the tile (rows -1 and BY, then columns -1 and BX). Own and ring nodes gather their
+# second-step populations from fs[i][by + 2 - cy_i][bx + 2 - cx_i] and write psi(t + 1) into
+# psb[by + 1][bx + 1]; own nodes collide the second step with psb at their 18 neighbours and
+# are stored when inside the row pitch and the box height.
+# ------------------------------------------------------------------------------------------
+
+SHAPES2 = [(64, 8, 8), (32, 16, 8), (64, 16, 16)]   # (BX, BY, WAVES)
+
+
+def two_step_maps(BX, BY, WAVES, nx, ny, px, tix, tiy):
+    NT = 64 * WAVES
+    NO = BX * BY // NT
+    LX, LY, AX, AY, GX, GY = BX + 6, BY + 6, BX + 4, BY + 4, BX + 2, BY + 2
+    NL = LX * LY
+    NSA = -(-NL // NT)
+    NHR = 2 * GX + 2 * BY
+    NSH = -(-NHR // NT)
+    x0, y0 = tix * BX, tiy * BY
+    wv, hv = min(BX, nx - x0), min(BY, ny - y0)
+    loaded, collided = {}, set()
+    for t in range(NT):
+        for k in range(NSA):
+            s = t + k * NT
+            if s >= NL:
+                continue
+            lx, ly = s % LX, s // LX
+            assert (lx, ly) not in loaded, "an LDS position is pulled twice"
+            loaded[(lx, ly)] = ((x0 - 3 + min(lx, wv + 5)) % nx, (y0 - 3 + min(ly, hv + 5)) % ny)
+            if 1 <= lx <= AX and 1 <= ly <= AY:
+                collided.add((lx, ly))
+    own, ring = [], []
+    for t in range(NT):
+        for j in range(NO):
+            o = t + j * NT
+            own.append((o % BX, o // BX))
+        for h in range(NSH):
+            r = t + h * NT
+            if r >= NHR:
+                continue
+            if r < GX:
+                ring.append((r - 1, -1))
+            elif r < 2 * GX:
+                ring.append((r - GX - 1, BY))
+            elif r < 2 * GX + BY:
+                ring.append((-1, r - 2 * GX))
+            else:
+                ring.append((BX, r - 2 * GX - BY))
+    return dict(NT=NT, LX=LX, LY=LY, AX=AX, AY=AY, GX=GX, GY=GY, wv=wv, hv=hv, x0=x0, y0=y0,
+                loaded=loaded, collided=collided, own=own, ring=ring)
+
+
+@pytest.mark.parametrize("shape", SHAPES2)
+def test_two_step_tile_maps_cover_what_valid_outputs_need(shape):
+    BX, BY, WAVES = shape
+    for nx, ny, packed in ((1, 1, False), (3, 5, False), (37, 29, False), (65, 9, True),
+                           (100, 100, False), (100, 37, True), (130, 17, False), (49, 52, True),
+                           (BX, BY, False), (2 * BX + 1, 3 * BY - 1, True)):
+        px = row_pitch(nx, 4, packed)
+        plane_bytes = px * ny * 4
+        for tix in range(-(-nx // BX)):
+            for tiy in range(-(-ny // BY)):
+                m = two_step_maps(BX, BY, WAVES, nx, ny, px, tix, tiy)
+                wv, hv, loaded, collided = m["wv"], m["hv"], m["loaded"], m["collided"]
+                # every LDS position of the region is pulled once; beyond the (wv + 6) x (hv + 6)
+                # corner from the corner's last column or row
+                assert set(loaded) == {(lx, ly) for lx in range(m["LX"]) for ly in range(m["LY"])}
+                for (lx, ly), (x, y) in loaded.items():
+                    if lx >= wv + 6 or ly >= hv + 6:
+                        assert x == (m["x0"] + min(lx, wv + 5) - 3) % nx
+                        assert y == (m["y0"] + min(ly, hv + 5) - 3) % ny
+                # each loads a node of the box (offsets of it and its x/y neighbours in the plane)
+                for (x, y) in loaded.values():
+                    assert 0 <= x < nx and 0 <= y < ny
+                    for dx, dy in NEIGH:
+                        xo, yo = (x + dx) % nx, (y + dy) % ny
+                        assert 0 <= yo * px * 4 + xo * 4 < plane_bytes
+                # own nodes tile the whole BX x BY tile once; ring nodes the ring around it once
+                assert sorted(m["own"]) == sorted((bx, by) for bx in range(BX) for by in range(BY))
+                ring_want = ([(bx, -1) for bx in range(-1, BX + 1)] + [(bx, BY) for bx in range(-1, BX + 1)]
+                             + [(-1, by) for by in range(BY)] + [(BX, by) for by in range(BY)])
+                assert sorted(m["ring"]) == sorted(ring_want)
+                # LDS bounds of every gather and psb write, valid or not
+                for bx, by in m["own"] + m["ring"]:
+                    assert 0 <= by + 1 < m["GY"] and 0 <= bx + 1 < m["GX"]
+                    for i in range(Q):
+                        gy, gx = by + 2 - CY[i], bx + 2 - CX[i]
+                        assert 0 <= gy < m["AY"] and 0 <= gx < m["AX"]
+                for lx, ly in collided:
+                    assert 0 <= ly - 1 < m["AY"] and 0 <= lx - 1 < m["AX"]
+                # stores: own nodes inside the row pitch and the box height, in the plane
+                for bx, by in m["own"]:
+                    xg, yg = m["x0"] + bx, m["y0"] + by
+                    if xg < px and yg < ny:
+                        assert yg * px * 4 + xg * 4 < plane_bytes
+                # dependencies of the outputs inside the box: psi(t + 1) at the outputs and their
+                # 18 neighbours, gathered by own or ring nodes from first-step nodes that
+                # collided, whose psi neighbours and own moments were pulled
+                own_ring = set(m["own"]) | set(m["ring"])
+                gather = {(bx + dx, by + dy) for bx in range(wv) for by in range(hv)
+                          for dx, dy in NEIGH}
+                assert gather <= own_ring
+                first = {(nx_ + 3 - CX[i], ny_ + 3 - CY[i]) for nx_, ny_ in gather for i in range(Q)}
+                assert first <= collided, (shape, nx, ny, tix, tiy)
+                assert {(lx + ex, ly + ey) for lx, ly in first for ex, ey in NEIGH} <= set(loaded)
+                # each first-step node sits at the wrapped global position the outputs expect
+                for lx, ly in first:
+                    assert loaded[(lx, ly)] == ((m["x0"] + lx - 3) % nx, (m["y0"] + ly - 3) % ny)

@@ -37,8 +37,14 @@ def test_group_candidates_are_unique_and_valid():
             assert c["workers"] in (256, 512) and c["workers"] % 8 == 0
         else:
             assert c["workers"] == 0
-    # every shape with every chunking, one-workgroup-per-item and both persistent grids
-    assert len(cands) == len(tune.SHAPES) * (5 + 3) * 3
+    # every shape with every chunking, one-workgroup-per-item and both persistent grids; every
+    # two-step shape with its chunkings, one workgroup per item
+    one = [c for c in cands if c["steps_per_pass"] == 1]
+    two = [c for c in cands if c["steps_per_pass"] == 2]
+    assert len(one) == len(tune.SHAPES) * (5 + 3) * 3
+    assert len(two) == len(tune.SHAPES2) * (3 + 3) and not any(c["persistent"] for c in two)
+    assert all(c["z_chunk"] == 0 or c["z_chunk"] >= 16 for c in two)
+    assert len(tune.group_candidates(two_step=False)) == len(one)
 
 
 def test_box_candidates_respect_the_box_height():
