@@ -600,8 +600,41 @@ def test_full_size_bench_workload_sampled():
             d = ((x + XI[i, 0]) % 256, (y + XI[i, 1]) % 256, (z + XI[i, 2]) % 256)
             worst = max(worst, abs(f1[i, d[2], d[1], d[0]] - fs[i]) / scale)
     say("worst sampled error / max|f| =", worst)
-    assert worst <= 1e-6
+    # measured 7.2e-8 of max |f| on MI355X; the bound is three times that
+    assert worst <= 2.2e-7
     assert abs(o1["mass"] - o0["mass"]) <= 1e-7 * o0["mass"]
+
+
+def test_full_size_bench_workload_two_steps_sampled():
+    """The same 256^3 droplet advanced by one launch of the kernel the benchmark times (two time
+    steps per pass in the default shape). After two steps a node's populations depend only on
+    the state within 4 nodes of it, so the oracle's two whole steps on the periodic 9^3
+    neighbourhood of a sampled node give that node's exact result; every population of each
+    sampled node is checked against it."""
+    say("256^3 FP32 bench workload, sampled two-step parity")
+    cfg = lbm.config(256, 256, 256, psi=0, geom=lbm.LBM_SC_DROPLET, prec=lbm.LBM_SC_FP32_SHIFTED,
+                     g_over_gc=1.3, radius=60.0, width=2.0, noise_amp=1e-6, seed=3)
+    rng = np.random.default_rng(2026)
+    with lbm.Box(cfg) as b:
+        assert b.launch()["steps_per_pass"] == 2
+        G = b.info()["G"]
+        f0 = b.get()
+        b.step(2)
+        f2 = b.get()
+    pts = [tuple(int(v) for v in rng.integers(0, 256, 3)) for _ in range(40)]
+    pts += [(128 + 60 + d, 128, 128) for d in range(-3, 4)] + [(0, 0, 0), (255, 255, 255),
+                                                                (255, 0, 128), (31, 32, 63)]
+    scale = np.abs(f0).max()
+    worst = 0.0
+    for (x, y, z) in pts:
+        ix, iy, iz = [(np.arange(-4, 5) + c) % 256 for c in (x, y, z)]
+        sub = f0[:, iz][:, :, iy][:, :, :, ix]
+        want = core.run(np.ascontiguousarray(sub), G, 1.0, 0, 2)[:, 4, 4, 4]
+        worst = max(worst, np.abs(f2[:, z, y, x] - want).max() / scale)
+    say("worst sampled error / max|f| =", worst)
+    # measured 7.4e-8 of max |f| on MI355X (two FP32 steps, the first stored and reloaded from
+    # LDS as it would be from memory); the bound is three times that
+    assert worst <= 2.2e-7
 
 
 @pytest.mark.parametrize("L,prec,tol", [(400, lbm.LBM_SC_FP64, TOL64),

@@ -597,3 +597,24 @@ def test_init_profile_geometry():
     n0 = core.init_density(9, 10, 11, core.DROPLET, 3.0, 2.0, nl, ng)
     d = nn - n0
     assert np.abs(d).max() <= 1e-6 and abs(d.mean()) < 2e-7 and d.std() > 4e-7
+
+
+# --------------------------------------------------------------------------------------------
+# Stencil radius (Sec. 2: streaming along the D3Q19 links, the force from the 18 nearest
+# neighbours): one step reaches 2 nodes, two steps 4. The GPU's two-steps-per-pass launch is
+# checked at full size against the oracle's two steps on 9^3 neighbourhoods, which rests on this.
+# --------------------------------------------------------------------------------------------
+
+def test_two_steps_reach_exactly_four_nodes():
+    """The oracle's two whole-box steps at a node equal its two steps on the periodic 9^3
+    neighbourhood of that node (to the bit), and not on the 7^3 one; a force or streaming
+    stencil wider than nearest neighbours would break the first, a narrower one the second."""
+    f = inputs.random_populations((14, 13, 12), 5, W_LAT * 1.5, amp=0.3)
+    full = core.run(f.copy(), -6.0, 1.0, core.PSI_EXP, 2)
+    for (x, y, z) in [(0, 0, 0), (13, 12, 11), (5, 6, 7), (2, 11, 3)]:
+        for r, exact in ((4, True), (3, False)):
+            ix, iy, iz = [(np.arange(-r, r + 1) + c) % n for c, n in ((x, 14), (y, 13), (z, 12))]
+            sub = np.ascontiguousarray(f[:, iz][:, :, iy][:, :, :, ix])
+            got = core.run(sub, -6.0, 1.0, core.PSI_EXP, 2)[:, r, r, r]
+            diff = np.abs(got - full[:, z, y, x]).max()
+            assert (diff == 0.0) if exact else (diff > 1e-8), (x, y, z, r, diff)
