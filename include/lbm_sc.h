@@ -310,8 +310,11 @@ void lbm_sc_group_destroy(lbm_sc_group* g);
  * LBM_SC_NOALLOC_MAX_BOXES boxes per call (LBM_SC_EINVAL beyond, nothing enqueued).
  * The boxes stay owned by the caller; every box must be non-NULL, appear once, share one
  * precision and have been created on one stream, where the work is enqueued; launch follows the
- * rules of lbm_sc_group_set_launch, with steps_per_pass 0 or 1, and must fit every box
- * (LBM_SC_EINVAL otherwise, nothing enqueued). Each box's step counter advances by nsteps. Asynchronous. Calls that overlap in time
+ * rules of lbm_sc_group_set_launch and must fit every box (LBM_SC_EINVAL otherwise, nothing
+ * enqueued). With steps_per_pass 2 the two-step kernel takes the work items in list order (a
+ * group also spreads them over the XCDs by cost) and an odd last step runs as one single-step
+ * launch per box; inside a caller's capture a count of 4k + 2 records its last pair of steps that
+ * way too, so that every replay leaves each box in the buffer the next one expects. Each box's step counter advances by nsteps. Asynchronous. Calls that overlap in time
  * on one GPU (enqueued on different streams) race on the shared array; calls on one stream are
  * ordered. While the caller is capturing the stream the launches are recorded into the caller's
  * graph: nsteps must then be even, every replay advances the boxes by nsteps, and the host step

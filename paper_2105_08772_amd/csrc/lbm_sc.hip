@@ -1607,8 +1607,6 @@ int lbm_sc_step_boxes_noalloc(lbm_sc* const* boxes, int32_t nbox, int64_t nsteps
         return fail(LBM_SC_EINVAL, "lbm_sc_step_boxes_noalloc takes at most 1024 boxes");
     if (nsteps < 0) return fail(LBM_SC_EINVAL, "nsteps must be >= 0");
     if (int rc = check_group_launch(launch)) return rc;
-    if (launch->steps_per_pass == 2)
-        return fail(LBM_SC_EINVAL, "lbm_sc_step_boxes_noalloc takes one step per launch (steps_per_pass 0 or 1)");
     const lbm_sc_group_launch& L = *launch;
     const lbm::StepShape shape = group_shape(L);
     for (int i = 0; i < nbox; ++i) {
@@ -1663,18 +1661,49 @@ int lbm_sc_step_boxes_noalloc(lbm_sc* const* boxes, int32_t nbox, int64_t nsteps
     }
     const unsigned workers = L.workers ? (unsigned)L.workers : 256u;
     const bool fp32 = boxes[0]->fp32, math64 = boxes[0]->math64;
-    int64_t done = 0;
+    // done: steps taken; flips: launches, each moving every box to its other buffer
+    int64_t done = 0, flips = 0;
     hipError_t e = hipSuccess;
-    for (; done < nsteps && e == hipSuccess; ++done)
-        e = lbm::launch_step_group(fp32, math64, shape, d_desc, nbox, nitems, (int)(done & 1),
-                                   L.persistent, workers, d_queue, st);
-    if (e != hipSuccess) --done;   // the failed launch did not step
+    if (group_spp(L) == 1) {
+        for (; done < nsteps && e == hipSuccess; ++done, ++flips)
+            e = lbm::launch_step_group(fp32, math64, shape, d_desc, nbox, nitems, (int)(flips & 1),
+                                       L.persistent, workers, d_queue, st);
+        if (e != hipSuccess) {   // the failed launch did not step
+            --done;
+            --flips;
+        }
+    } else {
+        // two steps per launch (the items in list order: no per-XCD item order, which would not
+        // fit the fixed array); the rest as single steps of each box alone in its own single-step
+        // shape: an odd last step, and inside a caller's capture the last pair of a count of
+        // 4k + 2, so that the recorded launches move every box an even number of times
+        int64_t pairs = nsteps / 2;
+        if (cs != hipStreamCaptureStatusNone && (pairs & 1)) --pairs;
+        for (int64_t k = 0; k < pairs && e == hipSuccess; ++k) {
+            e = lbm::launch_group2_f32(shape, d_desc, nbox, nitems, nullptr, 0, (int)(flips & 1), st);
+            if (e == hipSuccess) {
+                done += 2;
+                ++flips;
+            }
+        }
+        while (done < nsteps && e == hipSuccess) {
+            for (int i = 0; i < nbox && e == hipSuccess; ++i) {
+                const lbm_sc* h = boxes[i];
+                const int c = (int)((h->cur + flips) & 1);
+                e = lbm::launch_step(h->fp32, h->math64, h->box, h->shape, c, h->pop[c], h->pop[1 - c], st);
+            }
+            if (e == hipSuccess) {
+                ++done;
+                ++flips;
+            }
+        }
+    }
     for (int i = 0; i < nbox; ++i) {
         lbm_sc* h = boxes[i];
-        h->cur = (int)((h->cur + done) & 1);
+        h->cur = (int)((h->cur + flips) & 1);
         h->step += done;
     }
-    if (e != hipSuccess) return fail_hip("launch_step_group", e);
+    if (e != hipSuccess) return fail_hip("multi-box step launch", e);
     return LBM_SC_OK;
 }
 

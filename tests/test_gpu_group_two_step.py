@@ -5,8 +5,8 @@ must end bitwise equal to the same box advanced by single steps alone: for every
 shape, fixed and per-box z chunks, graph replays and plain launches, odd step counts, packed and
 padded rows, both pseudopotentials, a box that steps alone in between, the FP32 dither's step
 count over thousands of steps, and the full 64-box batched mix against the single-step group.
-Groups that cannot take it (FP64 storage or arithmetic, tau != 1, the persistent grid, the
-allocation-free entry point) reject it.
+Groups that cannot take it (FP64 storage or arithmetic, tau != 1, the persistent grid) reject it,
+and so does the allocation-free entry point for such boxes.
 """
 import sys
 
@@ -219,7 +219,13 @@ def test_two_step_group_is_refused_where_it_does_not_apply():
         g.set([good])
         assert g.launch()["steps_per_pass"] == 2
         g.step(3)
+    # the allocation-free step takes two steps per launch for the boxes a group takes them for,
+    # and refuses the others and the persistent grid
+    lbm.lbm_sc_step_boxes_noalloc([good.h], 2, **two)
+    for bb in bad_boxes:
+        with pytest.raises(lbm.LbmScError):
+            lbm.lbm_sc_step_boxes_noalloc([bb.h], 2, **two)
     with pytest.raises(lbm.LbmScError):
-        lbm.lbm_sc_step_boxes_noalloc([good.h], 2, **two)
+        lbm.lbm_sc_step_boxes_noalloc([good.h], 2, **dict(two, persistent=1, workers=64))
     for b in bad_boxes + [good]:
         b.close()

@@ -1,7 +1,8 @@
 """The allocation-free multi-box step (lbm_sc_step_boxes_noalloc) against the group step: the same
 boxes stepped by both end bitwise equal, on two calls in a row (the second with fewer and smaller
 boxes, so the fixed device array still holds the first call's longer work list), with and without
-the persistent work-queue kernel, and when recorded into a caller's graph and replayed."""
+the persistent work-queue kernel, with two steps per launch (odd counts ending in single steps),
+and when recorded into a caller's graph and replayed."""
 import sys
 
 import numpy as np
@@ -130,3 +131,61 @@ def test_noalloc_rejects_bad_calls_before_any_device_work():
             [a.h] * (lbm.LBM_SC_NOALLOC_MAX_BOXES + 1), 2, **BASE).value)
         assert np.array_equal(a.get(), before)
         assert a.observables(profile=False)[0]["step"] == 0
+
+
+# two steps per launch: FP32-shifted boxes at tau = 1 only
+TWO = [dict(BASE, rows=2, waves=8, tile_x=32, z_chunk=0, items_per_cu=4, steps_per_pass=2),
+       dict(BASE, rows=1, waves=8, tile_x=64, prefetch=1, z_chunk=9, steps_per_pass=2)]
+
+
+def configs_tau1(stream):
+    return [c for c in configs(lbm.LBM_SC_FP32_SHIFTED, stream) if c.tau == 1.0]
+
+
+@pytest.mark.parametrize("li", range(len(TWO)))
+def test_noalloc_two_steps_per_launch_equal_group_step(li):
+    import torch
+    launch = TWO[li]
+    say(f"allocation-free step, two steps per launch: {launch}")
+    s = torch.cuda.Stream()
+    first = configs_tau1(s.cuda_stream)
+    second = [first[2], first[0]]          # fewer and smaller boxes on the second call
+    for cfgs, nsteps in ((first, 11), (second, 7)):
+        want = by_group(cfgs, launch, nsteps, s.cuda_stream)
+        boxes = [lbm.Box(c) for c in cfgs]
+        lbm.lbm_sc_step_boxes_noalloc([b.h for b in boxes], 3, **launch)
+        lbm.lbm_sc_step_boxes_noalloc([b.h for b in boxes], nsteps - 3, **launch)
+        got = [b.get() for b in boxes]
+        steps = [b.observables(profile=False)[0]["step"] for b in boxes]
+        for b in boxes:
+            b.close()
+        assert steps == [nsteps] * len(cfgs)
+        for k, (a, w) in enumerate(zip(got, want)):
+            assert np.array_equal(a, w), f"box {k} of {len(cfgs)} differs from the group step"
+
+
+@pytest.mark.parametrize("nsteps", [4, 6])
+def test_noalloc_two_steps_per_launch_recorded_into_a_caller_graph(nsteps):
+    """Recorded inside a caller's capture, 4 steps (two launches) and 6 (two launches and a pair
+    of single steps, so that the replays find every box where they expect it): each replay
+    advances the boxes like the same number of eager allocation-free steps."""
+    import torch
+    say(f"allocation-free two-step launches inside a caller's graph capture, {nsteps} steps")
+    s = torch.cuda.Stream()
+    launch = TWO[0]
+    cfgs = configs_tau1(s.cuda_stream)[:3]
+    boxes = [lbm.Box(c) for c in cfgs]
+    refs = [lbm.Box(c) for c in cfgs]
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        lbm.lbm_sc_step_boxes_noalloc([b.h for b in boxes], nsteps, **launch)
+    for _ in range(3):
+        g.replay()
+        torch.cuda.synchronize()
+        lbm.lbm_sc_step_boxes_noalloc([b.h for b in refs], nsteps, **launch)
+        torch.cuda.synchronize()
+        for b, r in zip(boxes, refs):
+            assert np.array_equal(b.get(), r.get())
+    for b in boxes + refs:
+        b.close()
