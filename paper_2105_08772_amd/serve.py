@@ -124,7 +124,8 @@ class GpuBackend:
     def create(self, r):
         return self._Box(self.config(r))
 
-    # x-y tiles: every box size fits them (full-row tiles need rows short enough for the workgroup)
+    # single-step x-y tiles: every box fits them (full-row tiles need rows short enough for the
+    # workgroup, two steps per launch FP32 boxes at tau = 1)
     FALLBACK = dict(rows=2, waves=4, tile_x=64, prefetch=0, persistent=0, steps_per_pass=1)
 
     def set_active(self, boxes):
@@ -140,13 +141,14 @@ class GpuBackend:
             self.group.set(boxes)
         except self.error:
             launch = self.group.launch()
-            if launch["tile_x"] != 0:
+            if launch["tile_x"] != 0 and launch.get("steps_per_pass", 1) != 2:
                 raise
-            # a box's rows are too long for the full-row tiles: switch the group to x-y tiles
+            # a box's rows are too long for the full-row tiles, or a box cannot take two steps
+            # per launch (tau != 1): switch the group to single-step x-y tiles
             self.group.set([])
             self.group.set_launch(**self.FALLBACK)
+            self.fallen_back = launch   # restored by the next call, also if this set fails
             self.group.set(boxes)
-            self.fallen_back = launch
 
     def set_launch(self, **kw):
         self.fallen_back = None

@@ -235,6 +235,44 @@ def test_backend_leaves_the_xy_tile_fallback_when_the_wide_box_leaves():
     assert be.group.launch() == chosen and be.group.boxes == ["small"]
 
 
+def test_backend_leaves_two_steps_per_launch_for_a_box_that_cannot_take_them():
+    """A box the two-step group refuses (tau != 1) switches the group to single-step x-y
+    tiles; once it has left, the two-step launch comes back; other refusals propagate."""
+    from paper_2105_08772_amd import LbmScError
+
+    class FakeGroup:
+        def __init__(self):
+            self.shape = dict(tile_x=32, rows=2, waves=8, z_chunk=16, prefetch=0, persistent=0,
+                              steps_per_pass=2)
+            self.boxes = []
+
+        def set(self, boxes):
+            if self.shape["steps_per_pass"] == 2 and "tau08" in boxes:
+                raise LbmScError(-1, "two steps per pass need tau = 1")
+            if "bad" in boxes:
+                raise LbmScError(-1, "a box was not created on the group's stream")
+            self.boxes = list(boxes)
+
+        def set_launch(self, **kw):
+            assert not self.boxes
+            self.shape.update(kw)
+
+        def launch(self):
+            return dict(self.shape)
+
+    be = object.__new__(serve.GpuBackend)
+    be.single, be.group, be.fallen_back, be.error = False, FakeGroup(), None, LbmScError
+    chosen = be.group.launch()
+    be.set_active(["a", "tau08"])
+    assert be.group.launch()["steps_per_pass"] == 1 and be.group.boxes == ["a", "tau08"]
+    be.set_active(["a"])
+    assert be.group.launch() == chosen and be.group.boxes == ["a"]
+    with pytest.raises(LbmScError):
+        be.set_active(["a", "bad"])
+    be.set_active(["a"])                 # the chosen launch comes back after a failed set
+    assert be.group.launch() == chosen and be.group.boxes == ["a"]
+
+
 class BackendError(RuntimeError):
     pass
 
