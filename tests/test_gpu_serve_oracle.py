@@ -1,6 +1,7 @@
 """Served requests against the FP64 oracle: three small droplet/bubble requests arriving at
 different times are served together (continuous batching, one multi-box launch per step) with FP64
-and with FP32-shifted populations. Each request's stop status, stop step and stop criterion must
+and with FP32-shifted populations, and with FP32-shifted populations under the benchmark's served
+launch (two steps per launch, bitwise equal to the single-step launches). Each request's stop status, stop step and stop criterion must
 be the ones the oracle's own trajectory implies under the same rule (Sec. 4 convergence criteria:
 relative dP change below 1e-5 between observations, or max |du| below 1e-9; a dissolved droplet
 or bubble stops as evaporated), and its final populations must match the oracle's at that step:
@@ -78,9 +79,19 @@ class ChunkClockGpu(serve.GpuBackend):
         self.clock.t += 1.0
 
 
-def serve_gpu(prec):
+# the launch the benchmark's served workload uses: two steps per multi-box launch in 32 x 16 tiles,
+# z chunks of 16 planes, on rows padded to whole lines
+SERVED_TWO_STEP = dict(rows=2, waves=8, tile_x=32, z_chunk=16, prefetch=0, persistent=0, workers=0,
+                       items_per_cu=0, steps_per_pass=2, graph_steps=64)
+
+
+def serve_gpu(prec, launch=None):
     clock = Clock()
-    be = ChunkClockGpu(clock, prec=prec, width=WIDTH, noise_amp=NOISE)
+    if launch:
+        be = ChunkClockGpu(clock, prec=prec, width=WIDTH, noise_amp=NOISE, packed_rows=False)
+        be.set_launch(**launch)
+    else:
+        be = ChunkClockGpu(clock, prec=prec, width=WIDTH, noise_amp=NOISE)
     reqs = requests()
     budget = sum(be.bytes_needed(r) for r in reqs)
     srv = serve.Server(be, budget, chunk=CHUNK, observe_every=EVERY, max_steps=20000,
@@ -136,10 +147,18 @@ def oracle_runs():
     return out
 
 
-@pytest.mark.parametrize("prec", [lbm.LBM_SC_FP64, lbm.LBM_SC_FP32_SHIFTED])
-def test_served_requests_match_the_oracle(oracle_runs, prec):
-    say(f"serving 3 requests with prec={prec}")
-    recs, srv = serve_gpu(prec)
+@pytest.mark.parametrize("prec,launch", [(lbm.LBM_SC_FP64, None), (lbm.LBM_SC_FP32_SHIFTED, None),
+                                         (lbm.LBM_SC_FP32_SHIFTED, SERVED_TWO_STEP)])
+def test_served_requests_match_the_oracle(oracle_runs, prec, launch):
+    say(f"serving 3 requests with prec={prec} launch={launch}")
+    recs, srv = serve_gpu(prec, launch)
+    if launch:
+        # two steps per launch: every served result bitwise that of single-step launches
+        single, _ = serve_gpu(prec)
+        for rid, rec in recs.items():
+            assert (rec.status, rec.criterion, rec.steps) == \
+                (single[rid].status, single[rid].criterion, single[rid].steps), rid
+            assert np.array_equal(rec.final, single[rid].final), rid
     assert srv.max_active >= 2          # the requests overlapped on the device
     G = {r.rid: eos.G_of(r.g_over_gc, core.PSI_EXP) for r in requests()}
     for rid, rec in sorted(recs.items()):
