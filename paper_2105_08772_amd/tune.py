@@ -28,7 +28,7 @@ def group_candidates(two_step=True):
     """Every compiled single-step shape with z chunks of 6..64 planes or per-box chunks (z_chunk
     0) of 4, 8 or 16 items per CU, one workgroup per item or persistent workers; and (two_step:
     groups of FP32 boxes at tau = 1, refused by other groups) every two-steps-per-pass shape with
-    z chunks of 16..64 planes or per-box chunks, one workgroup per item."""
+    z chunks of 16..128 planes or per-box chunks, one workgroup per item."""
     out = []
     chunks = [dict(z_chunk=zc, items_per_cu=0) for zc in (6, 8, 16, 32, 64)]
     chunks += [dict(z_chunk=0, items_per_cu=k) for k in (4, 8, 16)]
@@ -38,7 +38,7 @@ def group_candidates(two_step=True):
             out.append(dict(shape, **ch, xcd_remap=1, persistent=1, workers=workers,
                             steps_per_pass=1))
     if two_step:
-        chunks2 = [dict(z_chunk=zc, items_per_cu=0) for zc in (16, 32, 64)]
+        chunks2 = [dict(z_chunk=zc, items_per_cu=0) for zc in (16, 32, 64, 96, 128)]
         chunks2 += [dict(z_chunk=0, items_per_cu=k) for k in (4, 8, 16)]
         for shape, ch in itertools.product(SHAPES2, chunks2):
             out.append(dict(shape, **ch, xcd_remap=1, persistent=0, workers=0, steps_per_pass=2))

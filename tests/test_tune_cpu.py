@@ -42,7 +42,7 @@ def test_group_candidates_are_unique_and_valid():
     one = [c for c in cands if c["steps_per_pass"] == 1]
     two = [c for c in cands if c["steps_per_pass"] == 2]
     assert len(one) == len(tune.SHAPES) * (5 + 3) * 3
-    assert len(two) == len(tune.SHAPES2) * (3 + 3) and not any(c["persistent"] for c in two)
+    assert len(two) == len(tune.SHAPES2) * (5 + 3) and not any(c["persistent"] for c in two)
     assert all(c["z_chunk"] == 0 or c["z_chunk"] >= 16 for c in two)
     assert len(tune.group_candidates(two_step=False)) == len(one)
 
