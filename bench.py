@@ -27,17 +27,27 @@ METRIC = ("MLUPS + % of HBM roofline (1 GPU); batched droplets/hour and p50/p99 
           "time-to-equilibrium")
 HBM_PEAK_GBPS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step_droplet256_fp32.json")
+GROUP_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_group64_fp32.json")
 KERNEL_SRC = [os.path.join(ROOT, "paper_2105_08772_amd", "csrc", n)
               for n in ("step_kernels.hpp", "kernels.hpp", "d3q19.hpp")]
+# the multi-box launches also depend on the host's work list and item order
+GROUP_SRC = KERNEL_SRC + [os.path.join(ROOT, "paper_2105_08772_amd", "csrc", "lbm_sc.hip")]
+GROUP_NODES = 102318059      # the batched mix (seed 2105)
 
 
-def kernel_hash():
-    """Hash of the sources of the step kernels (their template code, layout and constants)."""
+def kernel_hash(paths=None):
+    """Hash of the sources of the step kernels (their template code, layout and constants), or
+    of the given files."""
     h = hashlib.sha256()
-    for p in KERNEL_SRC:
+    for p in paths or KERNEL_SRC:
         with open(p, "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+def group_hash():
+    """Hash of the step kernels and of the host code that builds a group's work list."""
+    return kernel_hash(GROUP_SRC)
 
 
 def measured_traffic(nodes, prec, launch):
@@ -128,19 +138,21 @@ def traffic_summary(prof_dir, bench_log, out_path):
           f"({spp} step(s) per launch)")
 
 
-def group_traffic(prof_dir, bench_log=None, timed_steps=256 + 128):
+def group_traffic(prof_dir, bench_log=None, timed_steps=256 + 128, out_path=None):
     """The same scaling for the multi-box step's counter runs (pmc_FETCH_SIZE_group,
     pmc_WRITE_SIZE_group), over the dispatches of the timed mix: its `timed_steps` steps (the
     256 steps of the counted run and the 128-step kernel timing), one dispatch per step, or per
     two steps when the tuned launch (from the counted run's bench line in bench_log) takes two
-    steps per pass; printed, not stored."""
+    steps per pass. Printed; with bench_log and out_path also written as the record the batched
+    leg reads (keyed by the tuned launch and the group sources' hash)."""
     with open(TRAFFIC_FILE) as fh:
         t = json.load(fh)
-    spp = 1
+    spp, launch = 1, None
     if bench_log:
         with open(bench_log) as fh:
             res = json.loads([ln for ln in fh if ln.startswith("{")][-1])
-        spp = res["batched"]["launch"].get("steps_per_pass", 1)
+        launch = res["batched"]["launch"]
+        spp = launch.get("steps_per_pass", 1)
     kernel = "void lbm::(anonymous namespace)::" + ("k_step2_group<" if spp == 2 else "k_step_group<")
     out = {"kernel": kernel, "steps_per_launch": spp}
     for counter, scale in (("FETCH_SIZE", t["fetch_scale"]), ("WRITE_SIZE", t["write_scale"])):
@@ -149,6 +161,36 @@ def group_traffic(prof_dir, bench_log=None, timed_steps=256 + 128):
         out[counter] = {"KiB_per_dispatch": round(v, 1), "bytes_per_launch": int(v * 1024 * scale),
                         "bytes_per_step": int(v * 1024 * scale / spp), "dispatches": n}
     print(json.dumps(out, indent=1))
+    if out_path and launch is not None:
+        rec = {"kernel": "multi-box step, batched 64-box mix (seed 2105), tuned launch",
+               "nodes": GROUP_NODES, "launch": launch, "steps_per_launch": spp,
+               "group_sha256_16": group_hash(),
+               "fetch_scale": t["fetch_scale"], "write_scale": t["write_scale"],
+               "FETCH_SIZE_KiB_per_dispatch": out["FETCH_SIZE"]["KiB_per_dispatch"],
+               "WRITE_SIZE_KiB_per_dispatch": out["WRITE_SIZE"]["KiB_per_dispatch"],
+               "fetch_bytes_per_launch": out["FETCH_SIZE"]["bytes_per_launch"],
+               "write_bytes_per_launch": out["WRITE_SIZE"]["bytes_per_launch"],
+               "bytes_per_launch": out["FETCH_SIZE"]["bytes_per_launch"]
+               + out["WRITE_SIZE"]["bytes_per_launch"],
+               "algorithmic_bytes_per_launch": 2 * 19 * 4 * GROUP_NODES * spp,
+               "dispatches": n}
+        with open(out_path, "w") as fh:
+            json.dump(rec, fh, indent=1)
+            fh.write("\n")
+
+
+def measured_group_traffic(nodes, launch):
+    """HBM bytes per multi-box launch from the committed group counter record, if it was taken
+    on the current group sources, the same mix and the same launch (else None)."""
+    try:
+        with open(GROUP_TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if (t.get("group_sha256_16") != group_hash() or t.get("nodes") != nodes
+            or t.get("launch") != launch):
+        return None
+    return t.get("bytes_per_launch")
 
 
 def stream_copy_gbps(torch, lbm, stream, nbytes=2 << 30, reps=20):
@@ -311,6 +353,10 @@ def run_batched(args, torch, lbm, stream, steps, log):
         "kernel_ms_per_step": round(t_step * 1e3, 4),
         "kernel_GBps": round(ginfo["bytes_per_step"] / t_step / 1e9, 1),
         "kernel_frac_of_8TBps": round(ginfo["bytes_per_step"] / t_step / 1e9 / HBM_PEAK_GBPS, 4),
+        # HBM bytes per launch (one or two steps) from the committed counter record of this mix
+        # and launch, null when the record does not match
+        "steps_per_launch": launch.get("steps_per_pass", 1),
+        "traffic_bytes_per_launch": measured_group_traffic(total_nodes, dict(launch, packed_rows=packed)),
         "launch": dict(launch, packed_rows=packed),
         "tuned_ms_per_step": {("two_step" if t["steps_per_pass"] == 2 else "single_step"):
                               round(t["seconds_per_step"] * 1e3, 4) for t in tuned},
@@ -724,7 +770,8 @@ def main():
         if args.traffic_bench_log:
             traffic_summary(args.traffic_from, args.traffic_bench_log, TRAFFIC_FILE)
         else:
-            group_traffic(args.traffic_from, args.traffic_group_log)
+            group_traffic(args.traffic_from, args.traffic_group_log,
+                          out_path=GROUP_TRAFFIC_FILE if args.traffic_group_log else None)
         return
     if args.gpus != 1:
         print("bench.py: the library runs on one GPU only (there is no multi-GPU path); use --gpus 1",

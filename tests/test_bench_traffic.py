@@ -116,9 +116,15 @@ def test_group_traffic_follows_the_tuned_kernel(tmp_path, capsys):
     log = os.path.join(p, "group.log")
     with open(log, "w") as fh:
         fh.write(json.dumps({"batched": {"launch": {"steps_per_pass": 2, "tile_x": 32}}}) + "\n")
-    b.group_traffic(p, log)
+    rec_path = os.path.join(p, "group_record.json")
+    b.group_traffic(p, log, out_path=rec_path)
     out = json.loads(capsys.readouterr().out)
     assert out["steps_per_launch"] == 2 and out["kernel"].endswith("k_step2_group<")
+    g = json.load(open(rec_path))
+    assert g["launch"] == {"steps_per_pass": 2, "tile_x": 32} and g["steps_per_launch"] == 2
+    assert g["group_sha256_16"] == b.group_hash() and g["nodes"] == b.GROUP_NODES
+    assert g["bytes_per_launch"] == g["fetch_bytes_per_launch"] + g["write_bytes_per_launch"]
+    assert g["algorithmic_bytes_per_launch"] == 152 * b.GROUP_NODES * 2
     assert out["FETCH_SIZE"]["dispatches"] == 192 and out["FETCH_SIZE"]["KiB_per_dispatch"] == 1000.0
     assert out["FETCH_SIZE"]["bytes_per_launch"] == int(1000 * 1024 * rec["fetch_scale"])
     assert out["FETCH_SIZE"]["bytes_per_step"] == int(1000 * 1024 * rec["fetch_scale"] / 2)
@@ -130,3 +136,21 @@ def test_group_traffic_follows_the_tuned_kernel(tmp_path, capsys):
     out = json.loads(capsys.readouterr().out)
     assert out["steps_per_launch"] == 1 and out["FETCH_SIZE"]["dispatches"] == 25
     assert out["FETCH_SIZE"]["KiB_per_dispatch"] == 5000.0
+
+
+def test_committed_group_traffic_record_matches_the_current_sources():
+    """The batched leg reports the committed counter record only for the group sources and the
+    launch it was taken on; the record is consistent with itself."""
+    b = bench()
+    with open(b.GROUP_TRAFFIC_FILE) as fh:
+        g = json.load(fh)
+    assert g["group_sha256_16"] == b.group_hash(), \
+        "step kernels or group host code changed since the counters were taken: profile again"
+    assert b.measured_group_traffic(g["nodes"], g["launch"]) == g["bytes_per_launch"]
+    assert b.measured_group_traffic(g["nodes"], dict(g["launch"], z_chunk=7)) is None
+    assert g["bytes_per_launch"] == g["fetch_bytes_per_launch"] + g["write_bytes_per_launch"]
+    spp = g["steps_per_launch"]
+    one_pass = g["algorithmic_bytes_per_launch"] / 2 / spp
+    # a launch reads at least one pass over the state and writes about one (plus padding lanes)
+    assert g["fetch_bytes_per_launch"] >= one_pass
+    assert 0.99 < g["write_bytes_per_launch"] / one_pass < 1.15
