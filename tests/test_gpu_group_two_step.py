@@ -24,7 +24,7 @@ def say(*a):
     sys.stdout.flush()
 
 
-def box_configs(stream, packed=(0, 0, 0, 0, 0, 0)):
+def box_configs(stream, packed=(0, 0, 0, 0, 0, 0, 0)):
     """FP32-shifted boxes at tau = 1: ragged sizes, both psi, droplet, bubble and slab."""
     F32 = lbm.LBM_SC_FP32_SHIFTED
     c = [lbm.config(20, 20, 20, psi=0, geom=lbm.LBM_SC_DROPLET, prec=F32, g_over_gc=1.3,
@@ -38,7 +38,9 @@ def box_configs(stream, packed=(0, 0, 0, 0, 0, 0)):
          lbm.config(131, 9, 40, psi=0, geom=lbm.LBM_SC_DROPLET, prec=F32, g_over_gc=1.7,
                     radius=6.0, width=2.0, noise_amp=1e-6, seed=14, stream=stream),
          lbm.config(49, 49, 2, psi=1, geom=lbm.LBM_SC_DROPLET, prec=F32, g_over_gc=1.4,
-                    radius=8.0, width=2.0, noise_amp=1e-6, seed=15, stream=stream)]
+                    radius=8.0, width=2.0, noise_amp=1e-6, seed=15, stream=stream),
+         lbm.config(1, 2, 3, psi=1, geom=lbm.LBM_SC_DROPLET, prec=F32, g_over_gc=1.2,
+                    radius=1.0, width=1.0, noise_amp=1e-3, seed=16, stream=stream)]
     for cfg, p in zip(c, packed):
         cfg.packed_rows = p
     return c
@@ -99,7 +101,7 @@ def test_two_step_group_packed_rows_resync_and_reorder():
     out of phase (rebuilt before the next launch); the box order changes between calls."""
     import torch
     s = torch.cuda.Stream()
-    cfgs = box_configs(s.cuda_stream, packed=(1, 0, 1, 1, 0, 1))
+    cfgs = box_configs(s.cuda_stream, packed=(1, 0, 1, 1, 0, 1, 1))
     want = alone_single(box_configs(s.cuda_stream), (15,))
     boxes = [lbm.Box(c) for c in cfgs]
     with lbm.Group(s.cuda_stream) as g:
