@@ -402,12 +402,11 @@ def run_served(args, torch, lbm, log, capacity_mlups=None):
         torch.cuda.empty_cache()
         return srv, recs, budget
 
-    # two steps per launch in 32 x 16 tiles on rows padded to whole lines, z chunks of 16 planes
-    # (a few boxes at a time: short chunks keep every CU busy); measured on this workload against
-    # full-row single-step launches on packed rows: p50 / p99 1.58 / 7.99 s against 1.71 / 9.75 s
-    be = serve.GpuBackend(packed_rows=False)
-    be.set_launch(rows=2, waves=8, tile_x=32, z_chunk=16, prefetch=0, persistent=0, workers=0,
-                  items_per_cu=0, steps_per_pass=2, graph_steps=64)
+    # the backend's default for FP32-shifted boxes at tau = 1: two steps per launch in 32 x 16
+    # tiles on rows padded to whole lines, z chunks of 16 planes (a few boxes at a time: short
+    # chunks keep every CU busy)
+    be = serve.GpuBackend()
+    assert be.group.launch()["steps_per_pass"] == 2 and not be.packed_rows
     journal = open(args.served_journal, "w") if args.served_journal else None
     srv, recs, budget = serve_all(be, journal=journal)
     if journal:
@@ -496,7 +495,7 @@ def tolman_sweep(torch, lbm, log, psi):
                 rid += 1
 
     def sweep(prec):
-        be = serve.GpuBackend(prec=prec, width=1.0)
+        be = serve.GpuBackend(prec=prec, width=1.0, packed_rows=True)
         be.set_launch(rows=4, waves=8, tile_x=0, z_chunk=8, prefetch=0, persistent=0, workers=0,
                       graph_steps=64)
         srv = serve.Server(be, be.free_bytes() - (8 << 30), chunk=512, observe_every=2048,

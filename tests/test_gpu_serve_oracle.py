@@ -79,17 +79,14 @@ class ChunkClockGpu(serve.GpuBackend):
         self.clock.t += 1.0
 
 
-# the launch the benchmark's served workload uses: two steps per multi-box launch in 32 x 16 tiles,
-# z chunks of 16 planes, on rows padded to whole lines
-SERVED_TWO_STEP = dict(rows=2, waves=8, tile_x=32, z_chunk=16, prefetch=0, persistent=0, workers=0,
-                       items_per_cu=0, steps_per_pass=2, graph_steps=64)
-
-
-def serve_gpu(prec, launch=None):
+def serve_gpu(prec, single_step=False):
+    """Serve the requests with the backend's default launch (for FP32-shifted boxes at tau = 1
+    two steps per launch on padded rows, the benchmark's served configuration), or with
+    single-step full-row launches on packed rows."""
     clock = Clock()
-    if launch:
-        be = ChunkClockGpu(clock, prec=prec, width=WIDTH, noise_amp=NOISE, packed_rows=False)
-        be.set_launch(**launch)
+    if single_step:
+        be = ChunkClockGpu(clock, prec=prec, width=WIDTH, noise_amp=NOISE, packed_rows=True)
+        be.set_launch(**serve.GpuBackend.FULL_ROW)
     else:
         be = ChunkClockGpu(clock, prec=prec, width=WIDTH, noise_amp=NOISE)
     reqs = requests()
@@ -101,6 +98,7 @@ def serve_gpu(prec, launch=None):
     for r in reqs:
         srv.submit(r)
     recs = {r.rid: r for r in srv.run()}
+    srv.launch_used = be.group.launch()
     be.close()
     return recs, srv
 
@@ -147,14 +145,16 @@ def oracle_runs():
     return out
 
 
-@pytest.mark.parametrize("prec,launch", [(lbm.LBM_SC_FP64, None), (lbm.LBM_SC_FP32_SHIFTED, None),
-                                         (lbm.LBM_SC_FP32_SHIFTED, SERVED_TWO_STEP)])
-def test_served_requests_match_the_oracle(oracle_runs, prec, launch):
-    say(f"serving 3 requests with prec={prec} launch={launch}")
-    recs, srv = serve_gpu(prec, launch)
-    if launch:
+@pytest.mark.parametrize("prec,single_step", [(lbm.LBM_SC_FP64, False),
+                                               (lbm.LBM_SC_FP32_SHIFTED, True),
+                                               (lbm.LBM_SC_FP32_SHIFTED, False)])
+def test_served_requests_match_the_oracle(oracle_runs, prec, single_step):
+    say(f"serving 3 requests with prec={prec} single_step={single_step}")
+    recs, srv = serve_gpu(prec, single_step)
+    if prec == lbm.LBM_SC_FP32_SHIFTED and not single_step:
+        assert srv.launch_used["steps_per_pass"] == 2
         # two steps per launch: every served result bitwise that of single-step launches
-        single, _ = serve_gpu(prec)
+        single, _ = serve_gpu(prec, single_step=True)
         for rid, rec in recs.items():
             assert (rec.status, rec.criterion, rec.steps) == \
                 (single[rid].status, single[rid].criterion, single[rid].steps), rid
