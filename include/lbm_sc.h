@@ -203,8 +203,9 @@ int lbm_sc_set_step(lbm_sc* h, int64_t step);
  * with the line grid; LBM_SC_EINVAL if that is below 1). steps_per_pass = 2 selects the
  * two-steps-per-pass kernel instead (FP32 storage and arithmetic, tau = 1), whose shapes are
  * tile_x 64 with rows 1 and waves 8 (64 x 8 tiles, either prefetch setting), tile_x 32 with rows
- * 2 and waves 8 (32 x 16 tiles, either prefetch setting) or tile_x 64 with rows 2 and waves 16
- * (64 x 16 tiles, prefetch 0); it is the default for those boxes (32 x 16 without prefetch from
+ * 2 and waves 8 (32 x 16 tiles, either prefetch setting), tile_x 32 with rows 2 and waves 4
+ * (32 x 16 tiles, two nodes per thread, prefetch 0) or tile_x 64 with rows 2 and waves 16
+ * (64 x 16 tiles, prefetch 0); it is the default for those boxes (32 x 16 tiles of 4 waves from
  * 3 M nodes, 64 x 8 with prefetch below), and lbm_sc_get_launch reports the shape of the kernel
  * in use. */
 typedef struct {

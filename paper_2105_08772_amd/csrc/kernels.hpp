@@ -63,6 +63,7 @@ inline bool step2_shape_supported(const StepShape& s)
     if (s.z_chunk < 1 || (s.xcd_remap & ~1) || (s.prefetch & ~1)) return false;
     return (s.tile_x == 64 && s.rows == 1 && s.waves == 8) ||
            (s.tile_x == 32 && s.rows == 2 && s.waves == 8) ||
+           (s.tile_x == 32 && s.rows == 2 && s.waves == 4 && s.prefetch == 0) ||
            (s.tile_x == 64 && s.rows == 2 && s.waves == 16 && s.prefetch == 0);
 }
 

@@ -27,7 +27,8 @@ const char* const SHAPE_MSG =
 
 const char* const SHAPE2_MSG =
     "unsupported two-step launch shape (tile_x 64 with rows 1 and waves 8, tile_x 32 with rows 2 and "
-    "waves 8, or tile_x 64 with rows 2 and waves 16 without prefetch)";
+    "waves 8, or without prefetch tile_x 32 with rows 2 and waves 4 or tile_x 64 with rows 2 and "
+    "waves 16)";
 
 int fail(int code, const char* msg)
 {
@@ -560,15 +561,15 @@ void default_shape(lbm_sc* h)
     const int slots = cus * (h->shape.prefetch ? 1 : std::max(1, 8 / h->shape.waves));
     h->shape.z_chunk = z_chunk_for(h->box, h->shape.tile_x, lbm::tile_height(h->shape), slots, 2);
     // FP32 storage and arithmetic at tau = 1: two steps per pass, each chunk pulling 6 planes more
-    // than it steps. Boxes of 3 M nodes or more: 32 x 16 tiles of 8 waves without prefetch (78 KB
-    // of LDS and 128 VGPRs: two workgroups per CU); smaller ones: 64 x 8 tiles of 8 waves with the
-    // next plane prefetched (one workgroup per CU). Measured against the 64 x 8 tiles: 3-13 %
-    // faster from 160^3 to 384^3, 4 % at 96^3, 3 % slower at 128^3 and 24-29 % slower at 48^3 and
-    // 64^3; the two-step kernel runs 1.11-1.22x the single-step rate for boxes of 128^3 to 384^3
-    // in 64 x 8 tiles
+    // than it steps. Boxes of 3 M nodes or more: 32 x 16 tiles of 4 waves without prefetch (two
+    // nodes per thread, 78 KB of LDS and 215 VGPRs without spills: two workgroups per CU);
+    // smaller ones: 64 x 8 tiles of 8 waves with the next plane prefetched (one workgroup per CU).
+    // Measured against the 64 x 8 tiles: 11-16 % faster from 160^3 to 384^3 (and 2-8 % faster
+    // than 32 x 16 tiles of 8 waves, whose 128 VGPRs spill), 3 % slower at 128^3, 35-39 % slower
+    // at 48^3 and 64^3
     const bool big = (double)h->box.n >= 3.0e6;
     h->shape2.rows = big ? 2 : 1;
-    h->shape2.waves = 8;
+    h->shape2.waves = big ? 4 : 8;
     h->shape2.prefetch = big ? 0 : 1;
     h->shape2.tile_x = big ? 32 : 64;
     h->shape2.xcd_remap = 1;

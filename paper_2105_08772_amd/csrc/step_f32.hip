@@ -47,6 +47,8 @@ hipError_t launch_step2_f32(const BoxDesc& b, const StepShape& s, int sbuf, cons
     if (s.tile_x == 32 && s.rows == 2 && s.waves == 8)
         return s.prefetch ? launch_step2_t<32, 16, 8, true>(b, zc, remap, sbuf, src, dst, st)
                           : launch_step2_t<32, 16, 8, false, 4>(b, zc, remap, sbuf, src, dst, st);
+    if (s.tile_x == 32 && s.rows == 2 && s.waves == 4 && !s.prefetch)
+        return launch_step2_t<32, 16, 4, false, 2>(b, zc, remap, sbuf, src, dst, st);
     if (s.tile_x == 64 && s.rows == 2 && s.waves == 16 && !s.prefetch)
         return launch_step2_t<64, 16, 16, false>(b, zc, remap, sbuf, src, dst, st);
     return hipErrorInvalidValue;
@@ -73,6 +75,7 @@ hipError_t launch_group2_f32(const StepShape& s, const GroupBox* boxes, int nbox
         return s.prefetch ? LBM_G2(64, 8, 8, true) : LBM_G2(64, 8, 8, false);
     if (s.tile_x == 32 && s.rows == 2 && s.waves == 8)
         return s.prefetch ? LBM_G2(32, 16, 8, true) : LBM_G2(32, 16, 8, false, 4);
+    if (s.tile_x == 32 && s.rows == 2 && s.waves == 4 && !s.prefetch) return LBM_G2(32, 16, 4, false, 2);
     if (s.tile_x == 64 && s.rows == 2 && s.waves == 16 && !s.prefetch) return LBM_G2(64, 16, 16, false);
     return hipErrorInvalidValue;
 #undef LBM_G2

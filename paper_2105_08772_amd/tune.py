@@ -21,7 +21,8 @@ SHAPES = [dict(waves=4, rows=r, prefetch=pf, tile_x=64) for r in (1, 2, 4) for p
 # two steps per pass (single boxes, FP32 storage and arithmetic, tau = 1)
 SHAPES2 = [dict(waves=8, rows=1, prefetch=pf, tile_x=64) for pf in (0, 1)] + \
           [dict(waves=16, rows=2, prefetch=0, tile_x=64)] + \
-          [dict(waves=8, rows=2, prefetch=pf, tile_x=32) for pf in (0, 1)]
+          [dict(waves=8, rows=2, prefetch=pf, tile_x=32) for pf in (0, 1)] + \
+          [dict(waves=4, rows=2, prefetch=0, tile_x=32)]
 
 
 def group_candidates(two_step=True):

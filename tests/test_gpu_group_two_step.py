@@ -61,7 +61,8 @@ def alone_single(cfgs, counts):
 
 
 # two-step tile shapes (rows, waves, prefetch, tile_x)
-SHAPES2 = [(1, 8, 1, 64), (1, 8, 0, 64), (2, 16, 0, 64), (2, 8, 0, 32), (2, 8, 1, 32)]
+SHAPES2 = [(1, 8, 1, 64), (1, 8, 0, 64), (2, 16, 0, 64), (2, 8, 0, 32), (2, 8, 1, 32),
+           (2, 4, 0, 32)]
 CHUNKS = [dict(z_chunk=3), dict(z_chunk=16), dict(z_chunk=0, items_per_cu=1),
           dict(z_chunk=0, items_per_cu=8)]
 GRAPHS = [4, 6, 0, 8]       # 6: not a multiple of 4, so plain launches

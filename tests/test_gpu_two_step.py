@@ -40,7 +40,8 @@ def box(dims, psi=0, packed=0, prec=lbm.LBM_SC_FP32_SHIFTED, tau=1.0):
 
 
 # two-step shapes (rows, waves, prefetch)
-SHAPES2 = [(1, 8, 1, 64), (1, 8, 0, 64), (2, 16, 0, 64), (2, 8, 0, 32), (2, 8, 1, 32)]
+SHAPES2 = [(1, 8, 1, 64), (1, 8, 0, 64), (2, 16, 0, 64), (2, 8, 0, 32), (2, 8, 1, 32),
+           (2, 4, 0, 32)]
 
 
 def set_two(b, shape=(1, 8, 1, 64), zc=None, graph_steps=64):
@@ -163,7 +164,7 @@ def test_two_steps_per_pass_is_refused_where_it_does_not_apply():
                 b.set_launch(1, 16, 1, 1, 8, 64, 64, 3)
     with box((16, 16, 16)) as b:
         for bad in ((2, 8, 1, 64), (1, 4, 0, 64), (2, 16, 1, 64), (4, 8, 0, 64), (3, 12, 0, 64),
-                    (1, 8, 0, 32), (2, 16, 0, 32)):
+                    (1, 8, 0, 32), (2, 16, 0, 32), (2, 4, 1, 32), (1, 4, 0, 32)):
             with pytest.raises(lbm.LbmScError):
                 set_two(b, bad)
         set_two(b, (2, 8, 0, 32), zc=5)

@@ -274,7 +274,7 @@ def test_z_chunks_cover_every_plane_once(nz, zc):
 # are stored when inside the row pitch and the box height.
 # ------------------------------------------------------------------------------------------
 
-SHAPES2 = [(64, 8, 8), (32, 16, 8), (64, 16, 16)]   # (BX, BY, WAVES)
+SHAPES2 = [(64, 8, 8), (32, 16, 8), (32, 16, 4), (64, 16, 16)]   # (BX, BY, WAVES)
 
 
 def two_step_maps(BX, BY, WAVES, nx, ny, px, tix, tiy):
