@@ -206,7 +206,7 @@ int lbm_sc_set_step(lbm_sc* h, int64_t step);
  * 2 and waves 8 (32 x 16 tiles, either prefetch setting), tile_x 32 with rows 2 and waves 4
  * (32 x 16 tiles, two nodes per thread, prefetch 0) or tile_x 64 with rows 2 and waves 16
  * (64 x 16 tiles, prefetch 0); it is the default for those boxes (32 x 16 tiles of 4 waves from
- * 3 M nodes, 64 x 8 with prefetch below), and lbm_sc_get_launch reports the shape of the kernel
+ * 2.3 M nodes, 64 x 8 with prefetch below), and lbm_sc_get_launch reports the shape of the kernel
  * in use. */
 typedef struct {
     int32_t rows;       /* tile rows per wave: 1, 2 or 4 (full-row tiles: nodes per thread, 2, 4, 8) */

@@ -561,13 +561,13 @@ void default_shape(lbm_sc* h)
     const int slots = cus * (h->shape.prefetch ? 1 : std::max(1, 8 / h->shape.waves));
     h->shape.z_chunk = z_chunk_for(h->box, h->shape.tile_x, lbm::tile_height(h->shape), slots, 2);
     // FP32 storage and arithmetic at tau = 1: two steps per pass, each chunk pulling 6 planes more
-    // than it steps. Boxes of 3 M nodes or more: 32 x 16 tiles of 4 waves without prefetch (two
+    // than it steps. Boxes of 2.3 M nodes or more: 32 x 16 tiles of 4 waves without prefetch (two
     // nodes per thread, 78 KB of LDS and 215 VGPRs without spills: two workgroups per CU);
     // smaller ones: 64 x 8 tiles of 8 waves with the next plane prefetched (one workgroup per CU).
-    // Measured against the 64 x 8 tiles: 11-16 % faster from 160^3 to 384^3 (and 2-8 % faster
-    // than 32 x 16 tiles of 8 waves, whose 128 VGPRs spill), 3 % slower at 128^3, 35-39 % slower
-    // at 48^3 and 64^3
-    const bool big = (double)h->box.n >= 3.0e6;
+    // Measured against the 64 x 8 tiles: 6 % faster at 136^3, 16 % at 144^3, 11-16 % from 160^3
+    // to 384^3 (and 2-8 % faster than 32 x 16 tiles of 8 waves, whose 128 VGPRs spill), equal at
+    // 112^3, 1 % slower at 128^3, 35-39 % slower at 48^3 and 64^3
+    const bool big = (double)h->box.n >= 2.3e6;
     h->shape2.rows = big ? 2 : 1;
     h->shape2.waves = big ? 4 : 8;
     h->shape2.prefetch = big ? 0 : 1;
